@@ -1,0 +1,52 @@
+"""Seeded synthetic inputs for the dispatch workloads.
+
+This module only draws random numbers; it holds none of the method's arithmetic.  Both
+the CPU oracle (in the tests and the CPU baseline) and the GPU path are fed from here.
+The paper's own work item is a compute-only loop (Sec. 3) and it uses no dataset; the
+items below are synthetic, with the shapes and distributions of the evaluation
+workloads.
+"""
+import numpy as np
+
+# plain: 1 worker, 1000 sequential items, int32 affine + int64 sum over 4096 elements
+PLAIN_ITEMS, PLAIN_N = 1000, 4096
+# all CUs: one worker per CU, 10,000 SAXPY items per mailbox over 16,384 fp32
+ALLCU_ITEMS, ALLCU_N = 10000, 16384
+# cluster isolation: critical int32 affine+sum over 262,144 elements, 1 ms period;
+# interference: 256 MiB fp32 copies on the other clusters
+ISO_N, ISO_PERIOD_S, ISO_COPY_ELEMS = 262144, 1e-3, (256 << 20) // 4
+
+
+def uniform_i32(rng, shape):
+    return rng.integers(0, 2 ** 32, shape, dtype=np.uint32).view(np.int32)
+
+
+def plain(seed=0, items=PLAIN_ITEMS, n=PLAIN_N):
+    """X[items, n] int32 ~ uniform over all int32, AB[items, 2] int32 ~ uniform."""
+    rng = np.random.default_rng(seed)
+    X = uniform_i32(rng, (items, n))
+    AB = uniform_i32(rng, (items, 2))
+    return X, AB
+
+
+def allcu_lane(w, items=ALLCU_ITEMS, n=ALLCU_N, seed=2):
+    """Lane w (dense worker index): x, y ~ N(0,1) fp32, alpha[items] ~ U(-2, 2) fp32."""
+    rng = np.random.default_rng([seed, w])
+    x = rng.standard_normal(n, dtype=np.float32)
+    y = rng.standard_normal(n, dtype=np.float32)
+    alpha = rng.uniform(-2, 2, items).astype(np.float32)
+    return x, y, alpha
+
+
+def isolation(seed=3, periods=100000, n=ISO_N):
+    """Critical item input x[n] (fixed) and per-period (a, b) pairs."""
+    rng = np.random.default_rng(seed)
+    x = uniform_i32(rng, n)
+    AB = uniform_i32(rng, (periods, 2))
+    return x, AB
+
+
+def isolation_copy_source(cluster, elems=ISO_COPY_ELEMS, seed=3):
+    """Private fp32 ~ N(0,1) source buffer of one interfering cluster."""
+    rng = np.random.default_rng([seed, 100 + cluster])
+    return rng.standard_normal(elems, dtype=np.float32)
