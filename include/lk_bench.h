@@ -1,0 +1,91 @@
+/*
+ * lk_bench.h -- native timed runners, per-launch baselines and roofline probes of the
+ * LightKernel library (same shared library as lk.h).
+ *
+ * The paper measures host-side time per phase (Sec. 3, Tables 2-3) for its persistent
+ * path and for "traditional" kernels (Alloc, Launch, Wait, Dispose).  These runners take
+ * the same measurements in native code, so that no interpreter overhead sits inside a
+ * timed region:
+ *   - lkb_serial        Trigger + Wait per item on a running context, item after item;
+ *   - lkb_lanes         many clusters fed back-to-back by host threads;
+ *   - lkb_launch_serial one ordinary kernel launch per item (the paper's spawn path),
+ *                       optionally through a single-node hipGraph relaunched per item;
+ *   - lkb_launch_lanes  the lanes workload with one launch (or graph launch) per item;
+ *   - lkb_pingpong      the bare host<->device echo: the floor of any mailbox round trip;
+ *   - lkb_copy          streaming-copy bandwidth: the HBM roofline, and the known-size
+ *                       kernel used to scale memory-traffic counters.
+ * Latencies are host steady-clock microseconds.  All pointers in lkb_item are device
+ * addresses owned by the caller.  Every function returns LK_OK or a negative LK_E* code.
+ */
+#ifndef LK_BENCH_H
+#define LK_BENCH_H
+
+#include <stdint.h>
+
+#include "lk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One work item with its in/out references (40 bytes). */
+typedef struct lkb_item {
+  uint32_t op;      /* LK_OP_* */
+  int32_t a, b;     /* AFFINE_SUM_I32 coefficients; SPIN: a = iterations */
+  float alpha;      /* SAXPY_F32 */
+  uint64_t n;       /* elements */
+  uint64_t in, out; /* device addresses */
+} lkb_item;
+
+/* Submit-then-wait each item on `cluster` in order (the paper's Trigger then Wait).
+ * results[i] = the item's int64 result; lat_us[i] = lk_submit start to lk_wait return;
+ * trigger_us[i] = duration of lk_submit alone; info (nullable) = device-side timing.
+ * Any of the output arrays may be NULL.  Stops at the first error and returns it. */
+LK_API int lkb_serial(lk_ctx *c, uint32_t cluster, const lkb_item *items, uint64_t count, int64_t timeout_ns,
+               int64_t *results, double *lat_us, double *trigger_us, lk_completion *info);
+
+/* Feed n_lanes clusters back-to-back: lane l posts items[l*items_per_lane + k] to
+ * lane_cluster[l] in order, keeping up to `in_flight` of them posted, and is served by
+ * host thread l % n_threads.  lat_us[l*items_per_lane + k] = submit to completion
+ * observed; results likewise; *elapsed_s = first submit to last completion. */
+LK_API int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const lkb_item *items,
+              uint64_t items_per_lane, uint32_t in_flight, uint32_t n_threads, int64_t timeout_ns,
+              int64_t *results, double *lat_us, double *elapsed_s);
+
+#define LKB_COMPLETE_SYNC 0u  /* completion observed by hipStreamSynchronize */
+#define LKB_COMPLETE_FLAG 1u  /* completion observed through a host-coherent word the
+                                 kernel's last workgroup writes (system-scope release) */
+#define LKB_USE_GRAPH 2u      /* launch through a single-node hipGraph whose kernel node
+                                 parameters are updated per item */
+
+/* One launch per item on one stream, grid = k workgroups of `threads` (slice j per
+ * workgroup, the same slicing rule and op bodies as the persistent path).
+ * mode = LKB_COMPLETE_SYNC or LKB_COMPLETE_FLAG, optionally | LKB_USE_GRAPH.
+ * lat_us[i] = launch start to completion observed; launch_us[i] = the launch call. */
+LK_API int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb_item *items, uint64_t count,
+                      uint32_t mode, int64_t *results, double *lat_us, double *launch_us);
+
+/* The lanes workload with one launch per item: lane l runs on stream l % n_streams, one
+ * item in flight per lane, completion observed through the flag form, host thread
+ * l % n_threads.  mode = 0 or LKB_USE_GRAPH.  Outputs as lkb_lanes. */
+LK_API int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64_t items_per_lane,
+                     uint32_t n_streams, uint32_t n_threads, uint32_t threads, uint32_t mode,
+                     int64_t *results, double *lat_us, double *elapsed_s);
+
+/* Host<->device echo over fine-grained host-coherent memory: `workers` one-wave
+ * workgroups (one per CU when spread != 0) each echo `iters` values; the host thread
+ * writes value v to worker w's word and waits for the echo, workers in turn.
+ * rtt_us[w*iters + i] receives each round trip (NULL allowed). */
+LK_API int lkb_pingpong(int device, uint32_t workers, uint64_t iters, uint32_t poll_sleep, int spread,
+                 double *rtt_us);
+
+/* Streaming copy of `bytes` (multiple of 16, 16-byte aligned device buffers) with `grid`
+ * workgroups of 256 threads, repeated `reps` times; *ms_avg = average kernel time from
+ * HIP events; *gbps = 2*bytes / time (read + write). */
+LK_API int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t reps,
+             double *ms_avg, double *gbps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LK_BENCH_H */

@@ -1,0 +1,497 @@
+/*
+ * lk_bench.cpp -- native timed runners, per-launch baselines and probes (include/lk_bench.h).
+ */
+#include <hip/hip_runtime_api.h>
+#include <immintrin.h>
+
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lk.h"
+#include "lk_bench.h"
+#include "lk_device.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+inline double us_between(clk::time_point a, clk::time_point b) {
+  return std::chrono::duration<double, std::micro>(b - a).count();
+}
+
+thread_local std::string g_err;
+
+int bfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int bfail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  fprintf(stderr, "lk_bench: %s\n", buf);
+  return code;
+}
+
+inline uint64_t load_acquire(const uint64_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+
+lk_desc to_desc(const lkb_item &it) {
+  lk_desc d{};
+  d.op = it.op;
+  d.n = it.n;
+  d.a = it.a;
+  d.b = it.b;
+  d.alpha = it.alpha;
+  return d;
+}
+
+bool valid_item(const lkb_item &it) {
+  if (it.op >= LK_OP_COUNT) return false;
+  if ((it.in | it.out) & 3u) return false;
+  return true;
+}
+
+// Host-coherent scratch for the per-launch paths: completion words and partials.
+struct CoherentRegion {
+  void *p = nullptr;
+  ~CoherentRegion() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t alloc(size_t bytes) {
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable);
+    if (e == hipSuccess) memset(p, 0, bytes);
+    return e;
+  }
+};
+
+struct DeviceBuf {
+  void *p = nullptr;
+  ~DeviceBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// One single-node graph of the item kernel, parameters updated per item.
+struct ItemGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  lkd::ItemArgs args{};
+  void *kparams[1] = {&args};
+  hipKernelNodeParams np{};
+  uint32_t k = 1, threads = 256;
+  ItemGraph() = default;
+  ItemGraph(const ItemGraph &) = delete;
+  ItemGraph &operator=(const ItemGraph &) = delete;
+  ~ItemGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  hipError_t build(uint32_t k_, uint32_t threads_) {
+    k = k_;
+    threads = threads_;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    np.func = const_cast<void *>(lkd::item_kernel());
+    np.gridDim = dim3(k);
+    np.blockDim = dim3(threads);
+    np.sharedMemBytes = 0;
+    np.kernelParams = kparams;
+    np.extra = nullptr;
+    args.k = k;
+    e = hipGraphAddKernelNode(&node, g, nullptr, 0, &np);
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  }
+  hipError_t launch(const lkd::ItemArgs &a, hipStream_t s) {
+    args = a;
+    np.kernelParams = kparams;
+    hipError_t e = hipGraphExecKernelNodeSetParams(exec, node, &np);
+    if (e != hipSuccess) return e;
+    return hipGraphLaunch(exec, s);
+  }
+};
+
+lkd::ItemArgs item_args(const lkb_item &it, uint32_t k) {
+  lkd::ItemArgs a{};
+  a.op = it.op;
+  a.k = k;
+  a.n = it.n;
+  a.in = reinterpret_cast<const void *>(it.in);
+  a.out = reinterpret_cast<void *>(it.out);
+  a.a = static_cast<uint32_t>(it.a);
+  a.b = static_cast<uint32_t>(it.b);
+  a.alpha = it.alpha;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lkb_serial(lk_ctx *c, uint32_t cluster, const lkb_item *items, uint64_t count, int64_t timeout_ns,
+               int64_t *results, double *lat_us, double *trigger_us, lk_completion *info) {
+  if (!c || (!items && count)) return bfail(LK_EINVAL, "NULL argument");
+  for (uint64_t i = 0; i < count; ++i) {
+    const lk_desc d = to_desc(items[i]);
+    uint64_t t = 0;
+    const auto t0 = clk::now();
+    int rc = lk_submit(c, cluster, &d, reinterpret_cast<const void *>(items[i].in),
+                       reinterpret_cast<void *>(items[i].out), &t);
+    const auto t1 = clk::now();
+    if (rc) return rc;
+    lk_completion ci;
+    rc = lk_wait_info(c, cluster, t, timeout_ns, &ci);
+    const auto t2 = clk::now();
+    if (rc) return rc;
+    if (results) results[i] = ci.result;
+    if (lat_us) lat_us[i] = us_between(t0, t2);
+    if (trigger_us) trigger_us[i] = us_between(t0, t1);
+    if (info) info[i] = ci;
+  }
+  return LK_OK;
+}
+
+int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const lkb_item *items,
+              uint64_t items_per_lane, uint32_t in_flight, uint32_t n_threads, int64_t timeout_ns, int64_t *results,
+              double *lat_us, double *elapsed_s) {
+  if (!c || !lane_cluster || (!items && items_per_lane)) return bfail(LK_EINVAL, "NULL argument");
+  if (n_threads == 0 || n_threads > 256 || in_flight == 0 || in_flight > LK_MAX_DEPTH)
+    return bfail(LK_EINVAL, "n_threads 1..256 and in_flight 1..%u", LK_MAX_DEPTH);
+  lk_info inf;
+  lk_get_info(c, &inf);
+  if (in_flight > inf.queue_depth) return bfail(LK_EINVAL, "in_flight %u > queue depth %u", in_flight, inf.queue_depth);
+  if (n_threads > n_lanes) n_threads = n_lanes ? n_lanes : 1;
+  std::atomic<int> error{0};
+  std::atomic<bool> stop{false};
+  const auto start = clk::now();
+  auto worker = [&](uint32_t tix) {
+    struct Lane {
+      uint32_t id, cluster;
+      uint64_t next = 0, done = 0;
+      uint64_t first_ticket = 0;  // ticket of item 0
+      std::vector<clk::time_point> t_sub;
+    };
+    std::vector<Lane> lanes;
+    for (uint32_t l = tix; l < n_lanes; l += n_threads) {
+      Lane L;
+      L.id = l;
+      L.cluster = lane_cluster[l];
+      L.t_sub.resize(items_per_lane);
+      lanes.push_back(std::move(L));
+    }
+    uint64_t remaining = lanes.size() * items_per_lane;
+    while (remaining && !stop.load(std::memory_order_relaxed)) {
+      for (Lane &L : lanes) {
+        while (L.next < items_per_lane && L.next - L.done < in_flight) {
+          const lkb_item &it = items[static_cast<uint64_t>(L.id) * items_per_lane + L.next];
+          const lk_desc d = to_desc(it);
+          uint64_t t;
+          L.t_sub[L.next] = clk::now();
+          const int rc = lk_submit(c, L.cluster, &d, reinterpret_cast<const void *>(it.in),
+                                   reinterpret_cast<void *>(it.out), &t);
+          if (rc == LK_EAGAIN) break;
+          if (rc) {
+            error.store(rc);
+            stop.store(true);
+            return;
+          }
+          if (L.next == 0) L.first_ticket = t;
+          ++L.next;
+        }
+        while (L.done < L.next) {
+          const uint64_t t = L.first_ticket + L.done;
+          int fin = 0;
+          int rc = lk_poll(c, L.cluster, t, &fin);
+          if (rc) {
+            error.store(rc);
+            stop.store(true);
+            return;
+          }
+          if (!fin) {
+            if (timeout_ns >= 0 && clk::now() - L.t_sub[L.done] > std::chrono::nanoseconds(timeout_ns)) {
+              error.store(LK_ETIMEDOUT);
+              stop.store(true);
+              return;
+            }
+            break;
+          }
+          const auto now = clk::now();
+          int64_t r = 0;
+          rc = lk_wait(c, L.cluster, t, 0, &r);
+          if (rc) {
+            error.store(rc);
+            stop.store(true);
+            return;
+          }
+          const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.done;
+          if (results) results[idx] = r;
+          if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done], now);
+          ++L.done;
+          --remaining;
+        }
+      }
+      _mm_pause();
+    }
+  };
+  std::vector<std::thread> th;
+  for (uint32_t t = 0; t < n_threads; ++t) th.emplace_back(worker, t);
+  for (auto &t : th) t.join();
+  if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
+  const int rc = error.load();
+  if (rc) return bfail(rc, "lanes run failed: %s (%s)", lk_strerror(rc), lk_last_error());
+  return LK_OK;
+}
+
+int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb_item *items, uint64_t count, uint32_t mode,
+                      int64_t *results, double *lat_us, double *launch_us) {
+  if (!items && count) return bfail(LK_EINVAL, "NULL items");
+  if (k == 0 || k > 4096 || threads < 64 || threads > 1024 || threads % 64) return bfail(LK_EINVAL, "bad k/threads");
+  for (uint64_t i = 0; i < count; ++i)
+    if (!valid_item(items[i])) return bfail(LK_EINVAL, "item %llu invalid", static_cast<unsigned long long>(i));
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  hipStream_t s;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+    return bfail(LK_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+  CoherentRegion reg;
+  DeviceBuf counter;
+  int rc = LK_OK;
+  ItemGraph graph;
+  const bool flag = mode & LKB_COMPLETE_FLAG, use_graph = mode & LKB_USE_GRAPH;
+  if ((e = reg.alloc(4096 + 8ull * k)) != hipSuccess) {
+    rc = bfail(LK_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  } else if ((e = hipMalloc(&counter.p, 256)) != hipSuccess || (e = hipMemset(counter.p, 0, 256)) != hipSuccess) {
+    rc = bfail(LK_EHIP, "counter: %s", hipGetErrorString(e));
+  } else if (use_graph && (e = graph.build(k, threads)) != hipSuccess) {
+    rc = bfail(LK_EHIP, "graph build: %s", hipGetErrorString(e));
+  }
+  uint64_t *done_word = static_cast<uint64_t *>(reg.p);
+  int64_t *partials = reinterpret_cast<int64_t *>(static_cast<char *>(reg.p) + 4096);
+  for (uint64_t i = 0; rc == LK_OK && i < count; ++i) {
+    lkd::ItemArgs a = item_args(items[i], k);
+    a.partials = partials;
+    a.counter = static_cast<uint32_t *>(counter.p);
+    if (flag) {
+      a.done_word = done_word;
+      a.done_value = i + 1;
+    }
+    const auto t0 = clk::now();
+    e = use_graph ? graph.launch(a, s) : lkd::launch_item(a, threads, s);
+    const auto t1 = clk::now();
+    if (e != hipSuccess) {
+      rc = bfail(LK_EHIP, "launch: %s", hipGetErrorString(e));
+      break;
+    }
+    if (flag) {
+      const auto deadline = t0 + std::chrono::seconds(10);
+      uint32_t spins = 0;
+      while (load_acquire(done_word) != i + 1) {
+        if ((++spins & 1023u) == 0 && clk::now() > deadline) {
+          rc = bfail(LK_ETIMEDOUT, "item %llu: completion word not seen", static_cast<unsigned long long>(i));
+          break;
+        }
+        _mm_pause();
+      }
+    } else {
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = bfail(LK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    const auto t2 = clk::now();
+    if (rc) break;
+    int64_t sum = 0;
+    for (uint32_t j = 0; j < k; ++j) sum += __atomic_load_n(partials + j, __ATOMIC_RELAXED);
+    if (results) results[i] = sum;
+    if (lat_us) lat_us[i] = us_between(t0, t2);
+    if (launch_us) launch_us[i] = us_between(t0, t1);
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64_t items_per_lane, uint32_t n_streams,
+                     uint32_t n_threads, uint32_t threads, uint32_t mode, int64_t *results, double *lat_us,
+                     double *elapsed_s) {
+  if (!items && items_per_lane) return bfail(LK_EINVAL, "NULL items");
+  if (n_lanes == 0 || n_lanes > 65536 || n_streams == 0 || n_streams > 64 || n_threads == 0 || n_threads > 256 ||
+      threads < 64 || threads > 1024 || threads % 64)
+    return bfail(LK_EINVAL, "bad lanes/streams/threads");
+  for (uint64_t i = 0; i < static_cast<uint64_t>(n_lanes) * items_per_lane; ++i)
+    if (!valid_item(items[i])) return bfail(LK_EINVAL, "item %llu invalid", static_cast<unsigned long long>(i));
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  if (n_threads > n_lanes) n_threads = n_lanes;
+  std::vector<hipStream_t> streams(n_streams, nullptr);
+  int rc = LK_OK;
+  for (auto &s : streams)
+    if (rc == LK_OK && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+      rc = bfail(LK_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+  CoherentRegion reg;  // per lane: done word + partial, 64 bytes apart
+  if (rc == LK_OK && (e = reg.alloc(64ull * n_lanes)) != hipSuccess)
+    rc = bfail(LK_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  std::vector<ItemGraph> graphs(mode & LKB_USE_GRAPH ? n_lanes : 0);
+  for (auto &g : graphs)
+    if (rc == LK_OK && (e = g.build(1, threads)) != hipSuccess) rc = bfail(LK_EHIP, "graph build: %s", hipGetErrorString(e));
+  std::atomic<int> error{rc};
+  std::atomic<bool> stop{rc != LK_OK};
+  const auto start = clk::now();
+  auto worker = [&](uint32_t tix) {
+    struct Lane {
+      uint32_t id;
+      uint64_t next = 0;
+      bool busy = false;
+      clk::time_point t0;
+    };
+    std::vector<Lane> lanes;
+    for (uint32_t l = tix; l < n_lanes; l += n_threads) lanes.push_back(Lane{l});
+    uint64_t remaining = lanes.size() * items_per_lane;
+    while (remaining && !stop.load(std::memory_order_relaxed)) {
+      for (Lane &L : lanes) {
+        char *slot = static_cast<char *>(reg.p) + 64ull * L.id;
+        uint64_t *done_word = reinterpret_cast<uint64_t *>(slot);
+        int64_t *partial = reinterpret_cast<int64_t *>(slot + 8);
+        if (L.busy) {
+          if (load_acquire(done_word) != L.next + 1) {
+            if (clk::now() - L.t0 > std::chrono::seconds(10)) {
+              error.store(LK_ETIMEDOUT);
+              stop.store(true);
+              return;
+            }
+            continue;
+          }
+          const auto now = clk::now();
+          const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.next;
+          if (results) results[idx] = __atomic_load_n(partial, __ATOMIC_RELAXED);
+          if (lat_us) lat_us[idx] = us_between(L.t0, now);
+          L.busy = false;
+          ++L.next;
+          --remaining;
+        }
+        if (!L.busy && L.next < items_per_lane) {
+          const lkb_item &it = items[static_cast<uint64_t>(L.id) * items_per_lane + L.next];
+          lkd::ItemArgs a = item_args(it, 1);
+          a.partials = partial;
+          a.done_word = done_word;
+          a.done_value = L.next + 1;
+          hipStream_t s = streams[L.id % n_streams];
+          L.t0 = clk::now();
+          const hipError_t le = graphs.empty() ? lkd::launch_item(a, threads, s) : graphs[L.id].launch(a, s);
+          if (le != hipSuccess) {
+            error.store(LK_EHIP);
+            stop.store(true);
+            return;
+          }
+          L.busy = true;
+        }
+      }
+      _mm_pause();
+    }
+  };
+  std::vector<std::thread> th;
+  if (rc == LK_OK)
+    for (uint32_t t = 0; t < n_threads; ++t) th.emplace_back(worker, t);
+  for (auto &t : th) t.join();
+  if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
+  for (auto &s : streams)
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  graphs.clear();
+  rc = error.load();
+  if (rc) return bfail(rc, "launch lanes failed: %s", lk_strerror(rc));
+  return LK_OK;
+}
+
+int lkb_pingpong(int device, uint32_t workers, uint64_t iters, uint32_t poll_sleep, int spread, double *rtt_us) {
+  if (workers == 0 || workers > 1024 || iters == 0 || iters > 10000000ull || poll_sleep > 127)
+    return bfail(LK_EINVAL, "bad workers/iters/poll_sleep");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return bfail(LK_EHIP, "props: %s", hipGetErrorString(e));
+  if (spread && workers > static_cast<uint32_t>(prop.multiProcessorCount))
+    return bfail(LK_EINVAL, "spread pingpong needs workers <= CU count");
+  int wc_khz = 100000;
+  (void)hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, device);
+  const uint32_t stride = 16;  // one 128-byte line per worker and direction
+  CoherentRegion reg;
+  if ((e = reg.alloc(2ull * workers * stride * 8)) != hipSuccess) return bfail(LK_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  uint64_t *h2d = static_cast<uint64_t *>(reg.p);
+  uint64_t *d2h = h2d + static_cast<uint64_t>(workers) * stride;
+  DeviceBuf status;
+  if ((e = hipMalloc(&status.p, 4ull * workers)) != hipSuccess || (e = hipMemset(status.p, 0, 4ull * workers)) != hipSuccess)
+    return bfail(LK_EHIP, "status: %s", hipGetErrorString(e));
+  hipStream_t s;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return bfail(LK_EHIP, "stream: %s", hipGetErrorString(e));
+  // Device deadline: generous bound on the whole run (50 us per echo + 5 s).
+  const double run_s = 5.0 + 50e-6 * static_cast<double>(iters) * workers;
+  const uint64_t deadline_ticks = static_cast<uint64_t>(run_s * wc_khz * 1000.0);
+  e = lkd::launch_pingpong(h2d, d2h, stride, workers, iters, deadline_ticks, poll_sleep, static_cast<uint32_t *>(status.p),
+                           spread != 0, s);
+  int rc = LK_OK;
+  if (e != hipSuccess) rc = bfail(LK_EHIP, "launch pingpong: %s", hipGetErrorString(e));
+  for (uint64_t i = 1; rc == LK_OK && i <= iters; ++i) {
+    for (uint32_t w = 0; w < workers; ++w) {
+      uint64_t *in = h2d + static_cast<uint64_t>(w) * stride;
+      uint64_t *out = d2h + static_cast<uint64_t>(w) * stride;
+      const auto t0 = clk::now();
+      __atomic_store_n(in, i, __ATOMIC_RELEASE);
+      uint32_t spins = 0;
+      while (load_acquire(out) < i) {
+        if ((++spins & 1023u) == 0 && clk::now() - t0 > std::chrono::seconds(2)) {
+          rc = bfail(LK_ETIMEDOUT, "pingpong worker %u iteration %llu: no echo", w, static_cast<unsigned long long>(i));
+          break;
+        }
+        _mm_pause();
+      }
+      if (rc) break;
+      if (rtt_us) rtt_us[static_cast<uint64_t>(w) * iters + (i - 1)] = us_between(t0, clk::now());
+    }
+  }
+  if (rc) {  // release every worker so the kernel ends before its deadline
+    for (uint32_t w = 0; w < workers; ++w) __atomic_store_n(h2d + static_cast<uint64_t>(w) * stride, iters, __ATOMIC_RELEASE);
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t reps, double *ms_avg,
+             double *gbps) {
+  if (!src || !dst || bytes % 16 || (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 ||
+      grid == 0 || grid > (1u << 20) || reps == 0)
+    return bfail(LK_EINVAL, "bad copy arguments");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  hipStream_t s;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return bfail(LK_EHIP, "stream: %s", hipGetErrorString(e));
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  int rc = LK_OK;
+  // one untimed warm-up
+  if ((e = lkd::launch_copy_probe(src, dst, bytes, grid, s)) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
+  (void)hipEventRecord(a, s);
+  for (uint32_t r = 0; rc == LK_OK && r < reps; ++r)
+    if ((e = lkd::launch_copy_probe(src, dst, bytes, grid, s)) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
+  (void)hipEventRecord(b, s);
+  (void)hipStreamSynchronize(s);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  if (ms_avg) *ms_avg = ms / reps;
+  if (gbps) *gbps = ms > 0 ? 2.0 * bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+/*
+ * lk_device.hip -- gfx950 kernels of the LightKernel dispatch library launched through
+ * the HIP runtime (the persistent worker itself is in lk_worker.hip):
+ *   lk_item        the same work-item bodies as one ordinary launch per item (the
+ *                  "traditional" spawn path the paper compares against, Sec. 3);
+ *   lk_pingpong    bare host<->device echo over host-coherent memory: the latency floor
+ *                  of any mailbox round trip;
+ *   lk_copy_probe  plain streaming copy: the achievable HBM bandwidth, and the known-size
+ *                  reference for memory-traffic counters.
+ * Every loop that waits on the host is bounded by a device wall-clock deadline.
+ */
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lk_devutil.hpp"
+#include "lk_device.h"
+#include "lk_ops.hpp"
+#include "lk_wire.h"
+
+using namespace lkdev;
+
+// ----------------------------------------------------------------------------- per-item
+// One ordinary launch per item: workgroup j runs slice j of k (same slicing rule and
+// same op bodies as the persistent path).  Completion is observed either by stream
+// synchronisation or through done_word in host-coherent memory, written by the last
+// workgroup to finish.
+__global__ void __launch_bounds__(1024) lk_item(lkd::ItemArgs a) {
+  __shared__ int64_t s_red[lkops::kMaxWaves];
+  const uint32_t j = blockIdx.x;
+  uint64_t lo, hi;
+  lkd::slice_bounds(a.n, a.k, j, &lo, &hi);
+  lkops::Slice s;
+  s.op = a.op;
+  s.n = hi - lo;
+  const uint32_t esz = 4;
+  s.in = a.in ? static_cast<const char *>(a.in) + lo * esz : nullptr;
+  s.out = a.out ? static_cast<char *>(a.out) + lo * esz : nullptr;
+  s.a = a.a;
+  s.b = a.b;
+  s.alpha = a.alpha;
+  const int64_t partial = lkops::run_slice(s, s_red, blockDim.x);
+  drain_wave_memory();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (a.aux) a.aux[j] = partial;
+    if (a.partials) st_sys_i64(a.partials + j, partial);
+    uint32_t last = 1;
+    if (a.k > 1) {
+      const uint32_t prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      last = prev == a.k - 1;
+      if (last) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (last && a.done_word) st_sys_release(a.done_word, a.done_value);
+  }
+}
+
+// ----------------------------------------------------------------------------- probes
+// Echo: workgroup w (lane 0) waits for h2d[w*stride] to reach the next value and echoes
+// it to d2h[w*stride]; ends after `iters` echoes or when the deadline passes.
+__global__ void lk_pingpong(uint64_t *h2d, uint64_t *d2h, uint32_t stride, uint64_t iters,
+                            uint64_t deadline_ticks, uint32_t poll_sleep, uint32_t *status) {
+  extern __shared__ uint64_t lds_reserve[];
+  (void)lds_reserve;
+  if (threadIdx.x != 0) return;
+  const uint32_t w = blockIdx.x;
+  uint64_t *in = h2d + static_cast<uint64_t>(w) * stride;
+  uint64_t *out = d2h + static_cast<uint64_t>(w) * stride;
+  const uint64_t start = wall_clock64();
+  uint64_t expect = 1;
+  uint32_t polls = 0;
+  while (expect <= iters) {
+    const uint64_t v = ld_sys(in);
+    if (v >= expect) {
+      st_sys(out, v);
+      expect = v + 1;
+      continue;
+    }
+    if ((++polls & 255u) == 0 && wall_clock64() - start > deadline_ticks) {
+      status[w] = 2;
+      return;
+    }
+    backoff(poll_sleep);
+  }
+  status[w] = 1;
+}
+
+__global__ void __launch_bounds__(256) lk_copy_probe(const lkops::u32x4 *__restrict__ in,
+                                                     lkops::u32x4 *__restrict__ out, uint64_t nvec) {
+  constexpr int U = 8;
+  const uint64_t nt = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (; k + (U - 1) * nt < nvec; k += U * nt) {
+    lkops::u32x4 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(in + k + u * nt);
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(r[u], out + k + u * nt);
+  }
+  for (; k < nvec; k += nt) out[k] = in[k];
+}
+
+// ----------------------------------------------------------------------------- launchers
+namespace lkd {
+
+const void *item_kernel() { return reinterpret_cast<const void *>(lk_item); }
+
+hipError_t launch_item(const ItemArgs &a, uint32_t threads, hipStream_t s) {
+  hipLaunchKernelGGL(lk_item, dim3(a.k), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pingpong(uint64_t *h2d, uint64_t *d2h, uint32_t stride, uint32_t workers, uint64_t iters,
+                           uint64_t deadline_ticks, uint32_t poll_sleep, uint32_t *status, bool spread,
+                           hipStream_t s) {
+  uint32_t lds = 0;
+  if (spread) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(lk_pingpong),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, LKW_LDS_PAD_BYTES);
+    if (e != hipSuccess) return e;
+    lds = LKW_LDS_PAD_BYTES;
+  }
+  hipLaunchKernelGGL(lk_pingpong, dim3(workers), dim3(64), lds, s, h2d, d2h, stride, iters, deadline_ticks,
+                     poll_sleep, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void *in, void *out, uint64_t bytes, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(lk_copy_probe, dim3(grid), dim3(256), 0, s, static_cast<const lkops::u32x4 *>(in),
+                     static_cast<lkops::u32x4 *>(out), bytes / 16);
+  return hipGetLastError();
+}
+
+}  // namespace lkd

@@ -1,0 +1,664 @@
+/*
+ * lk_host.cpp -- host side of the LightKernel dispatch library (include/lk.h).
+ *
+ * Phases (Sec. 3): lk_init boots the persistent kernel (Init), lk_submit posts a command
+ * into each member's to_GPU mailbox (Trigger), lk_wait polls the members' from_GPU
+ * mailboxes (Wait), lk_dispose posts THREAD_EXIT and joins the kernel (Dispose).
+ *
+ * Submit and wait make no HIP runtime call and no driver transfer: the mailboxes live in
+ * fine-grained host-coherent memory that the workers read and write directly over PCIe,
+ * so the host side of a dispatch is a handful of ordinary stores and loads.
+ */
+#include <hip/hip_runtime_api.h>
+#include <immintrin.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "lk.h"
+#include "lk_device.h"
+#include "lk_queue.h"
+#include "lk_wire.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(LK_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+using clk = std::chrono::steady_clock;
+
+inline uint64_t load_acquire(const uint64_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+inline void store_relaxed(uint64_t *p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+inline void store_release(uint64_t *p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+
+enum State : uint32_t { RUNNING = 0, DISPOSED = 1, POISONED = 2 };
+
+struct WorkerInfo {
+  uint32_t mailbox;
+  uint32_t hwid, xcc, se, sh, cu;
+};
+
+inline bool exited_code(uint32_t code) { return code == LKW_FROM_EXITED || code == LKW_FROM_TIMEDOUT; }
+
+}  // namespace
+
+struct lk_ctx {
+  lk_config cfg{};
+  int device = 0;
+  uint32_t n_workers = 0, depth = 1, threads = 256, n_clusters = 0, cu_count = 0, xcd_count = 0;
+  uint32_t log_cap = 0;
+  uint64_t wall_hz = 100000000ull;
+  State state = RUNNING;
+  lkq::Queue wq;  // the persistent worker's own HSA queue
+  void *host_region = nullptr;
+  lkw_cmd *cmd = nullptr;
+  lkw_status *status = nullptr;
+  lkw_worker *wrec = nullptr;
+  lkw_log *d_log = nullptr;
+  uint32_t *d_claim = nullptr;
+  std::vector<WorkerInfo> workers;                  // physical order
+  std::vector<std::vector<uint32_t>> clusters;      // member worker indices, slice order
+  std::vector<std::vector<uint32_t>> cluster_mbox;  // member mailboxes, slice order
+  std::vector<uint64_t> posted, consumed;           // per cluster (== each member's seq)
+  std::vector<uint32_t> cluster_of_mbox;
+  std::vector<lkw_log> host_log;                    // copied at dispose
+  double init_ms = 0, dispose_ms = 0, kernel_ms = 0;
+  bool kernel_launched = false;
+  uint32_t exited_at_dispose = 0;
+};
+
+namespace {
+
+lkw_cmd *slot_cmd(lk_ctx *c, uint32_t mb, uint64_t seq) {
+  return c->cmd + static_cast<uint64_t>(mb) * c->depth + seq % c->depth;
+}
+lkw_status *slot_status(lk_ctx *c, uint32_t mb, uint64_t seq) {
+  return c->status + static_cast<uint64_t>(mb) * c->depth + seq % c->depth;
+}
+uint32_t worker_code(lk_ctx *c, uint32_t mb) { return LKW_CODE(load_acquire(&c->wrec[mb].word)); }
+
+// Write one command slot: tagged payload words first, then the doorbell word (release).
+void post_cmd(lk_ctx *c, uint32_t mb, uint64_t seq, uint32_t code, uint64_t n, uint64_t in, uint64_t out,
+              uint64_t aux, uint32_t a, uint32_t b, float alpha, uint32_t member) {
+  lkw_cmd *s = slot_cmd(c, mb, seq);
+  const uint64_t tag = LKW_TAG(seq);
+  uint32_t alpha_bits;
+  memcpy(&alpha_bits, &alpha, 4);
+  store_relaxed(&s->w[LKW_W_N], tag | (n & LKW_PAYLOAD_MASK));
+  store_relaxed(&s->w[LKW_W_IN], tag | (in & LKW_PAYLOAD_MASK));
+  store_relaxed(&s->w[LKW_W_OUT], tag | (out & LKW_PAYLOAD_MASK));
+  store_relaxed(&s->w[LKW_W_AUX], tag | (aux & LKW_PAYLOAD_MASK));
+  store_relaxed(&s->w[LKW_W_A], tag | (static_cast<uint64_t>(member & 0xffffu) << 32) | a);
+  store_relaxed(&s->w[LKW_W_B], tag | b);
+  store_relaxed(&s->w[LKW_W_ALPHA], tag | alpha_bits);
+  store_release(&s->w[LKW_W_DOORBELL], LKW_WORD(seq, code));
+}
+
+bool op_reads(uint32_t op) { return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32; }
+bool op_writes(uint32_t op) { return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32; }
+
+int validate_config(const lk_config *cfg) {
+  if (!cfg) return fail(LK_EINVAL, "config is NULL");
+  if (cfg->n_workers > LK_MAX_WORKERS) return fail(LK_EINVAL, "n_workers %u > %u", cfg->n_workers, LK_MAX_WORKERS);
+  const uint32_t t = cfg->threads_per_worker;
+  if (t != 0 && (t < 64 || t > 1024 || t % 64 != 0))
+    return fail(LK_EINVAL, "threads_per_worker %u: need a multiple of 64 in 64..1024", t);
+  if (cfg->queue_depth > LK_MAX_DEPTH) return fail(LK_EINVAL, "queue_depth %u > %u", cfg->queue_depth, LK_MAX_DEPTH);
+  if (cfg->cluster_policy > LK_CLUSTERS_EXPLICIT) return fail(LK_EINVAL, "unknown cluster_policy %u", cfg->cluster_policy);
+  if (cfg->cluster_policy == LK_CLUSTERS_EXPLICIT) {
+    if (!cfg->cluster_of_worker || cfg->n_clusters == 0)
+      return fail(LK_EINVAL, "explicit clusters need cluster_of_worker and n_clusters > 0");
+    if (cfg->n_workers == 0) return fail(LK_EINVAL, "explicit clusters need an explicit n_workers");
+    std::vector<uint32_t> seen(cfg->n_clusters, 0);
+    for (uint32_t w = 0; w < cfg->n_workers; ++w) {
+      if (cfg->cluster_of_worker[w] >= cfg->n_clusters)
+        return fail(LK_EINVAL, "cluster_of_worker[%u] = %u out of range", w, cfg->cluster_of_worker[w]);
+      seen[cfg->cluster_of_worker[w]] = 1;
+    }
+    for (uint32_t k = 0; k < cfg->n_clusters; ++k)
+      if (!seen[k]) return fail(LK_EINVAL, "cluster %u has no worker", k);
+  }
+  if (cfg->poll_sleep > 127) return fail(LK_EINVAL, "poll_sleep %u > 127", cfg->poll_sleep);
+  if (cfg->idle_timeout_ms > 3600000u) return fail(LK_EINVAL, "idle_timeout_ms %u > 3600000", cfg->idle_timeout_ms);
+  if (cfg->flags & ~(LK_F_REPORT_WORKING | LK_F_NO_ACQUIRE | LK_F_ANY_PLACEMENT))
+    return fail(LK_EINVAL, "unknown flags 0x%x", cfg->flags);
+  if (cfg->init_timeout_ns < 0) return fail(LK_EINVAL, "init_timeout_ns < 0");
+  if (cfg->log_capacity > (1u << 24)) return fail(LK_EINVAL, "log_capacity %u > 2^24", cfg->log_capacity);
+  return LK_OK;
+}
+
+// Only called once the persistent dispatch has ended (or was never made).
+void release_gpu(lk_ctx *c) {
+  c->wq.close();
+  if (c->d_log) (void)hipFree(c->d_log);
+  if (c->d_claim) (void)hipFree(c->d_claim);
+  if (c->host_region) (void)hipHostFree(c->host_region);
+  c->d_log = nullptr;
+  c->d_claim = nullptr;
+  c->host_region = nullptr;
+  c->cmd = nullptr;
+  c->status = nullptr;
+  c->wrec = nullptr;
+}
+
+// Wait (bounded) for the persistent kernel to end; true if it did.
+bool join_kernel(lk_ctx *c, double seconds) {
+  const auto deadline = clk::now() + std::chrono::duration<double>(seconds);
+  for (;;) {
+    if (c->wq.finished()) return true;
+    if (clk::now() > deadline) return false;
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void lk_config_default(lk_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->threads_per_worker = 256;
+  cfg->queue_depth = 1;
+  cfg->cluster_policy = LK_CLUSTERS_PER_WORKER;
+  cfg->log_capacity = 0;
+  cfg->idle_timeout_ms = 10000;
+}
+
+int lk_slice(uint64_t n, uint32_t k, uint32_t j, uint64_t *lo, uint64_t *hi) {
+  if (!lo || !hi) return fail(LK_EINVAL, "lo/hi is NULL");
+  if (k == 0) return fail(LK_EINVAL, "k == 0");
+  lkd::slice_bounds(n, k, j, lo, hi);
+  return LK_OK;
+}
+
+const char *lk_strerror(int code) {
+  switch (code) {
+    case LK_OK: return "ok";
+    case LK_EINVAL: return "invalid argument";
+    case LK_EAGAIN: return "mailbox ring full";
+    case LK_ETIMEDOUT: return "timed out";
+    case LK_ESTATE: return "invalid state";
+    case LK_ENODEV: return "no usable device";
+    case LK_EHIP: return "HIP runtime error";
+    case LK_EFAULT: return "descriptor rejected by worker";
+    default: return "unknown error";
+  }
+}
+
+const char *lk_last_error(void) { return g_last_error.c_str(); }
+
+int lk_init(const lk_config *cfg_in, lk_ctx **out) {
+  const auto t_begin = clk::now();
+  if (!out) return fail(LK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_config(cfg_in);
+  if (rc) return rc;
+  lk_config cfg = *cfg_in;
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(LK_ENODEV, "no HIP device (%s)", hipGetErrorString(e));
+  if (cfg.device < 0 || cfg.device >= ndev) return fail(LK_EINVAL, "device %d of %d", cfg.device, ndev);
+  if ((e = hipSetDevice(cfg.device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, cfg.device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LK_ENODEV, "device %d is %s; this library is built for gfx950", cfg.device, prop.gcnArchName);
+  if (prop.maxSharedMemoryPerMultiProcessor < 2 * LKW_LDS_PAD_BYTES - 64 * 1024)
+    return fail(LK_ENODEV, "unexpected LDS size %zu per CU", prop.maxSharedMemoryPerMultiProcessor);
+
+  auto *c = new lk_ctx();
+  c->cfg = cfg;
+  c->cfg.cluster_of_worker = nullptr;
+  c->device = cfg.device;
+  c->cu_count = static_cast<uint32_t>(prop.multiProcessorCount);
+  c->n_workers = cfg.n_workers ? cfg.n_workers : c->cu_count;
+  c->depth = cfg.queue_depth ? cfg.queue_depth : 1;
+  c->threads = cfg.threads_per_worker ? cfg.threads_per_worker : 256;
+  c->log_cap = cfg.log_capacity;
+  if (c->n_workers > c->cu_count || c->n_workers > LK_MAX_WORKERS) {
+    delete c;
+    return fail(LK_EINVAL, "n_workers %u exceeds the %u CUs", cfg.n_workers, c->cu_count);
+  }
+  int wc_khz = 0;
+  if (hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, cfg.device) == hipSuccess && wc_khz > 0)
+    c->wall_hz = static_cast<uint64_t>(wc_khz) * 1000ull;
+
+  auto bail = [&](int code) {
+    release_gpu(c);
+    delete c;
+    return code;
+  };
+
+  // Mailboxes: command ring, status ring, worker records, in one host-coherent region.
+  const size_t cmd_bytes = sizeof(lkw_cmd) * c->n_workers * c->depth;
+  const size_t st_bytes = sizeof(lkw_status) * c->n_workers * c->depth;
+  const size_t wr_bytes = sizeof(lkw_worker) * c->n_workers;
+  auto up = [](size_t v) { return (v + 4095) & ~static_cast<size_t>(4095); };
+  const size_t region = up(cmd_bytes) + up(st_bytes) + up(wr_bytes);
+  e = hipHostMalloc(&c->host_region, region, hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc(coherent mailboxes)"));
+  memset(c->host_region, 0, region);
+  char *base = static_cast<char *>(c->host_region);
+  c->cmd = reinterpret_cast<lkw_cmd *>(base);
+  c->status = reinterpret_cast<lkw_status *>(base + up(cmd_bytes));
+  c->wrec = reinterpret_cast<lkw_worker *>(base + up(cmd_bytes) + up(st_bytes));
+  // Mark every worker record as not yet booted (INIT is 0, so use an impossible word).
+  for (uint32_t m = 0; m < c->n_workers; ++m) store_release(&c->wrec[m].word, LKW_WORD(~0ull >> 8, 0xffu));
+
+  if ((e = hipMalloc(&c->d_claim, 256)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(claim)"));
+  if ((e = hipMemset(c->d_claim, 0, 256)) != hipSuccess) return bail(hip_fail(e, "hipMemset(claim)"));
+  if (c->log_cap) {
+    const size_t lb = sizeof(lkw_log) * c->n_workers * static_cast<size_t>(c->log_cap);
+    if ((e = hipMalloc(&c->d_log, lb)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(log)"));
+    if ((e = hipMemset(c->d_log, 0, lb)) != hipSuccess) return bail(hip_fail(e, "hipMemset(log)"));
+  }
+
+  // The persistent worker runs on a hardware queue of its own (lk_queue.cpp).
+  {
+    std::string err;
+    if (!c->wq.open(cfg.device, err)) return bail(fail(LK_EHIP, "worker queue: %s", err.c_str()));
+  }
+
+  lkw_params p{};
+  p.cmd = c->cmd;
+  p.status = c->status;
+  p.workers = c->wrec;
+  p.log = c->d_log;
+  p.claim = c->d_claim;
+  p.n_workers = c->n_workers;
+  p.depth = c->depth;
+  p.log_cap = c->log_cap ? c->log_cap : 1;
+  p.poll_sleep = cfg.poll_sleep;
+  p.threads = c->threads;
+  p.flags = ((cfg.flags & LK_F_REPORT_WORKING) ? LKW_K_REPORT_WORKING : 0u) |
+            ((cfg.flags & LK_F_NO_ACQUIRE) ? LKW_K_NO_ACQUIRE : 0u);
+  const uint32_t idle_ms = cfg.idle_timeout_ms ? cfg.idle_timeout_ms : 10000u;
+  p.idle_ticks = c->wall_hz / 1000ull * idle_ms;
+
+  {
+    std::string err;
+    if (!c->wq.dispatch(p, c->n_workers, c->threads, LKW_LDS_PAD_BYTES, err))
+      return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
+  }
+  c->kernel_launched = true;
+
+  // Boot handshake: every worker reports INIT with its placement.
+  const int64_t to_ns = cfg.init_timeout_ns ? cfg.init_timeout_ns : 5000000000ll;
+  const auto deadline = clk::now() + std::chrono::nanoseconds(to_ns);
+  uint32_t booted = 0;
+  bool early_end = false;
+  while (booted < c->n_workers) {
+    booted = 0;
+    for (uint32_t m = 0; m < c->n_workers; ++m) booted += load_acquire(&c->wrec[m].word) == LKW_WORD(0, LKW_FROM_INIT);
+    if (booted == c->n_workers) break;
+    if (c->wq.finished()) {
+      early_end = true;
+      break;
+    }
+    if (clk::now() > deadline) break;
+    _mm_pause();
+  }
+  if (booted < c->n_workers) {
+    for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
+    const double wait_s = 2.0 + idle_ms / 1000.0;
+    if (!join_kernel(c, wait_s)) {
+      c->state = POISONED;
+      *out = c;  // resources cannot be freed while the kernel may still touch them
+      return fail(LK_ENODEV, "only %u of %u workers became resident; kernel did not end (context poisoned)",
+                  booted, c->n_workers);
+    }
+    const int code = fail(LK_ENODEV, "only %u of %u workers became resident within %.3f s%s", booted,
+                          c->n_workers, to_ns / 1e9, early_end ? " (kernel ended early)" : "");
+    return bail(code);
+  }
+
+  // Placement learnt from the hardware-id registers; workers in physical order.
+  std::vector<WorkerInfo> ws(c->n_workers);
+  for (uint32_t m = 0; m < c->n_workers; ++m) {
+    const uint32_t hw = __atomic_load_n(&c->wrec[m].hwid, __ATOMIC_ACQUIRE);
+    const uint32_t xcc = __atomic_load_n(&c->wrec[m].xcc, __ATOMIC_ACQUIRE) & 0xfu;
+    ws[m] = WorkerInfo{m, hw, xcc, (hw >> 13) & 3u, (hw >> 12) & 1u, (hw >> 8) & 15u};
+  }
+  std::sort(ws.begin(), ws.end(), [](const WorkerInfo &x, const WorkerInfo &y) {
+    return std::make_tuple(x.xcc, x.se, x.sh, x.cu, x.mailbox) < std::make_tuple(y.xcc, y.se, y.sh, y.cu, y.mailbox);
+  });
+  if (!(cfg.flags & LK_F_ANY_PLACEMENT)) {
+    for (uint32_t i = 1; i < c->n_workers; ++i) {
+      const auto &x = ws[i - 1], &y = ws[i];
+      if (x.xcc == y.xcc && x.se == y.se && x.sh == y.sh && x.cu == y.cu) {
+        for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
+        if (!join_kernel(c, 2.0 + idle_ms / 1000.0)) {
+          c->state = POISONED;
+          *out = c;
+          return fail(LK_ENODEV, "two workers share CU (xcc %u se %u cu %u); kernel did not end", x.xcc, x.se, x.cu);
+        }
+        return bail(fail(LK_ENODEV, "two workers share CU (xcc %u se %u sh %u cu %u)", x.xcc, x.se, x.sh, x.cu));
+      }
+    }
+  }
+  c->workers = ws;
+  {
+    std::vector<uint32_t> xs;
+    for (auto &w : ws) xs.push_back(w.xcc);
+    std::sort(xs.begin(), xs.end());
+    c->xcd_count = static_cast<uint32_t>(std::unique(xs.begin(), xs.end()) - xs.begin());
+  }
+
+  // Clusters.
+  switch (cfg.cluster_policy) {
+    case LK_CLUSTERS_PER_WORKER:
+      for (uint32_t w = 0; w < c->n_workers; ++w) c->clusters.push_back({w});
+      break;
+    case LK_CLUSTERS_ONE: {
+      std::vector<uint32_t> all(c->n_workers);
+      for (uint32_t w = 0; w < c->n_workers; ++w) all[w] = w;
+      c->clusters.push_back(all);
+      break;
+    }
+    case LK_CLUSTERS_PER_XCD: {
+      uint32_t prev = ~0u;
+      for (uint32_t w = 0; w < c->n_workers; ++w) {
+        if (ws[w].xcc != prev) c->clusters.emplace_back();
+        c->clusters.back().push_back(w);
+        prev = ws[w].xcc;
+      }
+      break;
+    }
+    case LK_CLUSTERS_EXPLICIT:
+      c->clusters.resize(cfg.n_clusters);
+      for (uint32_t w = 0; w < c->n_workers; ++w) c->clusters[cfg.cluster_of_worker[w]].push_back(w);
+      break;
+  }
+  c->n_clusters = static_cast<uint32_t>(c->clusters.size());
+  c->cluster_mbox.resize(c->n_clusters);
+  c->cluster_of_mbox.assign(c->n_workers, 0);
+  for (uint32_t k = 0; k < c->n_clusters; ++k)
+    for (uint32_t w : c->clusters[k]) {
+      c->cluster_mbox[k].push_back(ws[w].mailbox);
+      c->cluster_of_mbox[ws[w].mailbox] = k;
+    }
+  c->posted.assign(c->n_clusters, 0);
+  c->consumed.assign(c->n_clusters, 0);
+  c->init_ms = std::chrono::duration<double, std::milli>(clk::now() - t_begin).count();
+  *out = c;
+  g_last_error.clear();
+  return LK_OK;
+}
+
+int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, void *out, uint64_t *ticket) {
+  if (!c || !d || !ticket) return fail(LK_EINVAL, "NULL argument");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  if (d->op >= LK_OP_COUNT) return fail(LK_EINVAL, "unknown op %u", d->op);
+  if (d->flags || d->reserved) return fail(LK_EINVAL, "flags/reserved must be 0");
+  if (d->n > LK_MAX_N) return fail(LK_EINVAL, "n %llu > LK_MAX_N", static_cast<unsigned long long>(d->n));
+  const uint64_t ia = reinterpret_cast<uint64_t>(in), oa = reinterpret_cast<uint64_t>(out);
+  if (d->n && op_reads(d->op) && (!in || (ia & 3u))) return fail(LK_EINVAL, "input pointer NULL or not 4-byte aligned");
+  if (d->n && op_writes(d->op) && (!out || (oa & 3u))) return fail(LK_EINVAL, "output pointer NULL or not 4-byte aligned");
+  if ((ia | oa | d->aux) >> LKW_TAG_SHIFT) return fail(LK_EINVAL, "pointer outside the 48-bit address range");
+  if (d->aux & 7u) return fail(LK_EINVAL, "aux not 8-byte aligned");
+  if (d->op == LK_OP_SPIN && d->a < 0) return fail(LK_EINVAL, "SPIN iterations < 0");
+
+  const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
+  const uint64_t t = c->posted[cluster] + 1;
+  if (t - c->consumed[cluster] > c->depth) return fail(LK_EAGAIN, "ring full (depth %u)", c->depth);
+  for (uint32_t mb : mbs)
+    if (exited_code(worker_code(c, mb))) return fail(LK_ESTATE, "worker of mailbox %u has exited", mb);
+
+  const uint32_t k = static_cast<uint32_t>(mbs.size());
+  const uint32_t esz = 4;
+  for (uint32_t j = 0; j < k; ++j) {
+    uint64_t lo, hi;
+    lkd::slice_bounds(d->n, k, j, &lo, &hi);
+    const uint64_t sin = (op_reads(d->op) && in) ? ia + lo * esz : 0;
+    const uint64_t sout = (op_writes(d->op) && out) ? oa + lo * esz : 0;
+    const uint64_t saux = d->aux ? d->aux + 8ull * j : 0;
+    post_cmd(c, mbs[j], t, LKW_TO_WORK + d->op, hi - lo, sin, sout, saux, static_cast<uint32_t>(d->a),
+             static_cast<uint32_t>(d->b), d->alpha, j);
+  }
+  c->posted[cluster] = t;
+  *ticket = t;
+  return LK_OK;
+}
+
+static int wait_impl(lk_ctx *c, uint32_t cluster, uint64_t t, int64_t timeout_ns, lk_completion *info) {
+  if (!c) return fail(LK_EINVAL, "NULL context");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  if (t == 0 || t > c->posted[cluster]) return fail(LK_EINVAL, "ticket %llu was not posted", static_cast<unsigned long long>(t));
+  if (t <= c->consumed[cluster]) return fail(LK_EINVAL, "ticket %llu already released", static_cast<unsigned long long>(t));
+  const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
+  const bool bounded = timeout_ns >= 0;
+  const auto deadline = bounded ? clk::now() + std::chrono::nanoseconds(timeout_ns) : clk::time_point::max();
+  int64_t sum = 0;
+  uint64_t pmin = ~0ull, pmax = 0, dmin = ~0ull, dmax = 0;
+  bool fault = false;
+  for (uint32_t mb : mbs) {
+    lkw_status *st = slot_status(c, mb, t);
+    uint32_t spins = 0;
+    uint64_t w;
+    for (;;) {
+      w = load_acquire(&st->word);
+      if (LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING) break;
+      if ((++spins & 255u) == 0) {
+        if (bounded && clk::now() > deadline) return fail(LK_ETIMEDOUT, "ticket %llu not finished", static_cast<unsigned long long>(t));
+        if (exited_code(worker_code(c, mb))) {
+          w = load_acquire(&st->word);
+          if (LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING) break;
+          return fail(LK_ESTATE, "worker of mailbox %u exited before finishing ticket %llu", mb,
+                      static_cast<unsigned long long>(t));
+        }
+      }
+      _mm_pause();
+    }
+    const uint32_t code = LKW_CODE(w);
+    if (code == LKW_FROM_ERROR) fault = true;
+    sum += __atomic_load_n(&st->partial, __ATOMIC_RELAXED);
+    const uint64_t tp = __atomic_load_n(&st->t_pick, __ATOMIC_RELAXED);
+    const uint64_t td = __atomic_load_n(&st->t_done, __ATOMIC_RELAXED);
+    pmin = std::min(pmin, tp);
+    pmax = std::max(pmax, tp);
+    dmin = std::min(dmin, td);
+    dmax = std::max(dmax, td);
+  }
+  c->consumed[cluster] = t;
+  if (info) {
+    info->result = sum;
+    info->t_pick_min = pmin;
+    info->t_pick_max = pmax;
+    info->t_done_min = dmin;
+    info->t_done_max = dmax;
+  }
+  if (fault) return fail(LK_EFAULT, "a worker rejected ticket %llu", static_cast<unsigned long long>(t));
+  return LK_OK;
+}
+
+int lk_wait(lk_ctx *c, uint32_t cluster, uint64_t ticket, int64_t timeout_ns, int64_t *result) {
+  lk_completion info;
+  const int rc = wait_impl(c, cluster, ticket, timeout_ns, &info);
+  if (rc == LK_OK && result) *result = info.result;
+  return rc;
+}
+
+int lk_wait_info(lk_ctx *c, uint32_t cluster, uint64_t ticket, int64_t timeout_ns, lk_completion *out) {
+  if (!out) return fail(LK_EINVAL, "out is NULL");
+  return wait_impl(c, cluster, ticket, timeout_ns, out);
+}
+
+int lk_poll(lk_ctx *c, uint32_t cluster, uint64_t t, int *done) {
+  if (!c || !done) return fail(LK_EINVAL, "NULL argument");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  if (t == 0 || t > c->posted[cluster]) return fail(LK_EINVAL, "ticket was not posted");
+  if (t <= c->consumed[cluster]) {
+    *done = 1;
+    return LK_OK;
+  }
+  int all = 1;
+  for (uint32_t mb : c->cluster_mbox[cluster]) {
+    const uint64_t w = load_acquire(&slot_status(c, mb, t)->word);
+    if (!(LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING)) {
+      all = 0;
+      break;
+    }
+  }
+  *done = all;
+  return LK_OK;
+}
+
+int lk_dispose(lk_ctx *c) {
+  if (!c) return fail(LK_EINVAL, "NULL context");
+  if (c->state == DISPOSED) return LK_OK;
+  if (c->state == POISONED) {
+    if (!c->kernel_launched || join_kernel(c, 0.5)) {
+      release_gpu(c);
+      c->state = DISPOSED;
+      return LK_OK;
+    }
+    return fail(LK_ETIMEDOUT, "context poisoned: persistent kernel still running");
+  }
+  const auto t0 = clk::now();
+  const uint32_t idle_ms = c->cfg.idle_timeout_ms ? c->cfg.idle_timeout_ms : 10000u;
+  // Let every posted item finish (bounded), then post THREAD_EXIT behind it.
+  const auto drain_deadline = t0 + std::chrono::seconds(10);
+  for (uint32_t k = 0; k < c->n_clusters; ++k) {
+    const uint64_t t = c->posted[k];
+    for (uint32_t mb : c->cluster_mbox[k]) {
+      if (t > c->consumed[k]) {
+        lkw_status *st = slot_status(c, mb, t);
+        while (!(LKW_SEQ(load_acquire(&st->word)) == t && LKW_CODE(load_acquire(&st->word)) != LKW_FROM_WORKING)) {
+          if (exited_code(worker_code(c, mb)) || clk::now() > drain_deadline) break;
+          _mm_pause();
+        }
+      }
+      if (!exited_code(worker_code(c, mb))) post_cmd(c, mb, t + 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
+    }
+    c->consumed[k] = t;
+  }
+  if (!join_kernel(c, 5.0 + idle_ms / 1000.0)) {
+    c->state = POISONED;
+    return fail(LK_ETIMEDOUT, "persistent kernel did not end after EXIT (context poisoned)");
+  }
+  c->kernel_ms = c->wq.kernel_ms();
+  if (c->d_log && c->log_cap) {
+    c->host_log.resize(static_cast<size_t>(c->n_workers) * c->log_cap);
+    const hipError_t e = hipMemcpy(c->host_log.data(), c->d_log, sizeof(lkw_log) * c->host_log.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) c->host_log.clear();
+  }
+  // Worker records survive for lk_get_info: keep a copy of the exit codes.
+  uint32_t exited = 0;
+  for (uint32_t m = 0; m < c->n_workers; ++m) exited += exited_code(worker_code(c, m));
+  c->exited_at_dispose = exited;
+  release_gpu(c);
+  c->state = DISPOSED;
+  c->dispose_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  return LK_OK;
+}
+
+int lk_free(lk_ctx *c) {
+  if (!c) return LK_OK;
+  int rc = LK_OK;
+  if (c->state != DISPOSED) rc = lk_dispose(c);
+  if (c->state != DISPOSED) return rc;  // poisoned: keep the object so nothing dangles
+  delete c;
+  return LK_OK;
+}
+
+int lk_get_info(lk_ctx *c, lk_info *info) {
+  if (!c || !info) return fail(LK_EINVAL, "NULL argument");
+  memset(info, 0, sizeof *info);
+  info->n_workers = c->n_workers;
+  info->n_clusters = c->n_clusters;
+  info->queue_depth = c->depth;
+  info->threads_per_worker = c->threads;
+  info->cu_count = c->cu_count;
+  info->xcd_count = c->xcd_count;
+  info->state = c->state;
+  if (c->state == RUNNING) {
+    for (uint32_t m = 0; m < c->n_workers; ++m) info->workers_exited += exited_code(worker_code(c, m));
+  } else {
+    info->workers_exited = c->exited_at_dispose;
+  }
+  info->wall_clock_hz = c->wall_hz;
+  info->init_ms = c->init_ms;
+  info->dispose_ms = c->dispose_ms;
+  info->kernel_ms = c->kernel_ms;
+  return LK_OK;
+}
+
+int lk_topology(lk_ctx *c, uint32_t w, uint32_t *xcc, uint32_t *se, uint32_t *sh, uint32_t *cu) {
+  if (!c) return fail(LK_EINVAL, "NULL context");
+  if (w >= c->workers.size()) return fail(LK_EINVAL, "worker %u of %zu", w, c->workers.size());
+  const WorkerInfo &x = c->workers[w];
+  if (xcc) *xcc = x.xcc;
+  if (se) *se = x.se;
+  if (sh) *sh = x.sh;
+  if (cu) *cu = x.cu;
+  return LK_OK;
+}
+
+int lk_cluster_members(lk_ctx *c, uint32_t cluster, uint32_t *workers, uint32_t cap, uint32_t *count) {
+  if (!c || !count) return fail(LK_EINVAL, "NULL argument");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  const auto &m = c->clusters[cluster];
+  *count = static_cast<uint32_t>(m.size());
+  if (workers)
+    for (uint32_t i = 0; i < m.size() && i < cap; ++i) workers[i] = m[i];
+  return LK_OK;
+}
+
+int lk_read_log(lk_ctx *c, uint32_t w, lk_log_entry *out, uint32_t cap, uint32_t *count) {
+  if (!c || !count) return fail(LK_EINVAL, "NULL argument");
+  *count = 0;
+  if (c->state != DISPOSED) return fail(LK_ESTATE, "the log is available after lk_dispose");
+  if (w >= c->workers.size()) return fail(LK_EINVAL, "worker %u of %zu", w, c->workers.size());
+  if (c->host_log.empty()) return LK_OK;
+  const uint32_t mb = c->workers[w].mailbox;
+  const lkw_log *L = c->host_log.data() + static_cast<size_t>(mb) * c->log_cap;
+  // Entries are written at (seq-1) % cap; collect the valid ones, oldest first.
+  std::vector<lkw_log> v;
+  for (uint32_t i = 0; i < c->log_cap; ++i)
+    if (L[i].seq) v.push_back(L[i]);
+  std::sort(v.begin(), v.end(), [](const lkw_log &a, const lkw_log &b) { return a.seq < b.seq; });
+  const size_t skip = v.size() > cap ? v.size() - cap : 0;
+  uint32_t n = 0;
+  for (size_t i = skip; i < v.size(); ++i) {
+    if (out) {
+      out[n].seq = v[i].seq;
+      out[n].code = v[i].code;
+      out[n].worker = static_cast<uint16_t>(w);
+      out[n].xcc = v[i].xcc;
+      out[n].hwid = v[i].hwid;
+      out[n].t_pick = v[i].t_pick;
+      out[n].t_done = v[i].t_done;
+    }
+    ++n;
+  }
+  *count = n;
+  return LK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+/*
+ * lk_ops.hpp -- work-item bodies executed by one workgroup over one slice.
+ *
+ * Used by the persistent worker (one workgroup per CU runs whatever slice its mailbox
+ * receives) and by the per-launch baseline kernels (one workgroup per slice), so both
+ * dispatch paths run identical arithmetic and memory access patterns.
+ *
+ * Layout: every thread of the workgroup streams 16-byte vectors, consecutive threads
+ * taking consecutive vectors (fully coalesced 1 KiB per wave64 access), with U vectors
+ * per stream in flight per thread.  A scalar head aligns the input to 16 bytes and a
+ * scalar tail finishes the slice; when input and output disagree in their alignment
+ * modulo 16, the whole slice takes the (still coalesced) 4-byte path.
+ *
+ * Reductions: per-thread int64 partials, a wave64 butterfly with __shfl_xor, then one
+ * LDS slot per wave summed by thread 0.  Integer addition is associative, so the
+ * result is exact whatever the order.
+ */
+#ifndef LK_OPS_HPP
+#define LK_OPS_HPP
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lkops {
+
+constexpr int kMaxWaves = 16;  // 1024 threads
+
+// Native 4 x 32-bit vector (the non-temporal builtins take clang vector types).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct Slice {
+  uint32_t op;
+  uint64_t n;
+  const void *in;
+  void *out;
+  uint32_t a, b;
+  float alpha;
+};
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of every thread's v over a workgroup of nt threads; the total is valid in thread 0.
+// Ends with a barrier.
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *s_red, uint32_t nt) {
+  v = wave_sum_i64(v);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (lane == 0) s_red[wave] = v;
+  __syncthreads();
+  int64_t t = 0;
+  if (threadIdx.x == 0) {
+    const uint32_t nw = (nt + 63u) >> 6;
+    for (uint32_t w = 0; w < nw; ++w) t += s_red[w];
+  }
+  return t;
+}
+
+__device__ __forceinline__ uint32_t affine(uint32_t a, uint32_t x, uint32_t b) { return a * x + b; }
+
+// int32 affine map modulo 2^32 and/or int64 sum.  STORE=false gives SUM_I32_I64 (a=1, b=0).
+template <bool STORE>
+__device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int32_t *__restrict__ y,
+                                              uint64_t n, uint32_t a, uint32_t b, uint64_t nt) {
+  constexpr int U = 4;
+  const uint64_t tid = threadIdx.x;
+  int64_t acc = 0;
+  uint64_t done = 0;
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(x) & 15u;
+  const bool vec = !STORE || xa == (reinterpret_cast<uintptr_t>(y) & 15u);
+  if (vec) {
+    uint64_t head = ((16u - xa) & 15u) >> 2;
+    if (head > n) head = n;
+    if (tid < head) {
+      const uint32_t v = affine(a, static_cast<uint32_t>(x[tid]), b);
+      if (STORE) y[tid] = static_cast<int32_t>(v);
+      acc += static_cast<int32_t>(v);
+    }
+    const int4 *__restrict__ xv = reinterpret_cast<const int4 *>(x + head);
+    int4 *__restrict__ yv = STORE ? reinterpret_cast<int4 *>(y + head) : nullptr;
+    const uint64_t nv = (n - head) >> 2;
+    uint64_t k = tid;
+    for (; k + (U - 1) * nt < nv; k += U * nt) {
+      int4 r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = xv[k + u * nt];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int4 o;
+        o.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].x), b));
+        o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].y), b));
+        o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].z), b));
+        o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].w), b));
+        if (STORE) yv[k + u * nt] = o;
+        acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
+               static_cast<int64_t>(o.w);
+      }
+    }
+    for (; k < nv; k += nt) {
+      const int4 r = xv[k];
+      int4 o;
+      o.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.x), b));
+      o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
+      o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
+      o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
+      if (STORE) yv[k] = o;
+      acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
+             static_cast<int64_t>(o.w);
+    }
+    done = head + nv * 4;
+  }
+  for (uint64_t i = done + tid; i < n; i += nt) {
+    const uint32_t v = affine(a, static_cast<uint32_t>(x[i]), b);
+    if (STORE) y[i] = static_cast<int32_t>(v);
+    acc += static_cast<int32_t>(v);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
+  float4 o;
+  o.x = __builtin_fmaf(a, x.x, y.x);
+  o.y = __builtin_fmaf(a, x.y, y.y);
+  o.z = __builtin_fmaf(a, x.z, y.z);
+  o.w = __builtin_fmaf(a, x.w, y.w);
+  return o;
+}
+
+// y[i] = fma(alpha, x[i], y[i]) in place.
+__device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__restrict__ y, uint64_t n,
+                                      float alpha, uint64_t nt) {
+  constexpr int U = 4;
+  const uint64_t tid = threadIdx.x;
+  uint64_t done = 0;
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(x) & 15u;
+  if (xa == (reinterpret_cast<uintptr_t>(y) & 15u)) {
+    uint64_t head = ((16u - xa) & 15u) >> 2;
+    if (head > n) head = n;
+    if (tid < head) y[tid] = __builtin_fmaf(alpha, x[tid], y[tid]);
+    const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
+    float4 *__restrict__ yv = reinterpret_cast<float4 *>(y + head);
+    const uint64_t nv = (n - head) >> 2;
+    uint64_t k = tid;
+    for (; k + (U - 1) * nt < nv; k += U * nt) {
+      float4 rx[U], ry[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rx[u] = xv[k + u * nt];
+        ry[u] = yv[k + u * nt];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) yv[k + u * nt] = fma4(alpha, rx[u], ry[u]);
+    }
+    for (; k < nv; k += nt) yv[k] = fma4(alpha, xv[k], yv[k]);
+    done = head + nv * 4;
+  }
+  for (uint64_t i = done + tid; i < n; i += nt) y[i] = __builtin_fmaf(alpha, x[i], y[i]);
+}
+
+// out[i] = in[i] as raw 32-bit words.
+__device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                       uint64_t n, uint64_t nt) {
+  constexpr int U = 8;
+  const uint64_t tid = threadIdx.x;
+  uint64_t done = 0;
+  const uintptr_t ia = reinterpret_cast<uintptr_t>(in) & 15u;
+  if (ia == (reinterpret_cast<uintptr_t>(out) & 15u)) {
+    uint64_t head = ((16u - ia) & 15u) >> 2;
+    if (head > n) head = n;
+    if (tid < head) out[tid] = in[tid];
+    const u32x4 *__restrict__ iv = reinterpret_cast<const u32x4 *>(in + head);
+    u32x4 *__restrict__ ov = reinterpret_cast<u32x4 *>(out + head);
+    const uint64_t nv = (n - head) >> 2;
+    uint64_t k = tid;
+    for (; k + (U - 1) * nt < nv; k += U * nt) {
+      u32x4 r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(iv + k + u * nt);
+#pragma unroll
+      for (int u = 0; u < U; ++u) __builtin_nontemporal_store(r[u], ov + k + u * nt);
+    }
+    for (; k < nv; k += nt) ov[k] = iv[k];
+    done = head + nv * 4;
+  }
+  for (uint64_t i = done + tid; i < n; i += nt) out[i] = in[i];
+}
+
+// Compute-only loop (the paper's benchmark item, Sec. 3): `iters` dependent integer
+// multiply-adds per thread, kept alive without touching memory.
+__device__ __forceinline__ void spin(uint32_t iters) {
+  uint32_t v = threadIdx.x;
+  for (uint32_t i = 0; i < iters; ++i) v = v * 1664525u + 1013904223u;
+  asm volatile("" ::"v"(v));
+}
+
+// Execute one slice with the calling workgroup of nt threads (the thread count is passed
+// explicitly: the persistent worker is dispatched without the runtime's implicit kernel
+// arguments); returns the slice's int64 result in thread 0 (0 elsewhere and for ops
+// without a result).  Ends with a barrier.
+__device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uint32_t nt) {
+  int64_t acc = 0;
+  switch (s.op) {
+    case 1:  // AFFINE_SUM_I32
+      acc = affine_sum<true>(static_cast<const int32_t *>(s.in), static_cast<int32_t *>(s.out), s.n, s.a, s.b, nt);
+      break;
+    case 2:  // SUM_I32_I64
+      acc = affine_sum<false>(static_cast<const int32_t *>(s.in), nullptr, s.n, 1u, 0u, nt);
+      break;
+    case 3:  // SAXPY_F32
+      saxpy(static_cast<const float *>(s.in), static_cast<float *>(s.out), s.n, s.alpha, nt);
+      break;
+    case 4:  // COPY_F32
+      copy32(static_cast<const uint32_t *>(s.in), static_cast<uint32_t *>(s.out), s.n, nt);
+      break;
+    case 5:  // SPIN
+      spin(s.a);
+      break;
+    default:
+      break;
+  }
+  if (s.op == 1 || s.op == 2) return block_sum_i64(acc, s_red, nt);
+  __syncthreads();
+  return 0;
+}
+
+}  // namespace lkops
+
+#endif

@@ -1,0 +1,170 @@
+/*
+ * lk_worker.hip -- the persistent worker of the LightKernel dispatch loop for gfx950.
+ *
+ * One workgroup per CU (Sec. 2.3: one block per cluster, pinned at boot), dispatched once
+ * for the whole session on an HSA queue of its own (see lk_queue.cpp).  Each workgroup:
+ *   1. claims a mailbox, reads its physical placement from the HW_ID / XCC_ID registers
+ *      and announces THREAD_INIT (Table 1);
+ *   2. polls its to_GPU command slot: wave 0 reads the whole 64-byte slot with lanes 0..7,
+ *      with s_sleep backoff and an idle watchdog on the device wall clock;
+ *   3. on a new command, takes one system-scope acquire and broadcasts the descriptor to
+ *      the workgroup through LDS;
+ *   4. runs the work item over its slice with all its waves (lk_ops.hpp);
+ *   5. drains every wave's stores, then lane 0 publishes THREAD_FINISHED with one
+ *      system-scope release (Sec. 2.4: the master thread owns the two mailboxes);
+ *   6. loops until THREAD_EXIT (Table 1) or the watchdog.
+ * It is compiled to a standalone code object and uses no implicit kernel argument: the
+ * thread count travels in lkw_params.
+ */
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lk_devutil.hpp"
+#include "lk_device.h"
+#include "lk_ops.hpp"
+#include "lk_wire.h"
+
+using namespace lkdev;
+
+// ----------------------------------------------------------------------------- worker
+extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
+  extern __shared__ uint64_t lds_reserve[];  // only holds the CU: one worker per CU
+  __shared__ uint64_t s_w[LKW_CMD_WORDS];
+  __shared__ uint64_t s_t_pick;
+  __shared__ uint32_t s_mb, s_go, s_hw, s_xcc;
+  __shared__ int64_t s_red[lkops::kMaxWaves];
+  (void)lds_reserve;
+  const uint32_t tid = threadIdx.x;
+
+  // Boot: claim a mailbox, record the physical placement, announce INIT (Table 1).
+  if (tid == 0) {
+    const uint32_t m = atomicAdd(p.claim, 1u);
+    s_mb = m;
+    if (m < p.n_workers) {
+      const uint32_t hw = read_hw_id(), xcc = read_xcc_id();
+      lkw_worker *wr = p.workers + m;
+      st_sys_u32(&wr->hwid, hw);
+      st_sys_u32(&wr->xcc, xcc);
+      st_sys_u32(&wr->wg, blockIdx.x);
+      st_sys(&wr->t_boot, wall_clock64());
+      st_sys_release(&wr->word, LKW_WORD(0, LKW_FROM_INIT));
+    }
+  }
+  __syncthreads();
+  const uint32_t m = s_mb;
+  if (m >= p.n_workers) return;
+
+  lkw_cmd *ring = p.cmd + static_cast<uint64_t>(m) * p.depth;
+  lkw_status *sring = p.status + static_cast<uint64_t>(m) * p.depth;
+  lkw_worker *wr = p.workers + m;
+  uint64_t seq = 0;  // last sequence number executed by this worker
+
+  for (;;) {
+    const uint64_t want = seq + 1;
+    const uint32_t slot = static_cast<uint32_t>(want % p.depth);
+
+    // ---- poll: wave 0 reads the whole 64-byte slot, one 8-byte word per lane 0..7.
+    if (tid < 64) {
+      const uint64_t *src = ring[slot].w;
+      const uint64_t tag = want & 0xffffu;
+      const uint64_t t0 = wall_clock64();
+      uint32_t polls = 0, outcome = 0;
+      uint64_t v = 0;
+      for (;;) {
+        if (tid < LKW_CMD_WORDS) v = ld_sys(src + tid);
+        bool ok = true;
+        if (tid == 0) ok = LKW_SEQ(v) == want;
+        else if (tid < LKW_CMD_WORDS) ok = (v >> LKW_TAG_SHIFT) == tag;
+        if (__all(ok)) break;
+        ++polls;
+        if ((polls & 63u) == 0) {
+          const uint64_t now = wall_clock64();
+          if (now - t0 > p.idle_ticks) {
+            outcome = 1;
+            break;
+          }
+          if ((polls & 4095u) == 0 && tid == 0) st_sys(&wr->heartbeat, now);
+        }
+        backoff(p.poll_sleep);
+      }
+      if (outcome == 0) {
+        if (!(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        if (tid < LKW_CMD_WORDS) s_w[tid] = v;
+      }
+      if (tid == 0) {
+        s_go = outcome;
+        s_t_pick = wall_clock64();
+        s_hw = read_hw_id();
+        s_xcc = read_xcc_id();
+      }
+    }
+    __syncthreads();
+
+    if (s_go != 0) {  // idle watchdog: leave the loop
+      if (tid == 0) st_sys_release(&wr->word, LKW_WORD(seq, LKW_FROM_TIMEDOUT));
+      return;
+    }
+    const uint64_t w0 = s_w[LKW_W_DOORBELL];
+    const uint32_t code = LKW_CODE(w0);
+    if (code == LKW_TO_EXIT) {  // THREAD_EXIT (Table 1)
+      if (tid == 0) {
+        lkw_status *st = sring + slot;
+        st_sys(&st->t_pick, s_t_pick);
+        st_sys_release(&st->word, LKW_WORD(want, LKW_FROM_EXITED));
+        st_sys_release(&wr->word, LKW_WORD(want, LKW_FROM_EXITED));
+      }
+      return;
+    }
+
+    if (tid == 0 && (p.flags & LKW_K_REPORT_WORKING))
+      st_sys(&sring[slot].word, LKW_WORD(want, LKW_FROM_WORKING));
+
+    uint32_t reply = LKW_FROM_FINISHED;
+    lkops::Slice s;
+    s.op = 0;
+    s.n = s_w[LKW_W_N] & LKW_PAYLOAD_MASK;
+    s.in = reinterpret_cast<const void *>(s_w[LKW_W_IN] & LKW_PAYLOAD_MASK);
+    s.out = reinterpret_cast<void *>(s_w[LKW_W_OUT] & LKW_PAYLOAD_MASK);
+    s.a = static_cast<uint32_t>(s_w[LKW_W_A]);
+    s.b = static_cast<uint32_t>(s_w[LKW_W_B]);
+    s.alpha = __uint_as_float(static_cast<uint32_t>(s_w[LKW_W_ALPHA]));
+    if (code == LKW_TO_NOP) {
+      reply = LKW_FROM_NOP;
+    } else if (code >= LKW_TO_WORK && code < LKW_TO_WORK + lkd::kOpCount) {
+      s.op = code - LKW_TO_WORK;
+    } else {
+      reply = LKW_FROM_ERROR;
+    }
+    const int64_t partial = lkops::run_slice(s, s_red, p.threads);
+
+    drain_wave_memory();
+    __syncthreads();
+
+    // ---- complete: one system-scope release orders the whole workgroup's output
+    // (drained above and ordered by the barrier) before the FINISHED word.
+    if (tid == 0) {
+      const uint64_t t_done = wall_clock64();
+      int64_t *aux = reinterpret_cast<int64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
+      if (aux) *aux = partial;
+      if (p.log) {
+        lkw_log *e = p.log + static_cast<uint64_t>(m) * p.log_cap + (seq % p.log_cap);
+        e->seq = static_cast<uint32_t>(want);
+        e->code = static_cast<uint16_t>(code);
+        e->mailbox = static_cast<uint16_t>(m);
+        e->xcc = s_xcc;
+        e->hwid = s_hw;
+        e->t_pick = s_t_pick;
+        e->t_done = t_done;
+      }
+      lkw_status *st = sring + slot;
+      st_sys_i64(&st->partial, partial);
+      st_sys(&st->t_pick, s_t_pick);
+      st_sys(&st->t_done, t_done);
+      st_sys_u32(&st->hwid, s_hw);
+      st_sys_u32(&st->xcc, s_xcc);
+      st_sys_release(&st->word, LKW_WORD(want, reply));
+    }
+    seq = want;
+  }
+}
+

@@ -1,0 +1,404 @@
+"""ctypes binding of liblk.so (include/lk.h, include/lk_bench.h).
+
+Argument marshalling only: every step of the dispatch path runs in the native library and
+its gfx950 kernels.  PyTorch tensors provide device memory (their data_ptr() is passed as
+a plain device address).  If the library is missing this module raises; there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblk.so")
+
+OK, EINVAL, EAGAIN, ETIMEDOUT, ESTATE, ENODEV, EHIP, EFAULT = 0, -1, -2, -3, -4, -5, -6, -7
+OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN = range(6)
+CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
+F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
+COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
+
+# Table 1 values of the command codes recorded in the device log.
+CODE_NOP, CODE_EXIT, CODE_WORK = 4, 8, 16
+
+EXPORTED = [
+    "lk_config_default", "lk_init", "lk_submit", "lk_wait", "lk_wait_info", "lk_poll",
+    "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
+    "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
+    "lkb_serial", "lkb_lanes", "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
+    "lkb_copy",
+]
+
+
+class LKError(RuntimeError):
+    def __init__(self, code, where, detail=""):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code}) {detail}".strip())
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_workers", ctypes.c_uint32),
+                ("threads_per_worker", ctypes.c_uint32), ("queue_depth", ctypes.c_uint32),
+                ("cluster_policy", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
+                ("cluster_of_worker", ctypes.POINTER(ctypes.c_uint32)),
+                ("poll_sleep", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("log_capacity", ctypes.c_uint32), ("idle_timeout_ms", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("alpha", ctypes.c_float),
+                ("reserved", ctypes.c_uint32), ("aux", ctypes.c_uint64),
+                ("user_tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("result", ctypes.c_int64), ("t_pick_min", ctypes.c_uint64),
+                ("t_pick_max", ctypes.c_uint64), ("t_done_min", ctypes.c_uint64),
+                ("t_done_max", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_workers", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
+                ("queue_depth", ctypes.c_uint32), ("threads_per_worker", ctypes.c_uint32),
+                ("cu_count", ctypes.c_uint32), ("xcd_count", ctypes.c_uint32),
+                ("state", ctypes.c_uint32), ("workers_exited", ctypes.c_uint32),
+                ("wall_clock_hz", ctypes.c_uint64), ("init_ms", ctypes.c_double),
+                ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+
+
+class LogEntry(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_uint32), ("code", ctypes.c_uint16), ("worker", ctypes.c_uint16),
+                ("xcc", ctypes.c_uint32), ("hwid", ctypes.c_uint32), ("t_pick", ctypes.c_uint64),
+                ("t_done", ctypes.c_uint64)]
+
+
+# numpy view of lkb_item (40 bytes)
+ITEM_DTYPE = np.dtype([("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4"),
+                       ("n", "<u8"), ("inp", "<u8"), ("out", "<u8")])
+COMPLETION_DTYPE = np.dtype([("result", "<i8"), ("t_pick_min", "<u8"), ("t_pick_max", "<u8"),
+                             ("t_done_min", "<u8"), ("t_done_max", "<u8")])
+LOG_DTYPE = np.dtype([("seq", "<u4"), ("code", "<u2"), ("worker", "<u2"), ("xcc", "<u4"),
+                      ("hwid", "<u4"), ("t_pick", "<u8"), ("t_done", "<u8")])
+
+_lib = None
+
+
+def lib():
+    """Load liblk.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); there is no fallback path")
+    # PyTorch bundles its own HIP runtime under the same soname; importing it first makes
+    # liblk.so bind to that one copy, so tensors and the library share one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32
+    PU32, PU64, PI64, PD = (ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double))
+    sig = {
+        "lk_config_default": (None, [ctypes.POINTER(Config)]),
+        "lk_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(P)]),
+        "lk_submit": (ctypes.c_int, [P, U32, ctypes.POINTER(Desc), P, P, PU64]),
+        "lk_wait": (ctypes.c_int, [P, U32, U64, I64, PI64]),
+        "lk_wait_info": (ctypes.c_int, [P, U32, U64, I64, ctypes.POINTER(Completion)]),
+        "lk_poll": (ctypes.c_int, [P, U32, U64, ctypes.POINTER(ctypes.c_int)]),
+        "lk_dispose": (ctypes.c_int, [P]),
+        "lk_free": (ctypes.c_int, [P]),
+        "lk_get_info": (ctypes.c_int, [P, ctypes.POINTER(Info)]),
+        "lk_topology": (ctypes.c_int, [P, U32, PU32, PU32, PU32, PU32]),
+        "lk_cluster_members": (ctypes.c_int, [P, U32, PU32, U32, PU32]),
+        "lk_read_log": (ctypes.c_int, [P, U32, P, U32, PU32]),
+        "lk_slice": (ctypes.c_int, [U64, U32, U32, PU64, PU64]),
+        "lk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lk_last_error": (ctypes.c_char_p, []),
+        "lkb_serial": (ctypes.c_int, [P, U32, P, U64, I64, P, P, P, P]),
+        "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD]),
+        "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
+        "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
+        "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
+        "lkb_copy": (ctypes.c_int, [I32, P, P, U64, U32, U32, PD, PD]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def strerror(code):
+    try:
+        return lib().lk_strerror(code).decode()
+    except ImportError:
+        return str(code)
+
+
+def last_error():
+    return lib().lk_last_error().decode()
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise LKError(rc, where, last_error())
+    return rc
+
+
+def slice_bounds(n, k, j):
+    lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().lk_slice(n, k, j, ctypes.byref(lo), ctypes.byref(hi)), "lk_slice")
+    return lo.value, hi.value
+
+
+def _ptr(t):
+    """Device address of a tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _i32(v):
+    """Any integer, reduced modulo 2^32 and read as a two's-complement int32."""
+    v = int(v) & 0xffffffff
+    return v - (1 << 32) if v >= (1 << 31) else v
+
+
+def _np_ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+_OP_DTYPES = {OP_AFFINE_SUM_I32: "int32", OP_SUM_I32_I64: "int32", OP_SAXPY_F32: "float32",
+              OP_COPY_F32: "float32"}
+
+
+def _check_tensor(t, op, what):
+    if t is None:
+        return
+    if isinstance(t, int):
+        return
+    want = _OP_DTYPES.get(op)
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if want is not None and str(t.dtype) != "torch." + want:
+        raise ValueError(f"{what} must be {want}, got {t.dtype}")
+
+
+class Context:
+    """A running LightKernel context: persistent workers, one per CU (lk_init)."""
+
+    def __init__(self, n_workers=0, threads=256, depth=1, clusters=CLUSTERS_PER_WORKER,
+                 cluster_of_worker=None, poll_sleep=0, flags=0, log_capacity=0,
+                 idle_timeout_ms=10000, init_timeout_s=5.0, device=0):
+        L = lib()
+        cfg = Config()
+        L.lk_config_default(ctypes.byref(cfg))
+        cfg.device = device
+        cfg.n_workers = n_workers
+        cfg.threads_per_worker = threads
+        cfg.queue_depth = depth
+        cfg.poll_sleep = poll_sleep
+        cfg.flags = flags
+        cfg.log_capacity = log_capacity
+        cfg.idle_timeout_ms = idle_timeout_ms
+        cfg.init_timeout_ns = int(init_timeout_s * 1e9)
+        self._cow = None
+        if cluster_of_worker is not None:
+            cow = np.ascontiguousarray(cluster_of_worker, dtype=np.uint32)
+            self._cow = cow
+            cfg.cluster_policy = CLUSTERS_EXPLICIT
+            cfg.n_clusters = int(cow.max()) + 1 if cow.size else 0
+            cfg.cluster_of_worker = cow.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        else:
+            cfg.cluster_policy = clusters
+        self._h = ctypes.c_void_p()
+        rc = L.lk_init(ctypes.byref(cfg), ctypes.byref(self._h))
+        if rc != OK:
+            detail = last_error()
+            if self._h:
+                L.lk_free(self._h)
+            self._h = None
+            raise LKError(rc, "lk_init", detail)
+        self._closed = False
+
+    # -- phases ---------------------------------------------------------------------------
+    def submit(self, cluster, op, x=None, y=None, a=0, b=0, alpha=0.0, n=None, aux=None):
+        """Trigger: post one item; returns its ticket.  Raises LKError(EAGAIN) if full."""
+        _check_tensor(x, op, "x")
+        _check_tensor(y, op, "y")
+        if n is None:
+            ref = x if x is not None else y
+            n = 0 if ref is None else (ref.numel() if not isinstance(ref, int) else 0)
+        d = Desc(op, 0, n, _i32(a), _i32(b), float(np.float32(alpha)), 0, _ptr(aux) or 0, 0)
+        t = ctypes.c_uint64()
+        rc = lib().lk_submit(self._h, cluster, ctypes.byref(d), _ptr(x), _ptr(y), ctypes.byref(t))
+        _check(rc, "lk_submit")
+        return t.value
+
+    def try_submit(self, cluster, op, **kw):
+        """Like submit but returns None when the ring is full."""
+        try:
+            return self.submit(cluster, op, **kw)
+        except LKError as e:
+            if e.code == EAGAIN:
+                return None
+            raise
+
+    def wait(self, cluster, ticket, timeout=10.0):
+        """Wait: returns the item's int64 result.  timeout in seconds (None = no deadline)."""
+        r = ctypes.c_int64()
+        ns = -1 if timeout is None else int(timeout * 1e9)
+        _check(lib().lk_wait(self._h, cluster, ticket, ns, ctypes.byref(r)), "lk_wait")
+        return r.value
+
+    def wait_info(self, cluster, ticket, timeout=10.0):
+        c = Completion()
+        ns = -1 if timeout is None else int(timeout * 1e9)
+        _check(lib().lk_wait_info(self._h, cluster, ticket, ns, ctypes.byref(c)), "lk_wait_info")
+        return {f: getattr(c, f) for f, _ in Completion._fields_}
+
+    def poll(self, cluster, ticket):
+        d = ctypes.c_int()
+        _check(lib().lk_poll(self._h, cluster, ticket, ctypes.byref(d)), "lk_poll")
+        return bool(d.value)
+
+    def close(self):
+        """Dispose: THREAD_EXIT to every worker, join the kernel, free GPU resources."""
+        if self._h and not self._closed:
+            _check(lib().lk_dispose(self._h), "lk_dispose")
+            self._closed = True
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().lk_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- introspection ---------------------------------------------------------------------
+    def info(self):
+        i = Info()
+        _check(lib().lk_get_info(self._h, ctypes.byref(i)), "lk_get_info")
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def topology(self, worker):
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _check(lib().lk_topology(self._h, worker, *[ctypes.byref(x) for x in v]), "lk_topology")
+        return tuple(x.value for x in v)  # (xcc, se, sh, cu)
+
+    def members(self, cluster):
+        cnt = ctypes.c_uint32()
+        _check(lib().lk_cluster_members(self._h, cluster, None, 0, ctypes.byref(cnt)), "lk_cluster_members")
+        out = (ctypes.c_uint32 * max(cnt.value, 1))()
+        _check(lib().lk_cluster_members(self._h, cluster, out, cnt.value, ctypes.byref(cnt)), "lk_cluster_members")
+        return [out[i] for i in range(cnt.value)]
+
+    def log(self, worker, cap=1 << 20):
+        """Device log of a worker (after close()), as a LOG_DTYPE array, oldest first."""
+        out = np.zeros(cap, dtype=LOG_DTYPE)
+        cnt = ctypes.c_uint32()
+        _check(lib().lk_read_log(self._h, worker, _np_ptr(out), cap, ctypes.byref(cnt)), "lk_read_log")
+        return out[:cnt.value]
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- native runners (lk_bench.h) -------------------------------------------------------
+    def run_serial(self, cluster, items, timeout=10.0):
+        """Submit-then-wait every item (ITEM_DTYPE array) on one cluster, natively timed.
+        Returns (results, lat_us, trigger_us, completions)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        n = items.size
+        res = np.zeros(n, np.int64)
+        lat = np.zeros(n, np.float64)
+        trig = np.zeros(n, np.float64)
+        comp = np.zeros(n, COMPLETION_DTYPE)
+        rc = lib().lkb_serial(self._h, cluster, _np_ptr(items), n, int(timeout * 1e9), _np_ptr(res),
+                              _np_ptr(lat), _np_ptr(trig), _np_ptr(comp))
+        _check(rc, "lkb_serial")
+        return res, lat, trig, comp
+
+    def run_lanes(self, lane_cluster, items, in_flight=1, threads=8, timeout=10.0):
+        """items: (n_lanes, items_per_lane) ITEM_DTYPE array.  Returns (results, lat_us, elapsed_s)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        lanes, per = items.shape
+        lc = np.ascontiguousarray(lane_cluster, dtype=np.uint32)
+        assert lc.size == lanes
+        res = np.zeros((lanes, per), np.int64)
+        lat = np.zeros((lanes, per), np.float64)
+        el = ctypes.c_double()
+        rc = lib().lkb_lanes(self._h, _np_ptr(lc), lanes, _np_ptr(items), per, in_flight, threads,
+                             int(timeout * 1e9), _np_ptr(res), _np_ptr(lat), ctypes.byref(el))
+        _check(rc, "lkb_lanes")
+        return res, lat, el.value
+
+
+def launch_serial(items, k=1, threads=256, mode=COMPLETE_SYNC, device=0):
+    """One ordinary kernel launch per item.  Returns (results, lat_us, launch_us)."""
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+    n = items.size
+    res = np.zeros(n, np.int64)
+    lat = np.zeros(n, np.float64)
+    lau = np.zeros(n, np.float64)
+    _check(lib().lkb_launch_serial(device, k, threads, _np_ptr(items), n, mode, _np_ptr(res),
+                                   _np_ptr(lat), _np_ptr(lau)), "lkb_launch_serial")
+    return res, lat, lau
+
+
+def launch_lanes(items, streams=4, threads_host=8, threads=256, mode=0, device=0):
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+    lanes, per = items.shape
+    res = np.zeros((lanes, per), np.int64)
+    lat = np.zeros((lanes, per), np.float64)
+    el = ctypes.c_double()
+    _check(lib().lkb_launch_lanes(device, lanes, _np_ptr(items), per, streams, threads_host, threads,
+                                  mode, _np_ptr(res), _np_ptr(lat), ctypes.byref(el)),
+           "lkb_launch_lanes")
+    return res, lat, el.value
+
+
+def pingpong(workers=1, iters=10000, poll_sleep=0, spread=True, device=0):
+    rtt = np.zeros(workers * iters, np.float64)
+    _check(lib().lkb_pingpong(device, workers, iters, poll_sleep, 1 if spread else 0, _np_ptr(rtt)),
+           "lkb_pingpong")
+    return rtt.reshape(workers, iters)
+
+
+def copy_bandwidth(src, dst, nbytes, grid, reps=10, device=0):
+    ms, gbps = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lkb_copy(device, _ptr(src), _ptr(dst), nbytes, grid, reps, ctypes.byref(ms),
+                          ctypes.byref(gbps)), "lkb_copy")
+    return ms.value, gbps.value
+
+
+def make_items(op, n, inp, out, a=0, b=0, alpha=0.0):
+    """Build an ITEM_DTYPE array from per-item columns (scalars broadcast)."""
+    cols = np.broadcast_arrays(np.asarray(op), np.asarray(n), np.asarray(inp, dtype=np.uint64),
+                               np.asarray(out, dtype=np.uint64), np.asarray(a), np.asarray(b),
+                               np.asarray(alpha, dtype=np.float32))
+    shape = cols[0].shape
+    it = np.zeros(shape, ITEM_DTYPE)
+    it["op"], it["n"], it["inp"], it["out"] = cols[0], cols[1], cols[2], cols[3]
+    it["a"] = (np.asarray(cols[4]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
+    it["b"] = (np.asarray(cols[5]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
+    it["alpha"] = cols[6]
+    return it

@@ -1,0 +1,164 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, it exports every
+symbol include/*.h declares, the Python structs match the C layouts, the wire codes are
+the paper's Table 1 values, argument validation happens before any device call, and the
+host slicing rule agrees with the oracle's."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_01212_amd import lk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+WIRE = os.path.join(ROOT, "paper_2310_01212_amd", "csrc", "lk_wire.h")
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = open(os.path.join(INCLUDE, h)).read()
+            names += re.findall(r"^LK_API\s+[\w\s\*]+?\b(lkb?_\w+)\s*\(", text, re.M)
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lk.lib()
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lk.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (lkb?_\w+)", out))
+    assert set(declared) == exported
+    assert set(lk.EXPORTED) == exported
+
+
+def test_struct_layouts_match_the_c_headers(tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text('#include "lk.h"\n#include "lk_bench.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc), sizeof(lk_config),'
+                   ' sizeof(lk_completion), sizeof(lk_info), sizeof(lk_log_entry), sizeof(lkb_item),'
+                   ' offsetof(lk_config, init_timeout_ns), offsetof(lk_desc, aux)); return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(lk.Desc), ctypes.sizeof(lk.Config), ctypes.sizeof(lk.Completion),
+            ctypes.sizeof(lk.Info), ctypes.sizeof(lk.LogEntry), lk.ITEM_DTYPE.itemsize,
+            lk.Config.init_timeout_ns.offset, lk.Desc.aux.offset]
+    assert got == want
+    assert lk.LOG_DTYPE.itemsize == ctypes.sizeof(lk.LogEntry)
+    assert lk.COMPLETION_DTYPE.itemsize == ctypes.sizeof(lk.Completion)
+
+
+def _wire_defines():
+    d = {}
+    for m in re.finditer(r"#define\s+(LKW_\w+)\s+(\d+)u", open(WIRE).read()):
+        d[m.group(1)] = int(m.group(2))
+    return d
+
+
+def test_wire_codes_are_table1():
+    golden = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "table1_mailbox_codes.txt")):
+        if line.strip() and not line.startswith("#"):
+            direction, name, v = line.split()
+            golden[(direction, name)] = int(v)
+    d = _wire_defines()
+    assert d["LKW_FROM_INIT"] == golden[("from_GPU", "THREAD_INIT")]
+    assert d["LKW_FROM_FINISHED"] == golden[("from_GPU", "THREAD_FINISHED")]
+    assert d["LKW_FROM_WORKING"] == golden[("from_GPU", "THREAD_WORKING")]
+    assert d["LKW_FROM_NOP"] == golden[("from_GPU", "THREAD_NOP")]
+    assert d["LKW_TO_NOP"] == golden[("to_GPU", "THREAD_NOP")]
+    assert d["LKW_TO_EXIT"] == golden[("to_GPU", "THREAD_EXIT")]
+    assert d["LKW_TO_WORK"] == golden[("to_GPU", "THREAD_WORK")]
+    # extension codes use values Table 1 leaves free
+    ext = {d["LKW_FROM_ERROR"], d["LKW_FROM_EXITED"], d["LKW_FROM_TIMEDOUT"]}
+    assert not ext & {0, 1, 2, 4} and len(ext) == 3
+    assert lk.CODE_NOP == d["LKW_TO_NOP"] and lk.CODE_EXIT == d["LKW_TO_EXIT"] and lk.CODE_WORK == d["LKW_TO_WORK"]
+
+
+def test_host_slicing_agrees_with_oracle():
+    oracle.build(force=False)
+    for n in [0, 1, 255, 256, 257, 4096, 8191, 262144, 262144 + 77, 16384, 10 ** 6 + 3]:
+        for k in [1, 2, 3, 7, 8, 32, 256]:
+            for j in range(k):
+                assert lk.slice_bounds(n, k, j) == oracle.slice_bounds(n, k, j), (n, k, j)
+    with pytest.raises(lk.LKError):
+        lk.slice_bounds(10, 0, 0)
+
+
+def test_strerror_names_every_code():
+    names = {c: lk.strerror(c) for c in range(-7, 1)}
+    assert len(set(names.values())) == 8
+    assert lk.strerror(-99) == "unknown error"
+
+
+def _cfg(**kw):
+    cfg = lk.Config()
+    lk.lib().lk_config_default(ctypes.byref(cfg))
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+@pytest.mark.parametrize("field,value", [
+    ("threads_per_worker", 100), ("threads_per_worker", 2048), ("queue_depth", 65),
+    ("cluster_policy", 9), ("poll_sleep", 200), ("idle_timeout_ms", 3600001),
+    ("flags", 0x80), ("n_workers", 5000), ("init_timeout_ns", -1),
+])
+def test_init_rejects_bad_config_before_touching_a_device(field, value):
+    L = lk.lib()
+    h = ctypes.c_void_p()
+    rc = L.lk_init(ctypes.byref(_cfg(**{field: value})), ctypes.byref(h))
+    assert rc == lk.EINVAL, (field, rc, lk.last_error())
+    assert not h
+
+
+def test_explicit_clusters_are_validated():
+    L = lk.lib()
+    h = ctypes.c_void_p()
+    cow = (ctypes.c_uint32 * 4)(0, 0, 2, 2)   # cluster 1 empty
+    cfg = _cfg(cluster_policy=lk.CLUSTERS_EXPLICIT, n_clusters=3, n_workers=4,
+               cluster_of_worker=ctypes.cast(cow, ctypes.POINTER(ctypes.c_uint32)))
+    assert L.lk_init(ctypes.byref(cfg), ctypes.byref(h)) == lk.EINVAL
+    assert "no worker" in lk.last_error()
+    cow2 = (ctypes.c_uint32 * 2)(0, 3)
+    cfg = _cfg(cluster_policy=lk.CLUSTERS_EXPLICIT, n_clusters=2, n_workers=2,
+               cluster_of_worker=ctypes.cast(cow2, ctypes.POINTER(ctypes.c_uint32)))
+    assert L.lk_init(ctypes.byref(cfg), ctypes.byref(h)) == lk.EINVAL
+
+
+def test_calls_on_a_null_context_fail_cleanly():
+    L = lk.lib()
+    d = lk.Desc()
+    t = ctypes.c_uint64()
+    r = ctypes.c_int64()
+    assert L.lk_submit(None, 0, ctypes.byref(d), None, None, ctypes.byref(t)) == lk.EINVAL
+    assert L.lk_wait(None, 0, 1, 0, ctypes.byref(r)) == lk.EINVAL
+    assert L.lk_dispose(None) == lk.EINVAL
+    assert L.lk_free(None) == lk.OK
+    assert L.lk_init(None, None) == lk.EINVAL
+
+
+def test_init_without_a_gpu_reports_no_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(lk.LKError) as e:
+        lk.Context()
+    assert e.value.code == lk.ENODEV
+
+
+def test_make_items_marshals_int32_and_addresses():
+    it = lk.make_items(lk.OP_AFFINE_SUM_I32, 4096, [0x1000, 0x2000], [0x3000, 0x4000],
+                       a=np.array([2 ** 32 - 1, 5], dtype=np.uint32), b=-7, alpha=0.5)
+    assert it.shape == (2,)
+    assert it["a"].tolist() == [-1, 5] and it["b"].tolist() == [-7, -7]
+    assert it["inp"].tolist() == [0x1000, 0x2000] and it["out"].tolist() == [0x3000, 0x4000]
+    assert lk._i32(2 ** 31) == -2 ** 31 and lk._i32(-1) == -1

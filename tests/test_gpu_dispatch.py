@@ -1,0 +1,430 @@
+"""GPU parity of the persistent dispatch path against the CPU oracle, through the C ABI.
+
+Each test prints the case it runs (seed, shape, entry point) before touching the GPU.
+While a context is open nothing here calls a device-wide synchronisation: results are
+read after close(), or through an independent stream (the visibility test).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_01212_amd import lk, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SENT_I32 = 0x7FBADBAD
+SENT_F32_BITS = 0x7FA0DEAD  # a signalling-NaN payload
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    lk.lib()
+    oracle.build(force=False)
+    torch.cuda.synchronize()
+    yield
+    torch.cuda.synchronize()
+
+
+def to_dev(a):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    torch.cuda.current_stream().synchronize()
+    return t
+
+
+def sentinel_i32(shape):
+    return torch.full(shape, SENT_I32, dtype=torch.int32, device="cuda")
+
+
+def sentinel_f32(shape):
+    return torch.full(shape, SENT_F32_BITS, dtype=torch.int32, device="cuda").view(torch.float32)
+
+
+def addr(t, elem_offset=0):
+    return t.data_ptr() + elem_offset * t.element_size()
+
+
+def same_f32(got, want):
+    """Bitwise equality, except that a NaN result only has to be a NaN: IEEE 754 leaves
+    the sign and payload of a NaN produced by an operation to the implementation."""
+    got = np.asarray(got, np.float32)
+    want = np.asarray(want, np.float32)
+    nan = np.isnan(want)
+    return bool(np.array_equal(np.isnan(got), nan) and
+                np.array_equal(got[~nan].view(np.uint32), want[~nan].view(np.uint32)))
+
+
+def check_log(entries, n_items, code, allowed_xcc=None):
+    """I1 exactly once and I2 FIFO per mailbox; I3 placement on allowed XCDs."""
+    assert entries.size == n_items
+    assert np.array_equal(entries["seq"], np.arange(1, n_items + 1, dtype=np.uint32))
+    if code is not None:
+        assert np.all(entries["code"] == code)
+    assert np.all(entries["t_done"] >= entries["t_pick"])
+    if allowed_xcc is not None:
+        assert set(np.unique(entries["xcc"]).tolist()) <= set(allowed_xcc)
+    cu_bits = entries["hwid"] & 0x7F00  # CU_ID, SH_ID, SE_ID fields: the physical CU
+    assert np.unique(cu_bits).size == 1, "a worker moved between CUs"
+
+
+# ------------------------------------------------------------------ plain: 1 worker, 1000 items
+def test_plain_1000_items_bit_exact_with_log_invariants():
+    say("plain: 1 worker x 1000 affine+sum items of 4096 int32, seed 0")
+    X, AB = workloads.plain()
+    x = to_dev(X)
+    y = sentinel_i32(X.shape)
+    torch.cuda.current_stream().synchronize()
+    rows = np.arange(X.shape[0], dtype=np.uint64)
+    items = lk.make_items(lk.OP_AFFINE_SUM_I32, X.shape[1], addr(x) + rows * X.shape[1] * 4,
+                          addr(y) + rows * X.shape[1] * 4, AB[:, 0], AB[:, 1])
+    ctx = lk.Context(n_workers=1, log_capacity=2048)
+    try:
+        res, lat, trig, comp = ctx.run_serial(0, items)
+    finally:
+        ctx.close()
+    Y = y.cpu().numpy()
+    for i in range(X.shape[0]):
+        yr, sr = oracle.affine_sum_i32(X[i], int(AB[i, 0]), int(AB[i, 1]))
+        assert res[i] == sr, i
+        assert np.array_equal(Y[i], yr), i
+    check_log(ctx.log(0), X.shape[0], lk.CODE_WORK + lk.OP_AFFINE_SUM_I32)
+    assert np.all(lat > 0) and np.all(trig <= lat)
+    info = ctx.info()
+    assert info["state"] == 1 and info["kernel_ms"] > 0
+
+
+# ------------------------------------------------------------------ edge cases on one worker
+def _edge_items(rng):
+    """(op, n, x_off, y_off, a, b, alpha) with ragged sizes and misalignments."""
+    cases = []
+    for n in [0, 1, 3, 4, 5, 255, 256, 257, 1023, 4097, 65537, 1000003]:
+        for xo, yo in [(0, 0), (1, 1), (3, 3), (1, 2)]:
+            cases.append((lk.OP_AFFINE_SUM_I32, n, xo, yo))
+            cases.append((lk.OP_SAXPY_F32, n, xo, yo))
+        cases.append((lk.OP_SUM_I32_I64, n, 2, 0))
+        cases.append((lk.OP_COPY_F32, n, 1, 3))
+    return cases
+
+
+def test_edge_cases_ragged_misaligned_and_special_values():
+    rng = np.random.default_rng(42)
+    cases = _edge_items(rng)
+    say(f"edge: {len(cases)} items, ragged n up to 1000003, misaligned in/out")
+    span = 1000003 + 8
+    xs_i = rng.integers(-2 ** 31, 2 ** 31, (len(cases), span), dtype=np.int64).astype(np.int32)
+    # float inputs with specials: subnormals, +-0, inf, nan payloads, near-overflow
+    xs_f = rng.standard_normal((len(cases), span)).astype(np.float32)
+    ys_f = rng.standard_normal((len(cases), span)).astype(np.float32)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-40, 3e38, -3e38], np.float32)
+    xs_f[:, :special.size] = special
+    ys_f[:, 1:special.size + 1] = special[::-1]
+    xs_f.view(np.uint32)[:, 20] = 0x7FC01234  # quiet NaN with payload
+    x_i = to_dev(xs_i)
+    x_f = to_dev(xs_f)
+    y_f = to_dev(ys_f.copy())
+    y_i = sentinel_i32((len(cases), span))
+    torch.cuda.current_stream().synchronize()
+    AB = rng.integers(-2 ** 31, 2 ** 31, (len(cases), 2), dtype=np.int64)
+    alphas = rng.uniform(-2, 2, len(cases)).astype(np.float32)
+    alphas[::7] = np.float32(0.0)
+    rows = []
+    for r, (op, n, xo, yo) in enumerate(cases):
+        if op in (lk.OP_AFFINE_SUM_I32, lk.OP_SUM_I32_I64):
+            inp, out = addr(x_i, r * span + xo), addr(y_i, r * span + yo)
+        elif op == lk.OP_SAXPY_F32:
+            inp, out = addr(x_f, r * span + xo), addr(y_f, r * span + yo)
+        else:
+            inp, out = addr(x_f, r * span + xo), addr(y_i, r * span + yo)
+        rows.append((op, n, inp, out, AB[r, 0], AB[r, 1], alphas[r]))
+    cols = list(zip(*rows))
+    items = lk.make_items(np.array(cols[0]), np.array(cols[1], np.uint64), np.array(cols[2], np.uint64),
+                          np.array(cols[3], np.uint64), np.array(cols[4]), np.array(cols[5]),
+                          np.array(cols[6], np.float32))
+    # NOP and SPIN ride along (no memory effect, result 0)
+    extra = lk.make_items(np.array([lk.OP_NOP, lk.OP_SPIN]), 0, 0, 0, a=np.array([0, 2000]), b=0)
+    items = np.concatenate([items, extra])
+    with lk.Context(n_workers=1, log_capacity=4096) as ctx:
+        res, _, _, _ = ctx.run_serial(0, items)
+    YI = y_i.cpu().numpy()
+    YF = y_f.cpu().numpy()
+    for r, (op, n, xo, yo) in enumerate(cases):
+        if op == lk.OP_AFFINE_SUM_I32:
+            yr, sr = oracle.affine_sum_i32(xs_i[r, xo:xo + n].copy(), int(AB[r, 0]), int(AB[r, 1]))
+            assert res[r] == sr, (r, op, n)
+            assert np.array_equal(YI[r, yo:yo + n], yr), (r, n, xo, yo)
+            assert np.all(YI[r, :yo] == SENT_I32) and np.all(YI[r, yo + n:] == SENT_I32)
+        elif op == lk.OP_SUM_I32_I64:
+            assert res[r] == oracle.sum_i32_i64(xs_i[r, xo:xo + n].copy()), (r, n)
+        elif op == lk.OP_SAXPY_F32:
+            yr = ys_f[r].copy()
+            seg = yr[yo:yo + n].copy()
+            oracle.saxpy_f32(alphas[r], xs_f[r, xo:xo + n].copy(), seg)
+            yr[yo:yo + n] = seg
+            assert same_f32(YF[r], yr), (r, n, xo, yo)
+        else:
+            got = YI[r, yo:yo + n].view(np.uint32)
+            want = oracle.copy_f32(xs_f[r, xo:xo + n].copy()).view(np.uint32)
+            assert np.array_equal(got, want), (r, n)
+            assert np.all(YI[r, yo + n:] == SENT_I32)
+    assert res[-1] == 0 and res[-2] == 0
+
+
+# ------------------------------------------------------------------ all CUs: small, full compare
+def _allcu_setup(ctx, items_per_lane, n_of_lane):
+    lanes = ctx.info()["n_workers"]
+    span = max(n_of_lane(w) for w in range(lanes)) + 4
+    X = np.zeros((lanes, span), np.float32)
+    Y0 = np.zeros((lanes, span), np.float32)
+    A = np.zeros((lanes, items_per_lane), np.float32)
+    for w in range(lanes):
+        x, y, a = workloads.allcu_lane(w, items=items_per_lane, n=n_of_lane(w))
+        X[w, :x.size], Y0[w, :y.size], A[w] = x, y, a
+    return X, Y0, A, span
+
+
+def test_all_cus_small_fifo_chains_bit_exact():
+    with lk.Context(n_workers=0, log_capacity=128) as ctx:
+        lanes = ctx.info()["n_workers"]
+        assert lanes == ctx.info()["cu_count"]
+        say(f"all CUs small: {lanes} lanes x 60 SAXPY items, ragged n")
+        nl = lambda w: 1000 + 37 * (w % 11)
+        X, Y0, A, span = _allcu_setup(ctx, 60, nl)
+        x, y = to_dev(X), to_dev(Y0)
+        torch.cuda.current_stream().synchronize()
+        lanes_idx = np.arange(lanes, dtype=np.uint64)[:, None]
+        n = np.array([nl(w) for w in range(lanes)], np.uint64)[:, None]
+        items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + lanes_idx * span * 4,
+                              addr(y) + lanes_idx * span * 4, alpha=A)
+        res, lat, el = ctx.run_lanes(np.arange(lanes), items, in_flight=1, threads=8)
+    Y = y.cpu().numpy()
+    for w in range(lanes):
+        yr = Y0[w, :nl(w)].copy()
+        oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=X[w, :nl(w)].copy(), out=yr, alpha=a) for a in A[w]])
+        assert np.array_equal(Y[w, :nl(w)].view(np.uint32), yr.view(np.uint32)), w
+        check_log(ctx.log(w), 60, lk.CODE_WORK + lk.OP_SAXPY_F32)
+    # workers are in physical order and each sits on its own CU
+    topo = [ctx.topology(w) for w in range(lanes)]
+    assert topo == sorted(topo) and len(set(topo)) == lanes
+
+
+def test_all_cus_full_size_sampled_elements():
+    """256 mailboxes x 10,000 back-to-back SAXPY items of 16,384 fp32; final y of 64
+    sampled elements per lane against the oracle's 10,000-step fma chain."""
+    with lk.Context(n_workers=0, depth=1) as ctx:
+        lanes = ctx.info()["n_workers"]
+        say(f"all CUs full size: {lanes} lanes x {workloads.ALLCU_ITEMS} items x {workloads.ALLCU_N}")
+        X, Y0, A, span = _allcu_setup(ctx, workloads.ALLCU_ITEMS, lambda w: workloads.ALLCU_N)
+        x, y = to_dev(X), to_dev(Y0)
+        torch.cuda.current_stream().synchronize()
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        items = lk.make_items(lk.OP_SAXPY_F32, workloads.ALLCU_N, addr(x) + li * span * 4,
+                              addr(y) + li * span * 4, alpha=A)
+        t0 = time.time()
+        res, lat, el = ctx.run_lanes(np.arange(lanes), items, in_flight=1, threads=8, timeout=30.0)
+        say(f"  {lanes * workloads.ALLCU_ITEMS / el:.0f} items/s, p50 {np.percentile(lat, 50):.2f} us, "
+            f"wall {time.time() - t0:.2f} s")
+    Y = y.cpu().numpy()
+    rng = np.random.default_rng(77)
+    for w in range(lanes):
+        idx = np.unique(np.concatenate([[0, workloads.ALLCU_N - 1], rng.integers(0, workloads.ALLCU_N, 62)]))
+        for i in idx:
+            want = oracle.saxpy_chain_elem(X[w, i], Y0[w, i], A[w])
+            assert Y[w, i].view(np.uint32) == np.float32(want).view(np.uint32), (w, i)
+
+
+# ------------------------------------------------------------------ clusters = XCDs
+def test_clusters_per_xcd_split_items_and_placement():
+    rng = np.random.default_rng(3)
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, log_capacity=64) as ctx:
+        info = ctx.info()
+        ncl = info["n_clusters"]
+        say(f"clusters per XCD: {ncl} clusters; affine+sum over 262144(+ragged), tiny and empty items")
+        assert ncl == info["xcd_count"]
+        members = [ctx.members(c) for c in range(ncl)]
+        xccs = [{ctx.topology(w)[0] for w in m} for m in members]
+        assert all(len(s) == 1 for s in xccs)
+        sizes = [262144, 262144 + 1000, 100, 0]
+        N = max(sizes)
+        X = rng.integers(-2 ** 31, 2 ** 31, (ncl, len(sizes), N), dtype=np.int64).astype(np.int32)
+        AB = rng.integers(-2 ** 31, 2 ** 31, (ncl, len(sizes), 2), dtype=np.int64)
+        x = to_dev(X)
+        y = sentinel_i32(X.shape)
+        aux = torch.zeros((ncl, len(sizes), 64), dtype=torch.int64, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        results = {}
+        for c in range(ncl):
+            for s, n in enumerate(sizes):
+                off = (c * len(sizes) + s) * N
+                t = ctx.submit(c, lk.OP_AFFINE_SUM_I32, x=addr(x, off), y=addr(y, off), a=int(AB[c, s, 0]),
+                               b=int(AB[c, s, 1]), n=n, aux=addr(aux, (c * len(sizes) + s) * 64))
+                results[(c, s)] = ctx.wait(c, t)
+    Y = y.cpu().numpy()
+    AUX = aux.cpu().numpy()
+    for c in range(ncl):
+        k = len(members[c])
+        for s, n in enumerate(sizes):
+            yr, sr = oracle.affine_sum_i32(X[c, s, :n].copy(), int(AB[c, s, 0]), int(AB[c, s, 1]))
+            assert results[(c, s)] == sr
+            assert oracle.exec_cluster(oracle.AFFINE_SUM_I32, k, X[c, s, :n].copy(), np.empty(n, np.int32),
+                                       a=int(AB[c, s, 0]), b=int(AB[c, s, 1])) == sr
+            assert np.array_equal(Y[c, s, :n], yr) and np.all(Y[c, s, n:] == SENT_I32)
+            assert AUX[c, s, :k].sum() == sr   # per-member partials
+        for w in members[c]:
+            check_log(ctx.log(w), len(sizes), lk.CODE_WORK + lk.OP_AFFINE_SUM_I32, allowed_xcc=xccs[c])
+
+
+# ------------------------------------------------------------------ I4 visibility and coexistence
+def test_completion_implies_visibility_on_an_independent_stream():
+    rng = np.random.default_rng(11)
+    n = 1 << 20
+    X = rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32)
+    say("visibility: 1 worker, affine over 1 Mi int32, read back on an independent stream")
+    x = to_dev(X)
+    y = sentinel_i32((n,))
+    torch.cuda.current_stream().synchronize()
+    side = torch.cuda.Stream()
+    with lk.Context(n_workers=4, idle_timeout_ms=4000) as ctx:
+        for trial in range(3):
+            a, b = int(rng.integers(-2 ** 31, 2 ** 31)), int(rng.integers(-2 ** 31, 2 ** 31))
+            t = ctx.submit(trial % 4, lk.OP_AFFINE_SUM_I32, x=x, y=y, a=a, b=b)
+            s = ctx.wait(trial % 4, t)
+            t0 = time.time()
+            with torch.cuda.stream(side):
+                host = y.to("cpu", non_blocking=False)
+                side.synchronize()
+                z = (x.float() * 2).sum()  # torch compute while the workers spin
+                side.synchronize()
+            dt = time.time() - t0
+            yr, sr = oracle.affine_sum_i32(X, a, b)
+            assert s == sr
+            assert np.array_equal(host.numpy(), yr)
+            assert dt < 2.0, f"side stream took {dt:.2f} s: queued behind the persistent kernel?"
+            # the legacy default stream and a device-wide synchronisation do not wait for
+            # the persistent dispatch either: it lives on a queue of its own
+            t0 = time.time()
+            host2 = y.cpu()
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            assert np.array_equal(host2.numpy(), yr)
+            assert dt < 2.0, f"default stream took {dt:.2f} s"
+            del z
+
+
+# ------------------------------------------------------------------ error paths
+def test_ring_full_timeout_and_disposed_state():
+    say("errors: EAGAIN at depth 1, ETIMEDOUT on a long SPIN item, ESTATE after close")
+    with lk.Context(n_workers=1, depth=1, idle_timeout_ms=5000) as ctx:
+        t1 = ctx.submit(0, lk.OP_SPIN, a=2_000_000)
+        with pytest.raises(lk.LKError) as e:
+            ctx.submit(0, lk.OP_NOP)
+        assert e.value.code == lk.EAGAIN
+        with pytest.raises(lk.LKError) as e:
+            ctx.wait(0, t1, timeout=0.0)
+        assert e.value.code == lk.ETIMEDOUT
+        assert ctx.wait(0, t1, timeout=10.0) == 0
+        with pytest.raises(lk.LKError) as e:
+            ctx.wait(0, t1)
+        assert e.value.code == lk.EINVAL   # already released
+        t2 = ctx.submit(0, lk.OP_NOP)
+        assert ctx.wait(0, t2) == 0
+    with pytest.raises(lk.LKError) as e:
+        ctx.submit(0, lk.OP_NOP)
+    assert e.value.code == lk.ESTATE
+    ctx.close()  # idempotent
+
+
+def test_deeper_ring_keeps_fifo():
+    rng = np.random.default_rng(5)
+    n = 4096
+    x0 = rng.standard_normal(n).astype(np.float32)
+    y0 = rng.standard_normal(n).astype(np.float32)
+    alphas = rng.uniform(-2, 2, 200).astype(np.float32)
+    say("depth 8: 200 SAXPY items on one mailbox, up to 8 in flight")
+    x, y = to_dev(x0), to_dev(y0)
+    with lk.Context(n_workers=1, depth=8, log_capacity=256) as ctx:
+        items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x), addr(y), alpha=alphas)[None, :]
+        res, lat, el = ctx.run_lanes([0], items, in_flight=8, threads=1)
+    want = y0.copy()
+    oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=x0, out=want, alpha=a) for a in alphas])
+    assert np.array_equal(y.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    check_log(ctx.log(0), 200, lk.CODE_WORK + lk.OP_SAXPY_F32)
+
+
+def test_idle_watchdog_ends_workers():
+    say("watchdog: idle timeout 300 ms, then submit sees the exited workers")
+    ctx = lk.Context(n_workers=2, idle_timeout_ms=300)
+    time.sleep(1.0)
+    assert ctx.info()["workers_exited"] == 2
+    with pytest.raises(lk.LKError) as e:
+        ctx.submit(0, lk.OP_NOP)
+    assert e.value.code == lk.ESTATE
+    ctx.close()
+    assert ctx.info()["state"] == 1
+
+
+# ------------------------------------------------------------------ per-launch baselines
+@pytest.mark.parametrize("mode", [lk.COMPLETE_SYNC, lk.COMPLETE_FLAG, lk.COMPLETE_SYNC | lk.USE_GRAPH])
+def test_per_launch_baseline_matches_oracle(mode):
+    say(f"baseline launch mode {mode}: 50 plain items, then one 32-slice item")
+    X, AB = workloads.plain(items=50)
+    x = to_dev(X)
+    y = sentinel_i32(X.shape)
+    torch.cuda.current_stream().synchronize()
+    rows = np.arange(50, dtype=np.uint64)
+    items = lk.make_items(lk.OP_AFFINE_SUM_I32, 4096, addr(x) + rows * 4096 * 4, addr(y) + rows * 4096 * 4,
+                          AB[:, 0], AB[:, 1])
+    res, lat, lau = lk.launch_serial(items, k=1, mode=mode)
+    Y = y.cpu().numpy()
+    for i in range(50):
+        yr, sr = oracle.affine_sum_i32(X[i], int(AB[i, 0]), int(AB[i, 1]))
+        assert res[i] == sr and np.array_equal(Y[i], yr)
+    big = np.random.default_rng(8).integers(-2 ** 31, 2 ** 31, 262144 + 5, dtype=np.int64).astype(np.int32)
+    xb = to_dev(big)
+    yb = sentinel_i32(big.shape)
+    torch.cuda.current_stream().synchronize()
+    it = lk.make_items(lk.OP_AFFINE_SUM_I32, big.size, addr(xb), addr(yb), 7, -3)[None]
+    r2, _, _ = lk.launch_serial(it, k=32, mode=mode)
+    yr, sr = oracle.affine_sum_i32(big, 7, -3)
+    assert r2[0] == sr and np.array_equal(yb.cpu().numpy(), yr)
+
+
+def test_launch_lanes_baseline_matches_oracle():
+    say("baseline launch lanes: 16 lanes x 20 SAXPY items, 4 streams, plain and graph")
+    rng = np.random.default_rng(6)
+    lanes, per, n = 16, 20, 3000
+    X = rng.standard_normal((lanes, n)).astype(np.float32)
+    Y0 = rng.standard_normal((lanes, n)).astype(np.float32)
+    A = rng.uniform(-2, 2, (lanes, per)).astype(np.float32)
+    for mode in (0, lk.USE_GRAPH):
+        x, y = to_dev(X), to_dev(Y0)
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * n * 4, addr(y) + li * n * 4, alpha=A)
+        lk.launch_lanes(items, streams=4, threads_host=4, mode=mode)
+        Y = y.cpu().numpy()
+        for w in range(lanes):
+            want = Y0[w].copy()
+            oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=X[w], out=want, alpha=a) for a in A[w]])
+            assert np.array_equal(Y[w].view(np.uint32), want.view(np.uint32)), (mode, w)
+
+
+# ------------------------------------------------------------------ probes
+def test_pingpong_and_copy_probes_run():
+    say("probes: pingpong 1 and 8 workers, copy 64 MiB")
+    rtt = lk.pingpong(workers=1, iters=2000)
+    assert rtt.shape == (1, 2000) and np.all(rtt > 0) and np.median(rtt) < 50
+    rtt8 = lk.pingpong(workers=8, iters=200)
+    assert np.all(rtt8 > 0)
+    nbytes = 64 << 20
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    torch.cuda.current_stream().synchronize()
+    ms, gbps = lk.copy_bandwidth(src, dst, nbytes, grid=2048, reps=5)
+    assert gbps > 100
+    assert torch.equal(src.cpu(), dst.cpu())
