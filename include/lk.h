@@ -209,7 +209,10 @@ typedef struct lk_info {
   double init_ms;              /* lk_init duration */
   double dispose_ms;           /* lk_dispose duration (0 before) */
   double kernel_ms;            /* persistent kernel duration from the packet processor's
-                                  dispatch timestamps (after lk_dispose; 0 before) */
+                                  dispatch timestamps (after lk_dispose; 0 before, and 0
+                                  when a tool intercepting the queue hides them) */
+  double device_span_ms;       /* first worker boot to last worker exit on the device
+                                  wall clock (after lk_dispose) */
 } lk_info;
 
 LK_API int lk_get_info(lk_ctx *ctx, lk_info *info);

@@ -47,10 +47,11 @@ LK_API int lkb_serial(lk_ctx *c, uint32_t cluster, const lkb_item *items, uint64
 /* Feed n_lanes clusters back-to-back: lane l posts items[l*items_per_lane + k] to
  * lane_cluster[l] in order, keeping up to `in_flight` of them posted, and is served by
  * host thread l % n_threads.  lat_us[l*items_per_lane + k] = submit to completion
- * observed; results likewise; *elapsed_s = first submit to last completion. */
+ * observed; results and info (device-side timing) likewise, each nullable;
+ * *elapsed_s = first submit to last completion. */
 LK_API int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const lkb_item *items,
               uint64_t items_per_lane, uint32_t in_flight, uint32_t n_threads, int64_t timeout_ns,
-              int64_t *results, double *lat_us, double *elapsed_s);
+              int64_t *results, double *lat_us, double *elapsed_s, lk_completion *info);
 
 #define LKB_COMPLETE_SYNC 0u  /* completion observed by hipStreamSynchronize */
 #define LKB_COMPLETE_FLAG 1u  /* completion observed through a host-coherent word the

@@ -160,7 +160,7 @@ int lkb_serial(lk_ctx *c, uint32_t cluster, const lkb_item *items, uint64_t coun
 
 int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const lkb_item *items,
               uint64_t items_per_lane, uint32_t in_flight, uint32_t n_threads, int64_t timeout_ns, int64_t *results,
-              double *lat_us, double *elapsed_s) {
+              double *lat_us, double *elapsed_s, lk_completion *info) {
   if (!c || !lane_cluster || (!items && items_per_lane)) return bfail(LK_EINVAL, "NULL argument");
   if (n_threads == 0 || n_threads > 256 || in_flight == 0 || in_flight > LK_MAX_DEPTH)
     return bfail(LK_EINVAL, "n_threads 1..256 and in_flight 1..%u", LK_MAX_DEPTH);
@@ -171,6 +171,9 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
   std::atomic<int> error{0};
   std::atomic<bool> stop{false};
   const auto start = clk::now();
+  // Each host thread owns a fixed set of lanes (one producer per mailbox).  Per lane and
+  // per sweep: first collect every finished ticket, then refill up to in_flight, so a
+  // lane is re-armed as soon as its completion is seen.
   auto worker = [&](uint32_t tix) {
     struct Lane {
       uint32_t id, cluster;
@@ -186,9 +189,34 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
       L.t_sub.resize(items_per_lane);
       lanes.push_back(std::move(L));
     }
+    auto fail_all = [&](int rc) {
+      error.store(rc);
+      stop.store(true);
+    };
     uint64_t remaining = lanes.size() * items_per_lane;
     while (remaining && !stop.load(std::memory_order_relaxed)) {
       for (Lane &L : lanes) {
+        while (L.done < L.next) {
+          const uint64_t t = L.first_ticket + L.done;
+          int fin = 0;
+          int rc = lk_poll(c, L.cluster, t, &fin);
+          if (rc) return fail_all(rc);
+          if (!fin) {
+            if (timeout_ns >= 0 && clk::now() - L.t_sub[L.done] > std::chrono::nanoseconds(timeout_ns))
+              return fail_all(LK_ETIMEDOUT);
+            break;
+          }
+          const auto now = clk::now();
+          lk_completion ci;
+          rc = lk_wait_info(c, L.cluster, t, 0, &ci);
+          if (rc) return fail_all(rc);
+          const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.done;
+          if (results) results[idx] = ci.result;
+          if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done], now);
+          if (info) info[idx] = ci;
+          ++L.done;
+          --remaining;
+        }
         while (L.next < items_per_lane && L.next - L.done < in_flight) {
           const lkb_item &it = items[static_cast<uint64_t>(L.id) * items_per_lane + L.next];
           const lk_desc d = to_desc(it);
@@ -197,44 +225,9 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
           const int rc = lk_submit(c, L.cluster, &d, reinterpret_cast<const void *>(it.in),
                                    reinterpret_cast<void *>(it.out), &t);
           if (rc == LK_EAGAIN) break;
-          if (rc) {
-            error.store(rc);
-            stop.store(true);
-            return;
-          }
+          if (rc) return fail_all(rc);
           if (L.next == 0) L.first_ticket = t;
           ++L.next;
-        }
-        while (L.done < L.next) {
-          const uint64_t t = L.first_ticket + L.done;
-          int fin = 0;
-          int rc = lk_poll(c, L.cluster, t, &fin);
-          if (rc) {
-            error.store(rc);
-            stop.store(true);
-            return;
-          }
-          if (!fin) {
-            if (timeout_ns >= 0 && clk::now() - L.t_sub[L.done] > std::chrono::nanoseconds(timeout_ns)) {
-              error.store(LK_ETIMEDOUT);
-              stop.store(true);
-              return;
-            }
-            break;
-          }
-          const auto now = clk::now();
-          int64_t r = 0;
-          rc = lk_wait(c, L.cluster, t, 0, &r);
-          if (rc) {
-            error.store(rc);
-            stop.store(true);
-            return;
-          }
-          const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.done;
-          if (results) results[idx] = r;
-          if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done], now);
-          ++L.done;
-          --remaining;
         }
       }
       _mm_pause();
@@ -245,7 +238,7 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
   for (auto &t : th) t.join();
   if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
   const int rc = error.load();
-  if (rc) return bfail(rc, "lanes run failed: %s (%s)", lk_strerror(rc), lk_last_error());
+  if (rc) return bfail(rc, "lanes run failed: %s", lk_strerror(rc));
   return LK_OK;
 }
 

@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(1024) lk_item(lkd::ItemArgs a) {
   s.a = a.a;
   s.b = a.b;
   s.alpha = a.alpha;
-  const int64_t partial = lkops::run_slice(s, s_red, blockDim.x);
+  const int64_t partial = lkops::run_slice<lkops::CachedStore>(s, s_red, blockDim.x);
   drain_wave_memory();
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -59,6 +59,20 @@ struct WorkerInfo {
   uint32_t hwid, xcc, se, sh, cu;
 };
 
+// Host-side sequence state of one cluster, on its own 128-byte block: clusters are
+// driven by different host threads and must not share cache lines.
+struct alignas(128) ClusterSeq {
+  uint64_t posted = 0;    // last ticket posted (== every member mailbox's last seq)
+  uint64_t consumed = 0;  // last ticket whose completion the host has taken
+};
+
+// A decoded status record.
+struct Status {
+  uint32_t code;
+  int64_t partial;
+  uint64_t t_pick, t_done;
+};
+
 inline bool exited_code(uint32_t code) { return code == LKW_FROM_EXITED || code == LKW_FROM_TIMEDOUT; }
 
 }  // namespace
@@ -80,10 +94,10 @@ struct lk_ctx {
   std::vector<WorkerInfo> workers;                  // physical order
   std::vector<std::vector<uint32_t>> clusters;      // member worker indices, slice order
   std::vector<std::vector<uint32_t>> cluster_mbox;  // member mailboxes, slice order
-  std::vector<uint64_t> posted, consumed;           // per cluster (== each member's seq)
+  std::vector<ClusterSeq> seqs;                     // per cluster
   std::vector<uint32_t> cluster_of_mbox;
   std::vector<lkw_log> host_log;                    // copied at dispose
-  double init_ms = 0, dispose_ms = 0, kernel_ms = 0;
+  double init_ms = 0, dispose_ms = 0, kernel_ms = 0, device_span_ms = 0;
   bool kernel_launched = false;
   uint32_t exited_at_dispose = 0;
 };
@@ -91,10 +105,30 @@ struct lk_ctx {
 namespace {
 
 lkw_cmd *slot_cmd(lk_ctx *c, uint32_t mb, uint64_t seq) {
-  return c->cmd + static_cast<uint64_t>(mb) * c->depth + seq % c->depth;
+  return c->cmd + static_cast<uint64_t>(mb) * LKW_RING_STRIDE(c->depth) + seq % c->depth;
 }
 lkw_status *slot_status(lk_ctx *c, uint32_t mb, uint64_t seq) {
-  return c->status + static_cast<uint64_t>(mb) * c->depth + seq % c->depth;
+  return c->status + static_cast<uint64_t>(mb) * LKW_RING_STRIDE(c->depth) + seq % c->depth;
+}
+
+// True (and *out filled) once the status record of `seq` is complete: word 0 holds seq
+// with a final code and every other word carries seq's tag.
+bool read_status(const lkw_status *st, uint64_t seq, Status *out) {
+  const uint64_t w0 = load_acquire(&st->w[LKW_S_WORD]);
+  if (LKW_SEQ(w0) != seq || LKW_CODE(w0) == LKW_FROM_WORKING) return false;
+  uint64_t v[LKW_S_WORDS];
+  const uint64_t tag = LKW_TAG(seq);
+  for (int i = 1; i < LKW_S_WORDS; ++i) {
+    v[i] = __atomic_load_n(&st->w[i], __ATOMIC_ACQUIRE);
+    if ((v[i] & ~LKW_PAYLOAD_MASK) != tag) return false;
+  }
+  if (out) {
+    out->code = LKW_CODE(w0);
+    out->partial = static_cast<int64_t>((v[LKW_S_PART_LO] & 0xffffffffull) | ((v[LKW_S_PART_HI] & 0xffffffffull) << 32));
+    out->t_pick = v[LKW_S_T_PICK] & LKW_PAYLOAD_MASK;
+    out->t_done = v[LKW_S_T_DONE] & LKW_PAYLOAD_MASK;
+  }
+  return true;
 }
 uint32_t worker_code(lk_ctx *c, uint32_t mb) { return LKW_CODE(load_acquire(&c->wrec[mb].word)); }
 
@@ -253,8 +287,8 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   };
 
   // Mailboxes: command ring, status ring, worker records, in one host-coherent region.
-  const size_t cmd_bytes = sizeof(lkw_cmd) * c->n_workers * c->depth;
-  const size_t st_bytes = sizeof(lkw_status) * c->n_workers * c->depth;
+  const size_t cmd_bytes = sizeof(lkw_cmd) * c->n_workers * LKW_RING_STRIDE(c->depth);
+  const size_t st_bytes = sizeof(lkw_status) * c->n_workers * LKW_RING_STRIDE(c->depth);
   const size_t wr_bytes = sizeof(lkw_worker) * c->n_workers;
   auto up = [](size_t v) { return (v + 4095) & ~static_cast<size_t>(4095); };
   const size_t region = up(cmd_bytes) + up(st_bytes) + up(wr_bytes);
@@ -400,8 +434,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
       c->cluster_mbox[k].push_back(ws[w].mailbox);
       c->cluster_of_mbox[ws[w].mailbox] = k;
     }
-  c->posted.assign(c->n_clusters, 0);
-  c->consumed.assign(c->n_clusters, 0);
+  c->seqs.assign(c->n_clusters, ClusterSeq{});
   c->init_ms = std::chrono::duration<double, std::milli>(clk::now() - t_begin).count();
   *out = c;
   g_last_error.clear();
@@ -423,8 +456,9 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   if (d->op == LK_OP_SPIN && d->a < 0) return fail(LK_EINVAL, "SPIN iterations < 0");
 
   const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
-  const uint64_t t = c->posted[cluster] + 1;
-  if (t - c->consumed[cluster] > c->depth) return fail(LK_EAGAIN, "ring full (depth %u)", c->depth);
+  ClusterSeq &cs = c->seqs[cluster];
+  const uint64_t t = cs.posted + 1;
+  if (t - cs.consumed > c->depth) return fail(LK_EAGAIN, "ring full (depth %u)", c->depth);
   for (uint32_t mb : mbs)
     if (exited_code(worker_code(c, mb))) return fail(LK_ESTATE, "worker of mailbox %u has exited", mb);
 
@@ -439,7 +473,7 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
     post_cmd(c, mbs[j], t, LKW_TO_WORK + d->op, hi - lo, sin, sout, saux, static_cast<uint32_t>(d->a),
              static_cast<uint32_t>(d->b), d->alpha, j);
   }
-  c->posted[cluster] = t;
+  cs.posted = t;
   *ticket = t;
   return LK_OK;
 }
@@ -448,8 +482,9 @@ static int wait_impl(lk_ctx *c, uint32_t cluster, uint64_t t, int64_t timeout_ns
   if (!c) return fail(LK_EINVAL, "NULL context");
   if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
   if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
-  if (t == 0 || t > c->posted[cluster]) return fail(LK_EINVAL, "ticket %llu was not posted", static_cast<unsigned long long>(t));
-  if (t <= c->consumed[cluster]) return fail(LK_EINVAL, "ticket %llu already released", static_cast<unsigned long long>(t));
+  ClusterSeq &cs = c->seqs[cluster];
+  if (t == 0 || t > cs.posted) return fail(LK_EINVAL, "ticket %llu was not posted", static_cast<unsigned long long>(t));
+  if (t <= cs.consumed) return fail(LK_EINVAL, "ticket %llu already released", static_cast<unsigned long long>(t));
   const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
   const bool bounded = timeout_ns >= 0;
   const auto deadline = bounded ? clk::now() + std::chrono::nanoseconds(timeout_ns) : clk::time_point::max();
@@ -457,34 +492,28 @@ static int wait_impl(lk_ctx *c, uint32_t cluster, uint64_t t, int64_t timeout_ns
   uint64_t pmin = ~0ull, pmax = 0, dmin = ~0ull, dmax = 0;
   bool fault = false;
   for (uint32_t mb : mbs) {
-    lkw_status *st = slot_status(c, mb, t);
+    const lkw_status *st = slot_status(c, mb, t);
     uint32_t spins = 0;
-    uint64_t w;
-    for (;;) {
-      w = load_acquire(&st->word);
-      if (LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING) break;
+    Status s;
+    while (!read_status(st, t, &s)) {
       if ((++spins & 255u) == 0) {
         if (bounded && clk::now() > deadline) return fail(LK_ETIMEDOUT, "ticket %llu not finished", static_cast<unsigned long long>(t));
         if (exited_code(worker_code(c, mb))) {
-          w = load_acquire(&st->word);
-          if (LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING) break;
+          if (read_status(st, t, &s)) break;
           return fail(LK_ESTATE, "worker of mailbox %u exited before finishing ticket %llu", mb,
                       static_cast<unsigned long long>(t));
         }
       }
       _mm_pause();
     }
-    const uint32_t code = LKW_CODE(w);
-    if (code == LKW_FROM_ERROR) fault = true;
-    sum += __atomic_load_n(&st->partial, __ATOMIC_RELAXED);
-    const uint64_t tp = __atomic_load_n(&st->t_pick, __ATOMIC_RELAXED);
-    const uint64_t td = __atomic_load_n(&st->t_done, __ATOMIC_RELAXED);
-    pmin = std::min(pmin, tp);
-    pmax = std::max(pmax, tp);
-    dmin = std::min(dmin, td);
-    dmax = std::max(dmax, td);
+    if (s.code == LKW_FROM_ERROR) fault = true;
+    sum += s.partial;
+    pmin = std::min(pmin, s.t_pick);
+    pmax = std::max(pmax, s.t_pick);
+    dmin = std::min(dmin, s.t_done);
+    dmax = std::max(dmax, s.t_done);
   }
-  c->consumed[cluster] = t;
+  cs.consumed = t;
   if (info) {
     info->result = sum;
     info->t_pick_min = pmin;
@@ -512,15 +541,15 @@ int lk_poll(lk_ctx *c, uint32_t cluster, uint64_t t, int *done) {
   if (!c || !done) return fail(LK_EINVAL, "NULL argument");
   if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
   if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
-  if (t == 0 || t > c->posted[cluster]) return fail(LK_EINVAL, "ticket was not posted");
-  if (t <= c->consumed[cluster]) {
+  const ClusterSeq &cs = c->seqs[cluster];
+  if (t == 0 || t > cs.posted) return fail(LK_EINVAL, "ticket was not posted");
+  if (t <= cs.consumed) {
     *done = 1;
     return LK_OK;
   }
   int all = 1;
   for (uint32_t mb : c->cluster_mbox[cluster]) {
-    const uint64_t w = load_acquire(&slot_status(c, mb, t)->word);
-    if (!(LKW_SEQ(w) == t && LKW_CODE(w) != LKW_FROM_WORKING)) {
+    if (!read_status(slot_status(c, mb, t), t, nullptr)) {
       all = 0;
       break;
     }
@@ -545,18 +574,18 @@ int lk_dispose(lk_ctx *c) {
   // Let every posted item finish (bounded), then post THREAD_EXIT behind it.
   const auto drain_deadline = t0 + std::chrono::seconds(10);
   for (uint32_t k = 0; k < c->n_clusters; ++k) {
-    const uint64_t t = c->posted[k];
+    const uint64_t t = c->seqs[k].posted;
     for (uint32_t mb : c->cluster_mbox[k]) {
-      if (t > c->consumed[k]) {
-        lkw_status *st = slot_status(c, mb, t);
-        while (!(LKW_SEQ(load_acquire(&st->word)) == t && LKW_CODE(load_acquire(&st->word)) != LKW_FROM_WORKING)) {
+      if (t > c->seqs[k].consumed) {
+        const lkw_status *st = slot_status(c, mb, t);
+        while (!read_status(st, t, nullptr)) {
           if (exited_code(worker_code(c, mb)) || clk::now() > drain_deadline) break;
           _mm_pause();
         }
       }
       if (!exited_code(worker_code(c, mb))) post_cmd(c, mb, t + 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
     }
-    c->consumed[k] = t;
+    c->seqs[k].consumed = t;
   }
   if (!join_kernel(c, 5.0 + idle_ms / 1000.0)) {
     c->state = POISONED;
@@ -568,9 +597,16 @@ int lk_dispose(lk_ctx *c) {
     const hipError_t e = hipMemcpy(c->host_log.data(), c->d_log, sizeof(lkw_log) * c->host_log.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) c->host_log.clear();
   }
-  // Worker records survive for lk_get_info: keep a copy of the exit codes.
+  // Worker records survive for lk_get_info: keep a copy of the exit codes and the span
+  // from the first boot to the last exit on the device wall clock.
   uint32_t exited = 0;
-  for (uint32_t m = 0; m < c->n_workers; ++m) exited += exited_code(worker_code(c, m));
+  uint64_t boot_min = ~0ull, exit_max = 0;
+  for (uint32_t m = 0; m < c->n_workers; ++m) {
+    exited += exited_code(worker_code(c, m));
+    boot_min = std::min(boot_min, __atomic_load_n(&c->wrec[m].t_boot, __ATOMIC_RELAXED));
+    exit_max = std::max(exit_max, __atomic_load_n(&c->wrec[m].t_exit, __ATOMIC_RELAXED));
+  }
+  if (exit_max > boot_min) c->device_span_ms = static_cast<double>(exit_max - boot_min) * 1e3 / static_cast<double>(c->wall_hz);
   c->exited_at_dispose = exited;
   release_gpu(c);
   c->state = DISPOSED;
@@ -606,6 +642,7 @@ int lk_get_info(lk_ctx *c, lk_info *info) {
   info->init_ms = c->init_ms;
   info->dispose_ms = c->dispose_ms;
   info->kernel_ms = c->kernel_ms;
+  info->device_span_ms = c->device_span_ms;
   return LK_OK;
 }
 

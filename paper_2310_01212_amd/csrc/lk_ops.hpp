@@ -14,6 +14,14 @@
  * Reductions: per-thread int64 partials, a wave64 butterfly with __shfl_xor, then one
  * LDS slot per wave summed by thread 0.  Integer addition is associative, so the
  * result is exact whatever the order.
+ *
+ * Output stores go through a store policy:
+ *   CachedStore  ordinary stores (the per-launch kernels: the end-of-kernel release
+ *                writes the L2 back);
+ *   SystemStore  system-coherent stores (sc0 sc1), written through the XCD's L2 to
+ *                memory.  The persistent worker uses them so that publishing a completion
+ *                needs only a drain of its own stores, not a writeback of the whole L2
+ *                shared with the 31 other workers of its XCD.
  */
 #ifndef LK_OPS_HPP
 #define LK_OPS_HPP
@@ -60,8 +68,39 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *s_red, uint
 
 __device__ __forceinline__ uint32_t affine(uint32_t a, uint32_t x, uint32_t b) { return a * x + b; }
 
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+struct CachedStore {
+  template <typename T>
+  __device__ static __forceinline__ void put(T *p, T v) { *p = v; }
+  __device__ static __forceinline__ void put(u32x4 *p, u32x4 v) { __builtin_nontemporal_store(v, p); }
+};
+
+struct SystemStore {
+  __device__ static __forceinline__ void put(int4 *p, int4 v) {
+    const i32x4 w = {v.x, v.y, v.z, v.w};
+    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(w) : "memory");
+  }
+  __device__ static __forceinline__ void put(float4 *p, float4 v) {
+    const i32x4 w = {__float_as_int(v.x), __float_as_int(v.y), __float_as_int(v.z), __float_as_int(v.w)};
+    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(w) : "memory");
+  }
+  __device__ static __forceinline__ void put(u32x4 *p, u32x4 v) {
+    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  }
+  __device__ static __forceinline__ void put(int32_t *p, int32_t v) {
+    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  }
+  __device__ static __forceinline__ void put(uint32_t *p, uint32_t v) {
+    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  }
+  __device__ static __forceinline__ void put(float *p, float v) {
+    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(__float_as_int(v)) : "memory");
+  }
+};
+
 // int32 affine map modulo 2^32 and/or int64 sum.  STORE=false gives SUM_I32_I64 (a=1, b=0).
-template <bool STORE>
+template <bool STORE, class St>
 __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int32_t *__restrict__ y,
                                               uint64_t n, uint32_t a, uint32_t b, uint64_t nt) {
   constexpr int U = 4;
@@ -75,7 +114,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
     if (head > n) head = n;
     if (tid < head) {
       const uint32_t v = affine(a, static_cast<uint32_t>(x[tid]), b);
-      if (STORE) y[tid] = static_cast<int32_t>(v);
+      if (STORE) St::put(y + tid, static_cast<int32_t>(v));
       acc += static_cast<int32_t>(v);
     }
     const int4 *__restrict__ xv = reinterpret_cast<const int4 *>(x + head);
@@ -93,7 +132,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
         o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].y), b));
         o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].z), b));
         o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].w), b));
-        if (STORE) yv[k + u * nt] = o;
+        if (STORE) St::put(yv + k + u * nt, o);
         acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
                static_cast<int64_t>(o.w);
       }
@@ -105,7 +144,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
       o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
       o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
       o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
-      if (STORE) yv[k] = o;
+      if (STORE) St::put(yv + k, o);
       acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
              static_cast<int64_t>(o.w);
     }
@@ -113,7 +152,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
   }
   for (uint64_t i = done + tid; i < n; i += nt) {
     const uint32_t v = affine(a, static_cast<uint32_t>(x[i]), b);
-    if (STORE) y[i] = static_cast<int32_t>(v);
+    if (STORE) St::put(y + i, static_cast<int32_t>(v));
     acc += static_cast<int32_t>(v);
   }
   return acc;
@@ -129,6 +168,7 @@ __device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
 }
 
 // y[i] = fma(alpha, x[i], y[i]) in place.
+template <class St>
 __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__restrict__ y, uint64_t n,
                                       float alpha, uint64_t nt) {
   constexpr int U = 4;
@@ -138,7 +178,7 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
   if (xa == (reinterpret_cast<uintptr_t>(y) & 15u)) {
     uint64_t head = ((16u - xa) & 15u) >> 2;
     if (head > n) head = n;
-    if (tid < head) y[tid] = __builtin_fmaf(alpha, x[tid], y[tid]);
+    if (tid < head) St::put(y + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
     const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
     float4 *__restrict__ yv = reinterpret_cast<float4 *>(y + head);
     const uint64_t nv = (n - head) >> 2;
@@ -151,15 +191,16 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
         ry[u] = yv[k + u * nt];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) yv[k + u * nt] = fma4(alpha, rx[u], ry[u]);
+      for (int u = 0; u < U; ++u) St::put(yv + k + u * nt, fma4(alpha, rx[u], ry[u]));
     }
-    for (; k < nv; k += nt) yv[k] = fma4(alpha, xv[k], yv[k]);
+    for (; k < nv; k += nt) St::put(yv + k, fma4(alpha, xv[k], yv[k]));
     done = head + nv * 4;
   }
-  for (uint64_t i = done + tid; i < n; i += nt) y[i] = __builtin_fmaf(alpha, x[i], y[i]);
+  for (uint64_t i = done + tid; i < n; i += nt) St::put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
 }
 
 // out[i] = in[i] as raw 32-bit words.
+template <class St>
 __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                        uint64_t n, uint64_t nt) {
   constexpr int U = 8;
@@ -169,7 +210,7 @@ __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t
   if (ia == (reinterpret_cast<uintptr_t>(out) & 15u)) {
     uint64_t head = ((16u - ia) & 15u) >> 2;
     if (head > n) head = n;
-    if (tid < head) out[tid] = in[tid];
+    if (tid < head) St::put(out + tid, in[tid]);
     const u32x4 *__restrict__ iv = reinterpret_cast<const u32x4 *>(in + head);
     u32x4 *__restrict__ ov = reinterpret_cast<u32x4 *>(out + head);
     const uint64_t nv = (n - head) >> 2;
@@ -179,12 +220,12 @@ __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t
 #pragma unroll
       for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(iv + k + u * nt);
 #pragma unroll
-      for (int u = 0; u < U; ++u) __builtin_nontemporal_store(r[u], ov + k + u * nt);
+      for (int u = 0; u < U; ++u) St::put(ov + k + u * nt, r[u]);
     }
-    for (; k < nv; k += nt) ov[k] = iv[k];
+    for (; k < nv; k += nt) St::put(ov + k, iv[k]);
     done = head + nv * 4;
   }
-  for (uint64_t i = done + tid; i < n; i += nt) out[i] = in[i];
+  for (uint64_t i = done + tid; i < n; i += nt) St::put(out + i, in[i]);
 }
 
 // Compute-only loop (the paper's benchmark item, Sec. 3): `iters` dependent integer
@@ -199,20 +240,21 @@ __device__ __forceinline__ void spin(uint32_t iters) {
 // explicitly: the persistent worker is dispatched without the runtime's implicit kernel
 // arguments); returns the slice's int64 result in thread 0 (0 elsewhere and for ops
 // without a result).  Ends with a barrier.
+template <class St>
 __device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uint32_t nt) {
   int64_t acc = 0;
   switch (s.op) {
     case 1:  // AFFINE_SUM_I32
-      acc = affine_sum<true>(static_cast<const int32_t *>(s.in), static_cast<int32_t *>(s.out), s.n, s.a, s.b, nt);
+      acc = affine_sum<true, St>(static_cast<const int32_t *>(s.in), static_cast<int32_t *>(s.out), s.n, s.a, s.b, nt);
       break;
     case 2:  // SUM_I32_I64
-      acc = affine_sum<false>(static_cast<const int32_t *>(s.in), nullptr, s.n, 1u, 0u, nt);
+      acc = affine_sum<false, St>(static_cast<const int32_t *>(s.in), nullptr, s.n, 1u, 0u, nt);
       break;
     case 3:  // SAXPY_F32
-      saxpy(static_cast<const float *>(s.in), static_cast<float *>(s.out), s.n, s.alpha, nt);
+      saxpy<St>(static_cast<const float *>(s.in), static_cast<float *>(s.out), s.n, s.alpha, nt);
       break;
     case 4:  // COPY_F32
-      copy32(static_cast<const uint32_t *>(s.in), static_cast<uint32_t *>(s.out), s.n, nt);
+      copy32<St>(static_cast<const uint32_t *>(s.in), static_cast<uint32_t *>(s.out), s.n, nt);
       break;
     case 5:  // SPIN
       spin(s.a);

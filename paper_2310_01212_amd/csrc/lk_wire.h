@@ -8,12 +8,17 @@
  * carries a sequence number beside its code, word = (seq << 8) | code, which makes the
  * handshake two-phase and lets one slot be reused without a reset through NOP.
  *
- * Command slot (64 bytes, one PCIe read): the worker reads the whole slot in a single
- * 64-byte load and accepts it only if word 0 holds the expected (seq, code) AND every
- * other word carries the low 16 bits of that seq in its top 16 bits.  Each word is
- * written by one aligned 8-byte host store and read by one 8-byte device load, so a
- * slot whose eight tags all match was written entirely for this seq: the descriptor
- * arrives with its doorbell, with no second dependent read over PCIe.
+ * Both directions move whole 64-byte records in one PCIe transaction:
+ *   - command slot (to_GPU): the worker reads the slot with one 64-byte load and accepts
+ *     it only if word 0 holds the expected (seq, code) AND every other word carries the
+ *     low 16 bits of that seq in its top 16 bits.  Each word is written by one aligned
+ *     8-byte host store and read by one 8-byte device load, so a slot whose eight tags
+ *     all match was written entirely for this seq: the descriptor arrives with its
+ *     doorbell, with no second dependent read;
+ *   - status slot (from_GPU): the worker writes the whole record with one 64-byte store
+ *     (one full-line posted write, no partial-line merge on the host side), tagged the
+ *     same way; the host accepts it once word 0 shows the seq and all tags match.
+ * Rings are padded so that every mailbox starts on its own 128-byte boundary.
  */
 #ifndef LK_WIRE_H
 #define LK_WIRE_H
@@ -59,15 +64,23 @@ typedef struct lkw_cmd {
   uint64_t w[LKW_CMD_WORDS];
 } lkw_cmd; /* 64 bytes */
 
-/* Status slot, written by the worker: payload first, word last (release). */
+/* Status slot: 8 tagged words written by one 64-byte device store. */
+enum {
+  LKW_S_WORD = 0,     /* (seq << 8) | from_GPU code */
+  LKW_S_PART_LO = 1,  /* low 32 bits of this member's int64 result */
+  LKW_S_PART_HI = 2,  /* high 32 bits */
+  LKW_S_T_PICK = 3,   /* device wall clock at pickup (48 bits) */
+  LKW_S_T_DONE = 4,   /* device wall clock before publication (48 bits) */
+  LKW_S_HWID = 5,     /* HW_ID (32 bits) | XCC_ID << 32 */
+  LKW_S_WORDS = 8     /* words 6..7: tag only */
+};
+
 typedef struct lkw_status {
-  uint64_t word;     /* (seq << 8) | from_GPU code */
-  int64_t partial;   /* this member's int64 result */
-  uint64_t t_pick;   /* device wall clock at pickup */
-  uint64_t t_done;   /* device wall clock before publication */
-  uint32_t hwid, xcc;
-  uint64_t pad[3];
+  uint64_t w[LKW_S_WORDS];
 } lkw_status; /* 64 bytes */
+
+/* Ring stride in slots: depth rounded up to an even count (128-byte multiple). */
+#define LKW_RING_STRIDE(depth) (((depth) + 1u) & ~1u)
 
 /* Per-worker boot/liveness record, written by the worker. */
 typedef struct lkw_worker {
@@ -77,7 +90,8 @@ typedef struct lkw_worker {
   uint32_t pad0;
   uint64_t heartbeat; /* bumped while idle-polling */
   uint64_t t_boot;    /* device wall clock at boot */
-  uint64_t pad[11];
+  uint64_t t_exit;    /* device wall clock when the worker left the loop */
+  uint64_t pad[10];
 } lkw_worker; /* 128 bytes */
 
 /* Device log record (device memory). */
@@ -91,8 +105,8 @@ typedef struct lkw_log {
 
 /* Kernel parameter block, passed by value. */
 typedef struct lkw_params {
-  lkw_cmd *cmd;          /* [n_workers][depth], host-coherent */
-  lkw_status *status;    /* [n_workers][depth], host-coherent */
+  lkw_cmd *cmd;          /* [n_workers][LKW_RING_STRIDE(depth)], host-coherent */
+  lkw_status *status;    /* [n_workers][LKW_RING_STRIDE(depth)], host-coherent */
   lkw_worker *workers;   /* [n_workers], host-coherent */
   lkw_log *log;          /* [n_workers][log_cap], device memory, or null */
   uint32_t *claim;       /* device counter: mailbox claim at boot */

@@ -10,8 +10,11 @@
  *   3. on a new command, takes one system-scope acquire and broadcasts the descriptor to
  *      the workgroup through LDS;
  *   4. runs the work item over its slice with all its waves (lk_ops.hpp);
- *   5. drains every wave's stores, then lane 0 publishes THREAD_FINISHED with one
- *      system-scope release (Sec. 2.4: the master thread owns the two mailboxes);
+ *   5. every wave drains its own output stores, which are written through to memory
+ *      (SystemStore, lk_ops.hpp); after a barrier wave 0 publishes THREAD_FINISHED as one
+ *      64-byte status record (Sec. 2.4: the master thread owns the two mailboxes).
+ *      Because no output line is left dirty in the L2, publication needs no L2
+ *      writeback, which would otherwise serialise the 32 workers of an XCD;
  *   6. loops until THREAD_EXIT (Table 1) or the watchdog.
  * It is compiled to a standalone code object and uses no implicit kernel argument: the
  * thread count travels in lkw_params.
@@ -26,11 +29,31 @@
 
 using namespace lkdev;
 
+// Lanes 0..7 of wave 0 write the eight tagged words of a status record in one store.
+__device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uint32_t code, int64_t partial,
+                                               uint64_t t_pick, uint64_t t_done, uint32_t hw, uint32_t xcc) {
+  const uint32_t lane = threadIdx.x;
+  const uint64_t tag = LKW_TAG(seq);
+  const uint64_t up = static_cast<uint64_t>(partial);
+  uint64_t v = tag;
+  switch (lane) {
+    case LKW_S_WORD: v = LKW_WORD(seq, code); break;
+    case LKW_S_PART_LO: v = tag | (up & 0xffffffffull); break;
+    case LKW_S_PART_HI: v = tag | (up >> 32); break;
+    case LKW_S_T_PICK: v = tag | (t_pick & LKW_PAYLOAD_MASK); break;
+    case LKW_S_T_DONE: v = tag | (t_done & LKW_PAYLOAD_MASK); break;
+    case LKW_S_HWID: v = tag | hw | (static_cast<uint64_t>(xcc & 0xffffu) << 32); break;
+    default: break;
+  }
+  st_sys(&st->w[lane], v);
+}
+
 // ----------------------------------------------------------------------------- worker
 extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   extern __shared__ uint64_t lds_reserve[];  // only holds the CU: one worker per CU
   __shared__ uint64_t s_w[LKW_CMD_WORDS];
-  __shared__ uint64_t s_t_pick;
+  __shared__ uint64_t s_t_pick, s_t_done;
+  __shared__ int64_t s_partial;
   __shared__ uint32_t s_mb, s_go, s_hw, s_xcc;
   __shared__ int64_t s_red[lkops::kMaxWaves];
   (void)lds_reserve;
@@ -54,8 +77,9 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   const uint32_t m = s_mb;
   if (m >= p.n_workers) return;
 
-  lkw_cmd *ring = p.cmd + static_cast<uint64_t>(m) * p.depth;
-  lkw_status *sring = p.status + static_cast<uint64_t>(m) * p.depth;
+  const uint64_t stride = LKW_RING_STRIDE(p.depth);
+  lkw_cmd *ring = p.cmd + m * stride;
+  lkw_status *sring = p.status + m * stride;
   lkw_worker *wr = p.workers + m;
   uint64_t seq = 0;  // last sequence number executed by this worker
 
@@ -101,23 +125,26 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     __syncthreads();
 
     if (s_go != 0) {  // idle watchdog: leave the loop
-      if (tid == 0) st_sys_release(&wr->word, LKW_WORD(seq, LKW_FROM_TIMEDOUT));
+      if (tid == 0) {
+        st_sys(&wr->t_exit, wall_clock64());
+        st_sys_release(&wr->word, LKW_WORD(seq, LKW_FROM_TIMEDOUT));
+      }
       return;
     }
     const uint64_t w0 = s_w[LKW_W_DOORBELL];
     const uint32_t code = LKW_CODE(w0);
     if (code == LKW_TO_EXIT) {  // THREAD_EXIT (Table 1)
+      if (tid < LKW_S_WORDS) publish_status(sring + slot, want, LKW_FROM_EXITED, 0, s_t_pick, s_t_pick, s_hw, s_xcc);
       if (tid == 0) {
-        lkw_status *st = sring + slot;
-        st_sys(&st->t_pick, s_t_pick);
-        st_sys_release(&st->word, LKW_WORD(want, LKW_FROM_EXITED));
+        drain_wave_memory();
+        st_sys(&wr->t_exit, wall_clock64());
         st_sys_release(&wr->word, LKW_WORD(want, LKW_FROM_EXITED));
       }
       return;
     }
 
     if (tid == 0 && (p.flags & LKW_K_REPORT_WORKING))
-      st_sys(&sring[slot].word, LKW_WORD(want, LKW_FROM_WORKING));
+      st_sys(&sring[slot].w[LKW_S_WORD], LKW_WORD(want, LKW_FROM_WORKING));
 
     uint32_t reply = LKW_FROM_FINISHED;
     lkops::Slice s;
@@ -135,35 +162,30 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     } else {
       reply = LKW_FROM_ERROR;
     }
-    const int64_t partial = lkops::run_slice(s, s_red, p.threads);
+    const int64_t partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
 
-    drain_wave_memory();
-    __syncthreads();
-
-    // ---- complete: one system-scope release orders the whole workgroup's output
-    // (drained above and ordered by the barrier) before the FINISHED word.
+    // ---- complete.  Thread 0 writes the optional per-member partial and the log record
+    // with system-coherent stores; every wave then waits until all of its stores have
+    // been acknowledged, and the barrier orders all of that before the status record.
     if (tid == 0) {
       const uint64_t t_done = wall_clock64();
+      s_t_done = t_done;
+      s_partial = partial;
       int64_t *aux = reinterpret_cast<int64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
-      if (aux) *aux = partial;
+      if (aux) st_sys_i64(aux, partial);
       if (p.log) {
         lkw_log *e = p.log + static_cast<uint64_t>(m) * p.log_cap + (seq % p.log_cap);
-        e->seq = static_cast<uint32_t>(want);
-        e->code = static_cast<uint16_t>(code);
-        e->mailbox = static_cast<uint16_t>(m);
-        e->xcc = s_xcc;
-        e->hwid = s_hw;
-        e->t_pick = s_t_pick;
-        e->t_done = t_done;
+        const uint64_t head = static_cast<uint64_t>(static_cast<uint32_t>(want)) |
+                              (static_cast<uint64_t>(code & 0xffffu) << 32) | (static_cast<uint64_t>(m & 0xffffu) << 48);
+        st_sys(reinterpret_cast<uint64_t *>(e) + 0, head);
+        st_sys(reinterpret_cast<uint64_t *>(e) + 1, static_cast<uint64_t>(s_xcc) | (static_cast<uint64_t>(s_hw) << 32));
+        st_sys(&e->t_pick, s_t_pick);
+        st_sys(&e->t_done, t_done);
       }
-      lkw_status *st = sring + slot;
-      st_sys_i64(&st->partial, partial);
-      st_sys(&st->t_pick, s_t_pick);
-      st_sys(&st->t_done, t_done);
-      st_sys_u32(&st->hwid, s_hw);
-      st_sys_u32(&st->xcc, s_xcc);
-      st_sys_release(&st->word, LKW_WORD(want, reply));
     }
+    drain_wave_memory();
+    __syncthreads();
+    if (tid < LKW_S_WORDS) publish_status(sring + slot, want, reply, s_partial, s_t_pick, s_t_done, s_hw, s_xcc);
     seq = want;
   }
 }

@@ -66,7 +66,8 @@ class Info(ctypes.Structure):
                 ("cu_count", ctypes.c_uint32), ("xcd_count", ctypes.c_uint32),
                 ("state", ctypes.c_uint32), ("workers_exited", ctypes.c_uint32),
                 ("wall_clock_hz", ctypes.c_uint64), ("init_ms", ctypes.c_double),
-                ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("device_span_ms", ctypes.c_double)]
 
 
 class LogEntry(ctypes.Structure):
@@ -121,7 +122,7 @@ def lib():
         "lk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "lk_last_error": (ctypes.c_char_p, []),
         "lkb_serial": (ctypes.c_int, [P, U32, P, U64, I64, P, P, P, P]),
-        "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD]),
+        "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD, P]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
@@ -337,18 +338,24 @@ class Context:
         _check(rc, "lkb_serial")
         return res, lat, trig, comp
 
-    def run_lanes(self, lane_cluster, items, in_flight=1, threads=8, timeout=10.0):
-        """items: (n_lanes, items_per_lane) ITEM_DTYPE array.  Returns (results, lat_us, elapsed_s)."""
+    def run_lanes(self, lane_cluster, items, in_flight=1, threads=8, timeout=10.0, with_info=False):
+        """items: (n_lanes, items_per_lane) ITEM_DTYPE array.
+        Returns (results, lat_us, elapsed_s), plus the per-item COMPLETION_DTYPE array when
+        with_info is set."""
         items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
         lanes, per = items.shape
         lc = np.ascontiguousarray(lane_cluster, dtype=np.uint32)
         assert lc.size == lanes
         res = np.zeros((lanes, per), np.int64)
         lat = np.zeros((lanes, per), np.float64)
+        info = np.zeros((lanes, per), COMPLETION_DTYPE) if with_info else None
         el = ctypes.c_double()
         rc = lib().lkb_lanes(self._h, _np_ptr(lc), lanes, _np_ptr(items), per, in_flight, threads,
-                             int(timeout * 1e9), _np_ptr(res), _np_ptr(lat), ctypes.byref(el))
+                             int(timeout * 1e9), _np_ptr(res), _np_ptr(lat), ctypes.byref(el),
+                             _np_ptr(info))
         _check(rc, "lkb_lanes")
+        if with_info:
+            return res, lat, el.value, info
         return res, lat, el.value
 
 
