@@ -51,6 +51,37 @@ def lat_summary(v):
             "jitter": round(pct(v, 1.0) - pct(v, 0.0), 3)}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lk_worker_allcu_saxpy_traffic.md")
+WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h"]
+
+
+def worker_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in WORKER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_01212_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_item(n):
+    """HBM bytes per item of the worker kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration);
+    None when the summary is missing, was taken for another item size, or the worker's
+    sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    import re
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("worker_source_digest") != worker_source_digest() or d.get("n") != n:
+        return None
+    return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,7 +90,8 @@ def parse():
     ap.add_argument("--items-per-step", type=int, default=1000, help="items per mailbox per step")
     ap.add_argument("--n", type=int, default=16384, help="elements per item")
     ap.add_argument("--depth", type=int, default=1, help="ring slots per mailbox (in flight)")
-    ap.add_argument("--threads", type=int, default=8, help="host feeder threads")
+    ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
+                    help="host feeder threads (one producer per mailbox)")
     ap.add_argument("--poll-sleep", type=int, default=0)
     ap.add_argument("--baseline-steps", type=int, default=1, help="steps timed for each baseline")
     ap.add_argument("--streams", type=int, default=4, help="HIP streams of the per-launch baseline")
@@ -67,6 +99,12 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=1000, help="items per mailbox in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=1024)
+    ap.add_argument("--workload", choices=["allcu", "isolation"], default="allcu",
+                    help="allcu: the headline all-CU workload; isolation: cluster 0 critical "
+                         "item every period beside streaming copies on the other XCDs")
+    ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
+    ap.add_argument("--period-us", type=float, default=1000.0)
+    ap.add_argument("--copy-mib", type=int, default=256, help="isolation: interference buffer size")
     return ap.parse_args()
 
 
@@ -78,7 +116,67 @@ def main():
               "the dispatch path has no multi-GPU component; see DESIGN.md for how it would shard.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "isolation":
+        return bench_isolation(args)
+    return bench_allcu(args)
 
+
+def bench_isolation(args):
+    """Cluster isolation: 8 clusters = 8 XCDs; cluster 0 gets a critical int32 affine +
+    int64 sum item over 262,144 elements every period, released by a host busy-wait, while
+    clusters 1-7 copy private fp32 buffers back-to-back (interference on) or idle-poll
+    (interference off)."""
+    import torch
+    import oracle
+    from paper_2310_01212_amd import lk, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lk.lib()
+    oracle.build(force=False)
+    dev = torch.device("cuda:0")
+    P = args.periods
+    log(f"isolation: generating inputs ({P} periods, {args.copy_mib} MiB copies)")
+    xh, AB = workloads.isolation(periods=P)
+    x = torch.from_numpy(xh).to(dev)
+    y = torch.zeros_like(x)
+    elems = (args.copy_mib << 20) // 4
+    srcs = [workloads.isolation_copy_source_device(c, elems, dev) for c in range(1, 8)]
+    dsts = [torch.empty_like(s) for s in srcs]
+    torch.cuda.synchronize()
+    crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, x.data_ptr(), y.data_ptr(), AB[:, 0], AB[:, 1])
+    bg = lk.make_items(lk.OP_COPY_F32, elems, [s.data_ptr() for s in srcs], [d.data_ptr() for d in dsts])
+    out = {"metric": "critical-item latency p50/p99/p99.9/max (µs) under cross-XCD interference",
+           "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "int32/int64 (critical), f32 copy",
+           "data": "synthetic (seeded)", "steps": P, "warmup": 0, "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": "cluster isolation: 8 clusters = 8 XCDs; cluster 0 critical affine+sum over "
+                                  f"{xh.size} int32 every {args.period_us} us; clusters 1-7 copy private "
+                                  f"{args.copy_mib} MiB fp32 buffers back-to-back", "periods": P}}
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=600000) as ctx:
+        ncl = ctx.info()["n_clusters"]
+        assert ncl == 8, f"expected 8 XCD clusters, got {ncl}"
+        ctx.run_isolation(0, crit[:200], args.period_us * 1e-6, [], bg[:0])  # warm-up, untimed
+        for name, bgc in (("off", []), ("on", list(range(1, 8)))):
+            log(f"isolation: interference {name}")
+            r = ctx.run_isolation(0, crit, args.period_us * 1e-6, bgc, bg[:len(bgc)])
+            wall = 1e8
+            span = (r["info"]["t_done_max"] - r["info"]["t_pick_min"]) / wall * 1e6
+            v = {"latency_us": lat_summary(r["lat_us"]), "device_span_us": lat_summary(span),
+                 "release_lateness_us": lat_summary(r["late_us"]), "elapsed_s": round(r["elapsed_s"], 3)}
+            if bgc:
+                copied = float(r["bg_done"].sum()) * 2 * (elems * 4)
+                v["interference_copy_gbps"] = round(copied / r["elapsed_s"] / 1e9, 1)
+                v["interference_items"] = int(r["bg_done"].sum())
+            # spot parity: sums of 20 sampled periods against the oracle
+            idx = np.linspace(0, P - 1, 20).astype(int)
+            bad = sum(int(r["results"][k] != oracle.affine_sum_i32(xh, int(AB[k, 0]), int(AB[k, 1]))[1]) for k in idx)
+            v["sampled_sum_mismatches"] = bad
+            out[name] = v
+    out["value"] = out["on"]["latency_us"]["max"]
+    out["ms_per_step"] = round(out["on"]["elapsed_s"] * 1e3 / P, 4)
+    print(json.dumps(out), flush=True)
+
+
+def bench_allcu(args):
     import torch
     from paper_2310_01212_amd import lk, workloads
 
@@ -105,8 +203,12 @@ def main():
     x_addr = x_d.data_ptr() + li * n * 4
     y_addr = y_d.data_ptr() + li * n * 4
 
+    # every step's descriptors are built before any timed region
+    steps_items = [lk.make_items(lk.OP_SAXPY_F32, n, x_addr, y_addr, alpha=A[:, s * per:(s + 1) * per])
+                   for s in range(args.warmup + args.steps)]
+
     def step_items(s):
-        return lk.make_items(lk.OP_SAXPY_F32, n, x_addr, y_addr, alpha=A[:, s * per:(s + 1) * per])
+        return steps_items[s]
 
     bytes_per_item = 12 * n  # SAXPY: 8n read + 4n write
 
@@ -130,7 +232,12 @@ def main():
     lat_all = np.concatenate([l.ravel() for l in lat_all])
     timed_items = lanes * per * args.steps
     items_per_s = timed_items / elapsed
-    kernel_ms = info["kernel_ms"]
+    # duration of the single worker dispatch: packet-processor timestamps, or (when a tool
+    # intercepting the queue hides them) the span from first boot to last exit on the
+    # device wall clock
+    kernel_ms, kernel_clock = info["kernel_ms"], "dispatch timestamps"
+    if kernel_ms <= 0:
+        kernel_ms, kernel_clock = info["device_span_ms"], "device wall clock"
     session_items = lanes * per * (args.warmup + args.steps)
     achieved_gbps = session_items * bytes_per_item / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
     log(f"persistent: {items_per_s:,.0f} items/s, p50 {pct(lat_all, .5):.2f} us, kernel {kernel_ms:.1f} ms")
@@ -160,8 +267,13 @@ def main():
     # ---------------- roofline of the worker kernel (one launch = the session)
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": HBM_PEAK_GBPS,
                           "unit": "GB/s", "frac": round(achieved_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
-                          "kernel": "lk_worker", "kernel_ms": round(kernel_ms, 3),
+                          "kernel": "lk_worker", "kernel_ms": round(kernel_ms, 3), "kernel_clock": kernel_clock,
+                          "items_per_launch": session_items, "algorithmic_bytes_per_item": bytes_per_item,
                           "algorithmic_bytes": session_items * bytes_per_item}
+    tr = traffic_per_item(n)
+    if tr is not None:
+        result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
+        result["roofline"]["traffic_source"] = tr["source"]
 
     # ---------------- baselines on the same workload
     if not args.skip_baselines:

@@ -8,6 +8,8 @@
  * timed region:
  *   - lkb_serial        Trigger + Wait per item on a running context, item after item;
  *   - lkb_lanes         many clusters fed back-to-back by host threads;
+ *   - lkb_isolation     a periodic critical item on one cluster beside streaming
+ *                       interference on the others;
  *   - lkb_launch_serial one ordinary kernel launch per item (the paper's spawn path),
  *                       optionally through a single-node hipGraph relaunched per item;
  *   - lkb_launch_lanes  the lanes workload with one launch (or graph launch) per item;
@@ -52,6 +54,17 @@ LK_API int lkb_serial(lk_ctx *c, uint32_t cluster, const lkb_item *items, uint64
 LK_API int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const lkb_item *items,
               uint64_t items_per_lane, uint32_t in_flight, uint32_t n_threads, int64_t timeout_ns,
               int64_t *results, double *lat_us, double *elapsed_s, lk_completion *info);
+
+/* Cluster isolation: a critical item is released on crit_cluster every period_ns (host
+ * busy-wait to t0 + k * period, item k = crit[k]), submitted and waited for, while each
+ * cluster bg_clusters[i] runs bg[i] back-to-back from its own host thread (re-posted as
+ * soon as it completes).  Per period: lat_us = release to lk_wait return, late_us =
+ * release to submit (host lateness), results and info (device-side timing); bg_done[i] =
+ * background items completed; *elapsed_s = run time.  The calling thread is pinned to
+ * the last host core for the run and background threads to the others. */
+LK_API int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64_t periods, int64_t period_ns,
+                  const uint32_t *bg_clusters, uint32_t n_bg, const lkb_item *bg, int64_t *results, double *lat_us,
+                  double *late_us, lk_completion *info, uint64_t *bg_done, double *elapsed_s);
 
 #define LKB_COMPLETE_SYNC 0u  /* completion observed by hipStreamSynchronize */
 #define LKB_COMPLETE_FLAG 1u  /* completion observed through a host-coherent word the

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime_api.h>
 #include <immintrin.h>
 
+#include <pthread.h>
+#include <sched.h>
+
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -239,6 +242,84 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
   if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
   const int rc = error.load();
   if (rc) return bfail(rc, "lanes run failed: %s", lk_strerror(rc));
+  return LK_OK;
+}
+
+int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64_t periods, int64_t period_ns,
+                  const uint32_t *bg_clusters, uint32_t n_bg, const lkb_item *bg, int64_t *results, double *lat_us,
+                  double *late_us, lk_completion *info, uint64_t *bg_done, double *elapsed_s) {
+  if (!c || (!crit && periods) || (!bg && n_bg) || (!bg_clusters && n_bg)) return bfail(LK_EINVAL, "NULL argument");
+  if (period_ns <= 0 || n_bg > 64) return bfail(LK_EINVAL, "period_ns > 0 and n_bg <= 64");
+  for (uint32_t i = 0; i < n_bg; ++i)
+    if (bg_clusters[i] == crit_cluster) return bfail(LK_EINVAL, "background cluster %u is the critical one", crit_cluster);
+  std::atomic<bool> stop{false};
+  std::atomic<int> bg_error{0};
+  std::vector<uint64_t> counts(n_bg, 0);
+  const unsigned ncpu = std::thread::hardware_concurrency();
+  // Background streams: one host thread per interfering cluster re-posts its item as soon
+  // as the previous one completes.
+  auto bg_worker = [&](uint32_t i) {
+    if (ncpu > n_bg + 1) {  // keep the critical thread's core (the last one) free
+      cpu_set_t set;
+      CPU_ZERO(&set);
+      CPU_SET(i % (ncpu - 1), &set);
+      pthread_setaffinity_np(pthread_self(), sizeof set, &set);
+    }
+    const lk_desc d = to_desc(bg[i]);
+    while (!stop.load(std::memory_order_relaxed)) {
+      uint64_t t;
+      int rc = lk_submit(c, bg_clusters[i], &d, reinterpret_cast<const void *>(bg[i].in),
+                         reinterpret_cast<void *>(bg[i].out), &t);
+      if (rc == LK_OK) rc = lk_wait(c, bg_clusters[i], t, 30000000000ll, nullptr);
+      if (rc) {
+        bg_error.store(rc);
+        return;
+      }
+      ++counts[i];
+    }
+  };
+  std::vector<std::thread> th;
+  for (uint32_t i = 0; i < n_bg; ++i) th.emplace_back(bg_worker, i);
+
+  // Critical stream on the calling thread, pinned to the last core for the run: release
+  // k happens at t0 + k * period (busy-wait), then submit and wait.
+  cpu_set_t old_set;
+  const bool pinned = ncpu > n_bg + 1 && pthread_getaffinity_np(pthread_self(), sizeof old_set, &old_set) == 0;
+  if (pinned) {
+    cpu_set_t set;
+    CPU_ZERO(&set);
+    CPU_SET(ncpu - 1, &set);
+    pthread_setaffinity_np(pthread_self(), sizeof set, &set);
+  }
+  int rc = LK_OK;
+  const auto start = clk::now();
+  const auto t0 = start + std::chrono::milliseconds(20);  // let the interference ramp up
+  for (uint64_t k = 0; k < periods && rc == LK_OK; ++k) {
+    const auto release = t0 + std::chrono::nanoseconds(period_ns * static_cast<int64_t>(k));
+    while (clk::now() < release) _mm_pause();
+    const auto ts = clk::now();
+    const lk_desc d = to_desc(crit[k]);
+    uint64_t t;
+    rc = lk_submit(c, crit_cluster, &d, reinterpret_cast<const void *>(crit[k].in), reinterpret_cast<void *>(crit[k].out), &t);
+    if (rc) break;
+    lk_completion ci;
+    rc = lk_wait_info(c, crit_cluster, t, 5000000000ll, &ci);
+    const auto te = clk::now();
+    if (rc) break;
+    if (results) results[k] = ci.result;
+    if (lat_us) lat_us[k] = us_between(release, te);
+    if (late_us) late_us[k] = us_between(release, ts);
+    if (info) info[k] = ci;
+    if (bg_error.load()) rc = bg_error.load();
+  }
+  if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
+  stop.store(true);
+  for (auto &t : th) t.join();
+  if (pinned) pthread_setaffinity_np(pthread_self(), sizeof old_set, &old_set);
+  for (uint32_t i = 0; i < n_bg; ++i)
+    if (bg_done) bg_done[i] = counts[i];
+  if (!rc) rc = bg_error.load();
+  if (rc) return bfail(rc, "isolation run failed: %s (%s)", lk_strerror(rc), lk_last_error());
   return LK_OK;
 }
 

@@ -70,32 +70,59 @@ __device__ __forceinline__ uint32_t affine(uint32_t a, uint32_t x, uint32_t b) {
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
+// Elements per segment of a slice: every op walks its slice in segments of at most
+// 1 GiB, so that a 32-bit buffer offset always reaches the whole segment.
+constexpr uint64_t kSegmentElems = 1ull << 28;
+
+// Ordinary stores; the per-launch kernels rely on the end-of-kernel release.
 struct CachedStore {
+  __device__ __forceinline__ CachedStore(void *, uint64_t) {}
   template <typename T>
-  __device__ static __forceinline__ void put(T *p, T v) { *p = v; }
-  __device__ static __forceinline__ void put(u32x4 *p, u32x4 v) { __builtin_nontemporal_store(v, p); }
+  __device__ __forceinline__ void put(T *p, T v) const { *p = v; }
+  __device__ __forceinline__ void put(u32x4 *p, u32x4 v) const { __builtin_nontemporal_store(v, p); }
 };
 
+// System-coherent stores (cache policy sc0 sc1) through a buffer resource covering the
+// segment's output: written through the XCD's L2 to memory, tracked by the compiler's
+// wait-count bookkeeping like any other store, and dropped by the hardware range check
+// if an offset ever fell outside the segment.
 struct SystemStore {
-  __device__ static __forceinline__ void put(int4 *p, int4 v) {
-    const i32x4 w = {v.x, v.y, v.z, v.w};
-    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(w) : "memory");
+  static constexpr int kSysCoherent = 1 | 16;  // sc0 | sc1
+  __amdgpu_buffer_rsrc_t rsrc;
+  uintptr_t base;
+  __device__ __forceinline__ SystemStore(void *out, uint64_t bytes) {
+    // The segment base is the same in every lane; make that explicit so the resource
+    // lives in scalar registers.
+    const uint64_t b = reinterpret_cast<uint64_t>(out);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+    base = (static_cast<uint64_t>(hi) << 32) | lo;
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(bytes));
+    rsrc = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(base), 0, static_cast<int>(nb), 0x00020000);
   }
-  __device__ static __forceinline__ void put(float4 *p, float4 v) {
-    const i32x4 w = {__float_as_int(v.x), __float_as_int(v.y), __float_as_int(v.z), __float_as_int(v.w)};
-    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(w) : "memory");
+  __device__ __forceinline__ int off(const void *p) const {
+    return static_cast<int>(reinterpret_cast<uintptr_t>(p) - base);
   }
-  __device__ static __forceinline__ void put(u32x4 *p, u32x4 v) {
-    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  __device__ __forceinline__ void put(int4 *p, int4 v) const {
+    const u32x4 w = {static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y), static_cast<uint32_t>(v.z),
+                     static_cast<uint32_t>(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rsrc, off(p), 0, kSysCoherent);
   }
-  __device__ static __forceinline__ void put(int32_t *p, int32_t v) {
-    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  __device__ __forceinline__ void put(float4 *p, float4 v) const {
+    const u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rsrc, off(p), 0, kSysCoherent);
   }
-  __device__ static __forceinline__ void put(uint32_t *p, uint32_t v) {
-    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+  __device__ __forceinline__ void put(u32x4 *p, u32x4 v) const {
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, off(p), 0, kSysCoherent);
   }
-  __device__ static __forceinline__ void put(float *p, float v) {
-    asm volatile("global_store_dword %0, %1, off sc0 sc1" ::"v"(p), "v"(__float_as_int(v)) : "memory");
+  __device__ __forceinline__ void put(int32_t *p, int32_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(static_cast<uint32_t>(v), rsrc, off(p), 0, kSysCoherent);
+  }
+  __device__ __forceinline__ void put(uint32_t *p, uint32_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, off(p), 0, kSysCoherent);
+  }
+  __device__ __forceinline__ void put(float *p, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, off(p), 0, kSysCoherent);
   }
 };
 
@@ -104,6 +131,7 @@ template <bool STORE, class St>
 __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int32_t *__restrict__ y,
                                               uint64_t n, uint32_t a, uint32_t b, uint64_t nt) {
   constexpr int U = 4;
+  const St st(y, n * 4);
   const uint64_t tid = threadIdx.x;
   int64_t acc = 0;
   uint64_t done = 0;
@@ -114,7 +142,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
     if (head > n) head = n;
     if (tid < head) {
       const uint32_t v = affine(a, static_cast<uint32_t>(x[tid]), b);
-      if (STORE) St::put(y + tid, static_cast<int32_t>(v));
+      if (STORE) st.put(y + tid, static_cast<int32_t>(v));
       acc += static_cast<int32_t>(v);
     }
     const int4 *__restrict__ xv = reinterpret_cast<const int4 *>(x + head);
@@ -132,7 +160,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
         o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].y), b));
         o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].z), b));
         o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].w), b));
-        if (STORE) St::put(yv + k + u * nt, o);
+        if (STORE) st.put(yv + k + u * nt, o);
         acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
                static_cast<int64_t>(o.w);
       }
@@ -144,7 +172,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
       o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
       o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
       o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
-      if (STORE) St::put(yv + k, o);
+      if (STORE) st.put(yv + k, o);
       acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
              static_cast<int64_t>(o.w);
     }
@@ -152,7 +180,7 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
   }
   for (uint64_t i = done + tid; i < n; i += nt) {
     const uint32_t v = affine(a, static_cast<uint32_t>(x[i]), b);
-    if (STORE) St::put(y + i, static_cast<int32_t>(v));
+    if (STORE) st.put(y + i, static_cast<int32_t>(v));
     acc += static_cast<int32_t>(v);
   }
   return acc;
@@ -172,13 +200,14 @@ template <class St>
 __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__restrict__ y, uint64_t n,
                                       float alpha, uint64_t nt) {
   constexpr int U = 4;
+  const St st(y, n * 4);
   const uint64_t tid = threadIdx.x;
   uint64_t done = 0;
   const uintptr_t xa = reinterpret_cast<uintptr_t>(x) & 15u;
   if (xa == (reinterpret_cast<uintptr_t>(y) & 15u)) {
     uint64_t head = ((16u - xa) & 15u) >> 2;
     if (head > n) head = n;
-    if (tid < head) St::put(y + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
+    if (tid < head) st.put(y + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
     const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
     float4 *__restrict__ yv = reinterpret_cast<float4 *>(y + head);
     const uint64_t nv = (n - head) >> 2;
@@ -191,12 +220,12 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
         ry[u] = yv[k + u * nt];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) St::put(yv + k + u * nt, fma4(alpha, rx[u], ry[u]));
+      for (int u = 0; u < U; ++u) st.put(yv + k + u * nt, fma4(alpha, rx[u], ry[u]));
     }
-    for (; k < nv; k += nt) St::put(yv + k, fma4(alpha, xv[k], yv[k]));
+    for (; k < nv; k += nt) st.put(yv + k, fma4(alpha, xv[k], yv[k]));
     done = head + nv * 4;
   }
-  for (uint64_t i = done + tid; i < n; i += nt) St::put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
+  for (uint64_t i = done + tid; i < n; i += nt) st.put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
 }
 
 // out[i] = in[i] as raw 32-bit words.
@@ -204,13 +233,14 @@ template <class St>
 __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                        uint64_t n, uint64_t nt) {
   constexpr int U = 8;
+  const St st(out, n * 4);
   const uint64_t tid = threadIdx.x;
   uint64_t done = 0;
   const uintptr_t ia = reinterpret_cast<uintptr_t>(in) & 15u;
   if (ia == (reinterpret_cast<uintptr_t>(out) & 15u)) {
     uint64_t head = ((16u - ia) & 15u) >> 2;
     if (head > n) head = n;
-    if (tid < head) St::put(out + tid, in[tid]);
+    if (tid < head) st.put(out + tid, in[tid]);
     const u32x4 *__restrict__ iv = reinterpret_cast<const u32x4 *>(in + head);
     u32x4 *__restrict__ ov = reinterpret_cast<u32x4 *>(out + head);
     const uint64_t nv = (n - head) >> 2;
@@ -220,12 +250,12 @@ __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t
 #pragma unroll
       for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(iv + k + u * nt);
 #pragma unroll
-      for (int u = 0; u < U; ++u) St::put(ov + k + u * nt, r[u]);
+      for (int u = 0; u < U; ++u) st.put(ov + k + u * nt, r[u]);
     }
-    for (; k < nv; k += nt) St::put(ov + k, iv[k]);
+    for (; k < nv; k += nt) st.put(ov + k, iv[k]);
     done = head + nv * 4;
   }
-  for (uint64_t i = done + tid; i < n; i += nt) St::put(out + i, in[i]);
+  for (uint64_t i = done + tid; i < n; i += nt) st.put(out + i, in[i]);
 }
 
 // Compute-only loop (the paper's benchmark item, Sec. 3): `iters` dependent integer
@@ -243,24 +273,29 @@ __device__ __forceinline__ void spin(uint32_t iters) {
 template <class St>
 __device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uint32_t nt) {
   int64_t acc = 0;
-  switch (s.op) {
-    case 1:  // AFFINE_SUM_I32
-      acc = affine_sum<true, St>(static_cast<const int32_t *>(s.in), static_cast<int32_t *>(s.out), s.n, s.a, s.b, nt);
-      break;
-    case 2:  // SUM_I32_I64
-      acc = affine_sum<false, St>(static_cast<const int32_t *>(s.in), nullptr, s.n, 1u, 0u, nt);
-      break;
-    case 3:  // SAXPY_F32
-      saxpy<St>(static_cast<const float *>(s.in), static_cast<float *>(s.out), s.n, s.alpha, nt);
-      break;
-    case 4:  // COPY_F32
-      copy32<St>(static_cast<const uint32_t *>(s.in), static_cast<uint32_t *>(s.out), s.n, nt);
-      break;
-    case 5:  // SPIN
-      spin(s.a);
-      break;
-    default:
-      break;
+  if (s.op == 5) {  // SPIN: no memory
+    spin(s.a);
+  } else {
+    for (uint64_t off = 0; off < s.n; off += kSegmentElems) {
+      const uint64_t len = s.n - off < kSegmentElems ? s.n - off : kSegmentElems;
+      switch (s.op) {
+        case 1:  // AFFINE_SUM_I32
+          acc += affine_sum<true, St>(static_cast<const int32_t *>(s.in) + off, static_cast<int32_t *>(s.out) + off,
+                                      len, s.a, s.b, nt);
+          break;
+        case 2:  // SUM_I32_I64
+          acc += affine_sum<false, St>(static_cast<const int32_t *>(s.in) + off, nullptr, len, 1u, 0u, nt);
+          break;
+        case 3:  // SAXPY_F32
+          saxpy<St>(static_cast<const float *>(s.in) + off, static_cast<float *>(s.out) + off, len, s.alpha, nt);
+          break;
+        case 4:  // COPY_F32
+          copy32<St>(static_cast<const uint32_t *>(s.in) + off, static_cast<uint32_t *>(s.out) + off, len, nt);
+          break;
+        default:
+          break;
+      }
+    }
   }
   if (s.op == 1 || s.op == 2) return block_sum_i64(acc, s_red, nt);
   __syncthreads();

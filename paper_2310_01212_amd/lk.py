@@ -26,7 +26,7 @@ EXPORTED = [
     "lk_config_default", "lk_init", "lk_submit", "lk_wait", "lk_wait_info", "lk_poll",
     "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
-    "lkb_serial", "lkb_lanes", "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
+    "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
     "lkb_copy",
 ]
 
@@ -123,6 +123,7 @@ def lib():
         "lk_last_error": (ctypes.c_char_p, []),
         "lkb_serial": (ctypes.c_int, [P, U32, P, U64, I64, P, P, P, P]),
         "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD, P]),
+        "lkb_isolation": (ctypes.c_int, [P, U32, P, U64, I64, P, U32, P, P, P, P, P, P, PD]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
@@ -357,6 +358,25 @@ class Context:
         if with_info:
             return res, lat, el.value, info
         return res, lat, el.value
+
+    def run_isolation(self, crit_cluster, crit_items, period_s, bg_clusters, bg_items):
+        """Periodic critical items on one cluster beside back-to-back background items on
+        others.  Returns dict(results, lat_us, late_us, info, bg_done, elapsed_s)."""
+        crit_items = np.ascontiguousarray(crit_items, dtype=ITEM_DTYPE)
+        bg_items = np.ascontiguousarray(bg_items, dtype=ITEM_DTYPE)
+        bgc = np.ascontiguousarray(bg_clusters, dtype=np.uint32)
+        k = crit_items.size
+        res = np.zeros(k, np.int64)
+        lat = np.zeros(k, np.float64)
+        late = np.zeros(k, np.float64)
+        info = np.zeros(k, COMPLETION_DTYPE)
+        done = np.zeros(max(bgc.size, 1), np.uint64)
+        el = ctypes.c_double()
+        rc = lib().lkb_isolation(self._h, crit_cluster, _np_ptr(crit_items), k, int(period_s * 1e9),
+                                 _np_ptr(bgc), bgc.size, _np_ptr(bg_items), _np_ptr(res), _np_ptr(lat),
+                                 _np_ptr(late), _np_ptr(info), _np_ptr(done), ctypes.byref(el))
+        _check(rc, "lkb_isolation")
+        return dict(results=res, lat_us=lat, late_us=late, info=info, bg_done=done[:bgc.size], elapsed_s=el.value)
 
 
 def launch_serial(items, k=1, threads=256, mode=COMPLETE_SYNC, device=0):

@@ -50,3 +50,12 @@ def isolation_copy_source(cluster, elems=ISO_COPY_ELEMS, seed=3):
     """Private fp32 ~ N(0,1) source buffer of one interfering cluster."""
     rng = np.random.default_rng([seed, 100 + cluster])
     return rng.standard_normal(elems, dtype=np.float32)
+
+
+def isolation_copy_source_device(cluster, elems=ISO_COPY_ELEMS, device="cuda", seed=3):
+    """The same kind of private source as isolation_copy_source, drawn on the device with
+    torch's seeded generator (fp32 ~ N(0,1)) so that 256 MiB buffers need no host copy."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed * 1000 + 100 + cluster)
+    return torch.randn(elems, generator=g, device=device, dtype=torch.float32)

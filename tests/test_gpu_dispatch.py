@@ -428,3 +428,27 @@ def test_pingpong_and_copy_probes_run():
     ms, gbps = lk.copy_bandwidth(src, dst, nbytes, grid=2048, reps=5)
     assert gbps > 100
     assert torch.equal(src.cpu(), dst.cpu())
+
+
+# ------------------------------------------------------------------ cluster isolation runner
+def test_isolation_runner_critical_items_and_copies_exact():
+    say("isolation: 200 periods of 0.5 ms on XCD 0, copies of 16 MiB on XCDs 1-2")
+    xh, AB = workloads.isolation(periods=200)
+    x = to_dev(xh)
+    y = sentinel_i32(xh.shape)
+    elems = (16 << 20) // 4
+    srcs = [workloads.isolation_copy_source_device(c, elems, "cuda") for c in (1, 2)]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    torch.cuda.synchronize()
+    crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, addr(x), addr(y), AB[:, 0], AB[:, 1])
+    bg = lk.make_items(lk.OP_COPY_F32, elems, [addr(s) for s in srcs], [addr(d) for d in dsts])
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=20000) as ctx:
+        r = ctx.run_isolation(0, crit, 0.5e-3, [1, 2], bg)
+    for k in range(200):
+        assert r["results"][k] == oracle.affine_sum_i32(xh, int(AB[k, 0]), int(AB[k, 1]))[1], k
+    yr, _ = oracle.affine_sum_i32(xh, int(AB[-1, 0]), int(AB[-1, 1]))
+    assert np.array_equal(y.cpu().numpy(), yr)
+    for s, d in zip(srcs, dsts):
+        assert np.array_equal(s.cpu().numpy().view(np.uint32), d.cpu().numpy().view(np.uint32))
+    assert np.all(r["bg_done"] > 0)
+    assert np.all(r["lat_us"] > 0) and np.all(r["late_us"] < r["lat_us"])
