@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--items-per-step", type=int, default=1000, help="items per mailbox per step")
     ap.add_argument("--n", type=int, default=16384, help="elements per item")
     ap.add_argument("--depth", type=int, default=1, help="ring slots per mailbox (in flight)")
+    ap.add_argument("--threads-per-worker", type=int, default=256,
+                    help="workgroup size of each persistent worker (256 = one wave64 per SIMD)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
                     help="host feeder threads (one producer per mailbox)")
     ap.add_argument("--poll-sleep", type=int, default=0)
@@ -99,9 +101,14 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=1000, help="items per mailbox in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=1024)
-    ap.add_argument("--workload", choices=["allcu", "isolation"], default="allcu",
+    ap.add_argument("--workload", choices=["allcu", "isolation", "replay", "batching"], default="allcu",
                     help="allcu: the headline all-CU workload; isolation: cluster 0 critical "
-                         "item every period beside streaming copies on the other XCDs")
+                         "item every period beside streaming copies on the other XCDs; replay: the "
+                         "paper's phase protocol with its compute-only item")
+    ap.add_argument("--runs", type=int, default=100, help="replay: runs per configuration")
+    ap.add_argument("--bursts", type=str, default="1,4,16,64,256,1024,4096", help="batching: burst sizes")
+    ap.add_argument("--burst-reps", type=int, default=5, help="batching: timed repetitions per burst")
+    ap.add_argument("--spin-iters", type=int, default=20000, help="replay: loop iterations of the item")
     ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
     ap.add_argument("--period-us", type=float, default=1000.0)
     ap.add_argument("--copy-mib", type=int, default=256, help="isolation: interference buffer size")
@@ -118,7 +125,161 @@ def main():
         sys.exit(2)
     if args.workload == "isolation":
         return bench_isolation(args)
+    if args.workload == "replay":
+        return bench_replay(args)
+    if args.workload == "batching":
+        return bench_batching(args)
     return bench_allcu(args)
+
+
+# Host clock cycles per phase printed in the paper (Sec. 3): Table 2 averages (single SM,
+# full GPU) and Table 3 worst case (single SM), NVIDIA GTX 980 + Intel i7 at 3.6 GHz.
+# Context only, never a target.
+PAPER_CYCLES = {
+    ("avg", "single", "LK"): {"Init": 509e6, "Trigger": 239, "Wait": 190e3, "Dispose": 30e6},
+    ("avg", "single", "CUDA"): {"Alloc": 496e6, "Spawn": 3.9e3, "Wait": 175e3, "Dispose": 274e3},
+    ("avg", "full", "LK"): {"Init": 503e6, "Trigger": 210, "Wait": 190e3, "Dispose": 30e6},
+    ("avg", "full", "CUDA"): {"Alloc": 497e6, "Spawn": 3.8e3, "Wait": 176e3, "Dispose": 247e3},
+    ("worst", "single", "LK"): {"Init": 521e6, "Trigger": 1.1e3, "Wait": 203e3, "Dispose": 33e6},
+    ("worst", "single", "CUDA"): {"Alloc": 501e6, "Spawn": 7.7e3, "Wait": 176e3, "Dispose": 893e3},
+}
+
+
+def bench_batching(args):
+    """Bursts of uneven items (int32 affine / fp32 SAXPY 50/50, log-uniform 256 .. 2^20
+    elements) as one persistent batch over all CUs, with the tile size and polling
+    interval picked per burst size by the autotuner on training bursts (seed 50), against
+    the same bursts as per-item launches and as a captured hipGraph."""
+    import torch
+    from paper_2310_01212_amd import autotune, lk, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lk.lib()
+    dev = torch.device("cuda:0")
+    sizes = [int(v) for v in args.bursts.split(",")]
+    reps = args.burst_reps
+
+    def burst(count, seed):
+        ops, n, ab, alpha = workloads.batching(count, seed=seed)
+        off = np.concatenate([[0], np.cumsum((n + 255) // 256 * 256)]).astype(np.uint64)
+        return ops, n, ab, alpha, off
+
+    plans = {(c, s): burst(c, s) for c in sizes for s in (50, 5)}
+    total = int(max(p[4][-1] for p in plans.values()))
+    log(f"batching: arenas of {total} elements x 4 buffers")
+    xi, xf = workloads.device_arena(total, seed=5, device=dev)
+    yf = torch.randn(total, device=dev, dtype=torch.float32)
+    z = torch.empty(total, device=dev, dtype=torch.int32)
+    torch.cuda.synchronize()
+
+    def items_of(p):
+        ops, n, ab, alpha, off = p
+        ins = np.where(ops == lk.OP_AFFINE_SUM_I32, xi.data_ptr(), xf.data_ptr()).astype(np.uint64) + off[:-1] * 4
+        outs = np.where(ops == lk.OP_AFFINE_SUM_I32, z.data_ptr(), yf.data_ptr()).astype(np.uint64) + off[:-1] * 4
+        return lk.make_items(ops, n, ins, outs, ab[:, 0], ab[:, 1], alpha)
+
+    def item_bytes(p):
+        ops, n = p[0], p[1].astype(np.float64)
+        return float(np.sum(np.where(ops == lk.OP_AFFINE_SUM_I32, 8 * n + 8, 12 * n)))
+
+    staged = {}
+
+    def staged_tiles(key, tile):
+        if (key, tile) not in staged:
+            tiles, _ = lk.batch_plan(items_of(plans[key]), tile)
+            d = torch.from_numpy(tiles.view(np.uint8)).to(dev)
+            part = torch.zeros(tiles.size, dtype=torch.int64, device=dev)
+            torch.cuda.synchronize()
+            staged[(key, tile)] = (d, tiles.size, part)
+        return staged[(key, tile)]
+
+    ctxs = {}
+
+    def ctx_for(sleep):
+        if sleep not in ctxs:
+            ctxs[sleep] = lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=sleep, idle_timeout_ms=120000)
+        return ctxs[sleep]
+
+    def run_burst(size, tile, sleep, r):
+        d, nt, part = staged_tiles((size, 50), tile)
+        ctx = ctx_for(sleep)
+        ctx.run_batch(0, d, nt, part, reps=1)  # warm-up
+        return ctx.run_batch(0, d, nt, part, reps=r)
+
+    log("batching: autotuning on training bursts (seed 50)")
+    table = autotune.tune(run_burst, sizes, reps=reps)
+    out = {"metric": "burst makespan (µs), items/s and achieved GB/s: one persistent batch vs per-item "
+                     "launches vs captured hipGraph",
+           "unit": "items/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int32 / f32",
+           "data": "synthetic (seeded: bursts seed 5, tuning seed 50)", "steps": reps, "warmup": 1,
+           "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": "bursts of uneven items, log-uniform 256..2^20 elements, int32 affine and "
+                                  "fp32 SAXPY 50/50, one persistent batch over all CUs", "bursts": sizes},
+           "tuning": {str(k): {"tile": v["tile"], "poll_sleep": v["poll_sleep"]} for k, v in table.items()},
+           "bursts": {}}
+    for size in sizes:
+        key = (size, 5)
+        tune_row = table[size]
+        d, nt, part = staged_tiles(key, tune_row["tile"])
+        ctx = ctx_for(tune_row["poll_sleep"])
+        ctx.run_batch(0, d, nt, part, reps=1)
+        ms_p = ctx.run_batch(0, d, nt, part, reps=reps)
+        items = items_of(plans[key])
+        lk.launch_burst(items, graph=False, reps=1)
+        ms_l = lk.launch_burst(items, graph=False, reps=reps)
+        ms_g = lk.launch_burst(items, graph=True, reps=reps)
+        b = item_bytes(plans[key])
+        row = {}
+        for name, ms in (("persistent", ms_p), ("launch", ms_l), ("graph", ms_g)):
+            med = float(np.median(ms))
+            row[name] = {"makespan_us": round(med, 2), "items_per_s": round(size / (med * 1e-6), 1),
+                         "gbps": round(b / (med * 1e-6) / 1e9, 1)}
+        row["tiles"] = int(nt)
+        row["bytes"] = int(b)
+        out["bursts"][str(size)] = row
+        log(f"burst {size}: persistent {row['persistent']['makespan_us']} us, launch {row['launch']['makespan_us']} us, "
+            f"graph {row['graph']['makespan_us']} us")
+    for c in ctxs.values():
+        c.close()
+    big = out["bursts"][str(max(sizes))]
+    out["value"] = big["persistent"]["items_per_s"]
+    out["ms_per_step"] = round(big["persistent"]["makespan_us"] / 1e3, 4)
+    out["roofline"] = {"bound": "hbm", "achieved": big["persistent"]["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": round(big["persistent"]["gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                       "kernel": "lk_worker (one batch)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_replay(args):
+    """The paper's evaluation protocol on one MI355X: per run, Init/Trigger/Wait/Dispose of
+    the persistent path and Alloc/Spawn/Wait/Dispose of one ordinary launch, with the
+    paper's compute-only loop item, on one CU and on every CU."""
+    import torch
+    from paper_2310_01212_amd import lk
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lk.lib()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"metric": "host time per phase, avg and worst over runs (µs and host TSC cycles)",
+           "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "int32 (compute-only loop)",
+           "data": "synthetic", "steps": args.runs, "warmup": 0, "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": f"paper protocol: SPIN item of {args.spin_iters} iterations per thread, "
+                                  f"{args.runs} runs, single CU and all {cus} CUs"}}
+    for scope, nw in (("single_cu", 1), ("full_gpu", cus)):
+        log(f"replay: {scope} ({nw} workers), {args.runs} runs")
+        lk_us, hip_us, lk_cy, hip_cy = lk.replay(nw, args.spin_iters, args.runs)
+        res = {}
+        for sys_name, us, cy, phases in (("LK", lk_us, lk_cy, lk.REPLAY_PHASES_LK),
+                                         ("HIP", hip_us, hip_cy, lk.REPLAY_PHASES_HIP)):
+            res[sys_name] = {ph: {"avg_us": round(float(us[:, i].mean()), 3), "worst_us": round(float(us[:, i].max()), 3),
+                                  "avg_cycles": int(cy[:, i].astype(np.float64).mean()),
+                                  "worst_cycles": int(cy[:, i].max())}
+                             for i, ph in enumerate(phases)}
+        out[scope] = res
+    out["paper_cycles_gtx980_i7_3.6GHz"] = {f"{a}/{b}/{c}": v for (a, b, c), v in PAPER_CYCLES.items()}
+    out["value"] = out["single_cu"]["LK"]["Trigger"]["avg_us"] + out["single_cu"]["LK"]["Wait"]["avg_us"]
+    out["ms_per_step"] = None
+    print(json.dumps(out), flush=True)
 
 
 def bench_isolation(args):
@@ -214,7 +375,8 @@ def bench_allcu(args):
 
     # ---------------- persistent path
     log("persistent path: boot")
-    ctx = lk.Context(n_workers=lanes, depth=args.depth, poll_sleep=args.poll_sleep, idle_timeout_ms=60000)
+    ctx = lk.Context(n_workers=lanes, depth=args.depth, threads=args.threads_per_worker,
+                     poll_sleep=args.poll_sleep, idle_timeout_ms=60000)
     info0 = ctx.info()
     for s in range(args.warmup):
         ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads)
@@ -258,7 +420,8 @@ def bench_allcu(args):
         "config": {"workload": "all-CU SAXPY: one worker per CU, each mailbox fed items back-to-back",
                    "workers": lanes, "items_per_mailbox": per * args.steps, "n": n,
                    "item_bytes": bytes_per_item, "queue_depth": args.depth,
-                   "host_threads": args.threads, "poll_sleep": args.poll_sleep},
+                   "host_threads": args.threads, "threads_per_worker": args.threads_per_worker,
+                   "poll_sleep": args.poll_sleep},
         "latency_us": lat_summary(lat_all),
         "init_ms": round(info0["init_ms"], 3),
         "dispose_ms": round(info["dispose_ms"], 3),

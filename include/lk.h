@@ -70,6 +70,8 @@ enum {
  *  LK_OP_COPY_F32       out[i] = in[i], bit for bit (float[n]).
  *  LK_OP_SPIN           compute-only loop of a iterations per thread (the paper's
  *                       benchmark item, Sec. 3); no memory effect; result 0.
+ *  LK_OP_BATCH          many items in one dispatch: submitted only through
+ *                       lk_submit_batch (see "batches" below).
  */
 enum {
   LK_OP_NOP = 0,
@@ -78,7 +80,8 @@ enum {
   LK_OP_SAXPY_F32 = 3,
   LK_OP_COPY_F32 = 4,
   LK_OP_SPIN = 5,
-  LK_OP_COUNT = 6
+  LK_OP_BATCH = 6,
+  LK_OP_COUNT = 7
 };
 
 /* Descriptor of one work item, copied by value at submission (Sec. 1: "a descriptor of
@@ -173,6 +176,37 @@ LK_API int lk_submit(lk_ctx *ctx, uint32_t cluster, const lk_desc *desc, const v
  * released), LK_EFAULT (a member rejected its descriptor), LK_ESTATE. */
 LK_API int lk_wait(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int64_t timeout_ns,
             int64_t *result);
+
+/* ------------------------------------------------------------------ batches
+ * A batch is a table of tiles in device memory; every member of the cluster receives the
+ * same BATCH command and the members claim tiles one at a time from a shared counter
+ * (one device atomic per tile), so uneven items spread over the whole cluster inside a
+ * single persistent dispatch.  Tile t runs op `op` over n elements of in/out (the same
+ * bodies and layouts as the single-item ops; NOP, AFFINE_SUM_I32, SUM_I32_I64,
+ * SAXPY_F32, COPY_F32 or SPIN) and writes its int64 result to partials[t].
+ * lk_batch_plan cuts items into such tiles. */
+typedef struct lk_tile {
+  uint64_t in, out;   /* device addresses of the tile's first element (4-byte aligned) */
+  uint32_t n;         /* elements in the tile */
+  uint32_t op;        /* LK_OP_* of the tile (not BATCH) */
+  int32_t a;          /* AFFINE_SUM_I32 a; SPIN iterations */
+  uint32_t b;         /* AFFINE_SUM_I32 b, or the bits of SAXPY_F32 alpha */
+} lk_tile; /* 32 bytes */
+
+/* Trigger phase for a batch: `tiles` is a device array of n_tiles lk_tile records and
+ * `partials` a device or host-coherent int64 array of n_tiles entries; both must stay
+ * untouched until lk_wait returns for the ticket.  lk_wait's result is the number of
+ * tiles executed (n_tiles), summed over the members.  Errors as lk_submit. */
+LK_API int lk_submit_batch(lk_ctx *ctx, uint32_t cluster, const lk_tile *tiles, uint32_t n_tiles,
+                    int64_t *partials, uint64_t *ticket);
+
+/* Cut items into tiles of at most tile_elems elements (a multiple of 256; the last tile
+ * of an item may be shorter).  items: count descriptors with their in/out device
+ * addresses (in_addr[i], out_addr[i]); writes up to cap tiles and, per tile, the index of
+ * its item (tile_item, may be NULL); *n_tiles receives the number needed (LK_EINVAL if it
+ * exceeds cap, with nothing written beyond cap). */
+LK_API int lk_batch_plan(const lk_desc *items, const uint64_t *in_addr, const uint64_t *out_addr, uint32_t count,
+                  uint64_t tile_elems, lk_tile *tiles, uint32_t *tile_item, uint32_t cap, uint32_t *n_tiles);
 
 /* Timing of one completed ticket, in device wall-clock ticks (lk_info.wall_clock_hz):
  * earliest pickup and latest completion over the cluster's members. */

@@ -10,6 +10,10 @@
  *   - lkb_lanes         many clusters fed back-to-back by host threads;
  *   - lkb_isolation     a periodic critical item on one cluster beside streaming
  *                       interference on the others;
+ *   - lkb_batch         bursts of uneven items as one batch over a cluster;
+ *   - lkb_launch_burst  the same bursts as per-item launches or a captured hipGraph;
+ *   - lkb_replay        the paper's phase protocol (Init/Trigger/Wait/Dispose vs
+ *                       Alloc/Spawn/Wait/Dispose) with its compute-only item;
  *   - lkb_launch_serial one ordinary kernel launch per item (the paper's spawn path),
  *                       optionally through a single-node hipGraph relaunched per item;
  *   - lkb_launch_lanes  the lanes workload with one launch (or graph launch) per item;
@@ -65,6 +69,31 @@ LK_API int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, 
 LK_API int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64_t periods, int64_t period_ns,
                   const uint32_t *bg_clusters, uint32_t n_bg, const lkb_item *bg, int64_t *results, double *lat_us,
                   double *late_us, lk_completion *info, uint64_t *bg_done, double *elapsed_s);
+
+/* The paper's evaluation protocol (Sec. 3, Tables 2-3) on this hardware: `runs` times,
+ * (1) persistent path: Init (lk_init with n_workers workers in one cluster), Trigger
+ * (lk_submit of one SPIN item of spin_iters iterations per thread, one slice per
+ * worker), Wait (lk_wait), Dispose (lk_dispose);
+ * (2) per-launch path: Alloc (hipMalloc + stream creation), Spawn (launch of the same
+ * SPIN item on n_workers workgroups), Wait (stream synchronisation), Dispose (stream
+ * destruction + hipFree).
+ * Phase r*4 + {0,1,2,3} of each output: microseconds (lk_us, hip_us) and host
+ * time-stamp-counter cycles (lk_cycles, hip_cycles); any output may be NULL. */
+LK_API int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t runs, double *lk_us,
+               double *hip_us, uint64_t *lk_cycles, uint64_t *hip_cycles);
+
+/* Batches: `reps` times, post one batch of n_tiles device tiles to `cluster` and wait for
+ * it; makespan_us[r] = lk_submit_batch start to lk_wait return; info (nullable) = the
+ * members' device-side timing.  LK_EFAULT if a batch did not execute exactly n_tiles. */
+LK_API int lkb_batch(lk_ctx *c, uint32_t cluster, const lk_tile *tiles, uint32_t n_tiles, int64_t *partials,
+              uint32_t reps, int64_t timeout_ns, double *makespan_us, lk_completion *info);
+
+/* The same items as ordinary launches: one launch per item on one stream (grid =
+ * ceil(n / elems_per_wg) workgroups, at most 4096) then one stream synchronisation, or,
+ * with mode LKB_USE_GRAPH, the launches captured once into a hipGraph (capture and
+ * instantiation not timed) and the graph launched.  makespan_us[r] per repetition. */
+LK_API int lkb_launch_burst(int device, const lkb_item *items, uint32_t count, uint64_t elems_per_wg,
+                     uint32_t threads, uint32_t mode, uint32_t reps, double *makespan_us);
 
 #define LKB_COMPLETE_SYNC 0u  /* completion observed by hipStreamSynchronize */
 #define LKB_COMPLETE_FLAG 1u  /* completion observed through a host-coherent word the

@@ -3,6 +3,7 @@
  */
 #include <hip/hip_runtime_api.h>
 #include <immintrin.h>
+#include <x86intrin.h>
 
 #include <pthread.h>
 #include <sched.h>
@@ -321,6 +322,174 @@ int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64
   if (!rc) rc = bg_error.load();
   if (rc) return bfail(rc, "isolation run failed: %s (%s)", lk_strerror(rc), lk_last_error());
   return LK_OK;
+}
+
+int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t runs, double *lk_us, double *hip_us,
+               uint64_t *lk_cycles, uint64_t *hip_cycles) {
+  if (runs == 0 || n_workers == 0 || n_workers > LK_MAX_WORKERS) return bfail(LK_EINVAL, "bad runs/n_workers");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  lkb_item spin_item{};
+  spin_item.op = LK_OP_SPIN;
+  spin_item.a = static_cast<int32_t>(spin_iters);
+  const lk_desc d = to_desc(spin_item);
+  auto record = [](double *us, uint64_t *cy, uint32_t r, int phase, clk::time_point a, clk::time_point b, uint64_t ca,
+                   uint64_t cb) {
+    if (us) us[r * 4 + phase] = us_between(a, b);
+    if (cy) cy[r * 4 + phase] = cb - ca;
+  };
+  for (uint32_t r = 0; r < runs; ++r) {
+    // ---- persistent path: Init, Trigger, Wait, Dispose
+    lk_config cfg;
+    lk_config_default(&cfg);
+    cfg.device = device;
+    cfg.n_workers = n_workers;
+    cfg.cluster_policy = LK_CLUSTERS_ONE;  // one Trigger reaches every worker
+    cfg.idle_timeout_ms = 20000;
+    lk_ctx *c = nullptr;
+    auto a = clk::now();
+    uint64_t ca = __rdtsc();
+    int rc = lk_init(&cfg, &c);
+    uint64_t cb = __rdtsc();
+    auto b = clk::now();
+    if (rc) return bfail(rc, "replay lk_init: %s", lk_last_error());
+    record(lk_us, lk_cycles, r, 0, a, b, ca, cb);
+    uint64_t t;
+    a = clk::now();
+    ca = __rdtsc();
+    rc = lk_submit(c, 0, &d, nullptr, nullptr, &t);
+    cb = __rdtsc();
+    b = clk::now();
+    record(lk_us, lk_cycles, r, 1, a, b, ca, cb);
+    if (rc == LK_OK) {
+      a = clk::now();
+      ca = __rdtsc();
+      rc = lk_wait(c, 0, t, 10000000000ll, nullptr);
+      cb = __rdtsc();
+      b = clk::now();
+      record(lk_us, lk_cycles, r, 2, a, b, ca, cb);
+    }
+    a = clk::now();
+    ca = __rdtsc();
+    const int rc2 = lk_dispose(c);
+    cb = __rdtsc();
+    b = clk::now();
+    record(lk_us, lk_cycles, r, 3, a, b, ca, cb);
+    lk_free(c);
+    if (rc || rc2) return bfail(rc ? rc : rc2, "replay persistent run %u: %s", r, lk_last_error());
+
+    // ---- per-launch path: Alloc, Spawn, Wait, Dispose
+    void *buf = nullptr;
+    hipStream_t s = nullptr;
+    a = clk::now();
+    ca = __rdtsc();
+    e = hipMalloc(&buf, 4096);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    cb = __rdtsc();
+    b = clk::now();
+    if (e != hipSuccess) return bfail(LK_EHIP, "replay alloc: %s", hipGetErrorString(e));
+    record(hip_us, hip_cycles, r, 0, a, b, ca, cb);
+    lkd::ItemArgs ia = item_args(spin_item, n_workers);
+    a = clk::now();
+    ca = __rdtsc();
+    e = lkd::launch_item(ia, 256, s);
+    cb = __rdtsc();
+    b = clk::now();
+    record(hip_us, hip_cycles, r, 1, a, b, ca, cb);
+    if (e != hipSuccess) return bfail(LK_EHIP, "replay spawn: %s", hipGetErrorString(e));
+    a = clk::now();
+    ca = __rdtsc();
+    e = hipStreamSynchronize(s);
+    cb = __rdtsc();
+    b = clk::now();
+    record(hip_us, hip_cycles, r, 2, a, b, ca, cb);
+    if (e != hipSuccess) return bfail(LK_EHIP, "replay wait: %s", hipGetErrorString(e));
+    a = clk::now();
+    ca = __rdtsc();
+    (void)hipStreamDestroy(s);
+    e = hipFree(buf);
+    cb = __rdtsc();
+    b = clk::now();
+    record(hip_us, hip_cycles, r, 3, a, b, ca, cb);
+    if (e != hipSuccess) return bfail(LK_EHIP, "replay dispose: %s", hipGetErrorString(e));
+  }
+  return LK_OK;
+}
+
+int lkb_batch(lk_ctx *c, uint32_t cluster, const lk_tile *tiles, uint32_t n_tiles, int64_t *partials, uint32_t reps,
+              int64_t timeout_ns, double *makespan_us, lk_completion *info) {
+  if (!c || reps == 0) return bfail(LK_EINVAL, "NULL context or reps == 0");
+  for (uint32_t r = 0; r < reps; ++r) {
+    uint64_t t;
+    const auto t0 = clk::now();
+    int rc = lk_submit_batch(c, cluster, tiles, n_tiles, partials, &t);
+    if (rc) return rc;
+    lk_completion ci;
+    rc = lk_wait_info(c, cluster, t, timeout_ns, &ci);
+    const auto t1 = clk::now();
+    if (rc) return rc;
+    if (ci.result != static_cast<int64_t>(n_tiles))
+      return bfail(LK_EFAULT, "batch executed %lld tiles of %u", static_cast<long long>(ci.result), n_tiles);
+    if (makespan_us) makespan_us[r] = us_between(t0, t1);
+    if (info) info[r] = ci;
+  }
+  return LK_OK;
+}
+
+int lkb_launch_burst(int device, const lkb_item *items, uint32_t count, uint64_t elems_per_wg, uint32_t threads,
+                     uint32_t mode, uint32_t reps, double *makespan_us) {
+  if ((!items && count) || reps == 0 || elems_per_wg == 0 || threads < 64 || threads > 1024 || threads % 64)
+    return bfail(LK_EINVAL, "bad burst arguments");
+  for (uint32_t i = 0; i < count; ++i)
+    if (!valid_item(items[i]) || items[i].op == LK_OP_BATCH) return bfail(LK_EINVAL, "item %u invalid", i);
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  hipStream_t s;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return bfail(LK_EHIP, "stream: %s", hipGetErrorString(e));
+  DeviceBuf counters;  // one per item (grids of more than one workgroup)
+  int rc = LK_OK;
+  if ((e = hipMalloc(&counters.p, 64ull * (count ? count : 1))) != hipSuccess ||
+      (e = hipMemset(counters.p, 0, 64ull * (count ? count : 1))) != hipSuccess)
+    rc = bfail(LK_EHIP, "counters: %s", hipGetErrorString(e));
+  auto launch_all = [&]() -> hipError_t {
+    for (uint32_t i = 0; i < count; ++i) {
+      const uint64_t k64 = (items[i].n + elems_per_wg - 1) / elems_per_wg;
+      const uint32_t k = static_cast<uint32_t>(k64 < 1 ? 1 : (k64 > 4096 ? 4096 : k64));
+      lkd::ItemArgs a = item_args(items[i], k);
+      a.counter = reinterpret_cast<uint32_t *>(static_cast<char *>(counters.p) + 64ull * i);
+      const hipError_t le = lkd::launch_item(a, threads, s);
+      if (le != hipSuccess) return le;
+    }
+    return hipSuccess;
+  };
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  const bool use_graph = mode & LKB_USE_GRAPH;
+  if (rc == LK_OK && use_graph) {
+    // Capture the burst once (not timed), instantiate, then time graph launches.
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      rc = bfail(LK_EHIP, "begin capture: %s", hipGetErrorString(e));
+    if (rc == LK_OK) {
+      const hipError_t le = launch_all();
+      e = hipStreamEndCapture(s, &g);
+      if (le != hipSuccess || e != hipSuccess) rc = bfail(LK_EHIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+    }
+    if (rc == LK_OK && (e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) != hipSuccess)
+      rc = bfail(LK_EHIP, "instantiate: %s", hipGetErrorString(e));
+  }
+  for (uint32_t r = 0; rc == LK_OK && r < reps; ++r) {
+    const auto t0 = clk::now();
+    e = use_graph ? hipGraphLaunch(ge, s) : launch_all();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const auto t1 = clk::now();
+    if (e != hipSuccess) rc = bfail(LK_EHIP, "burst: %s", hipGetErrorString(e));
+    else if (makespan_us) makespan_us[r] = us_between(t0, t1);
+  }
+  (void)hipStreamSynchronize(s);
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(s);
+  return rc;
 }
 
 int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb_item *items, uint64_t count, uint32_t mode,

@@ -11,7 +11,17 @@
 
 namespace lkd {
 
-constexpr uint32_t kOpCount = 6;  // NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN
+constexpr uint32_t kOpCount = 7;  // NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN, BATCH
+constexpr uint32_t kOpBatch = 6;
+
+// Tile record of a batch (same layout as lk_tile in lk.h).
+struct Tile {
+  uint64_t in, out;
+  uint32_t n, op;
+  int32_t a;
+  uint32_t b;
+};
+static_assert(sizeof(Tile) == 32, "tile record is 32 bytes");
 
 // Slicing rule of a cluster item: m = ceil(n/k) rounded up to a multiple of 256 elements,
 // slice j = [min(n, j*m), min(n, (j+1)*m)).  Used by the host to cut descriptors and by

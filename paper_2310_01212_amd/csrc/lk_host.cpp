@@ -91,6 +91,8 @@ struct lk_ctx {
   lkw_worker *wrec = nullptr;
   lkw_log *d_log = nullptr;
   uint32_t *d_claim = nullptr;
+  uint64_t *d_batch_counters = nullptr;             // [cluster][depth], 128 bytes apart
+  std::vector<uint64_t> batch_base;                 // [cluster][depth], host copy of each base
   std::vector<WorkerInfo> workers;                  // physical order
   std::vector<std::vector<uint32_t>> clusters;      // member worker indices, slice order
   std::vector<std::vector<uint32_t>> cluster_mbox;  // member mailboxes, slice order
@@ -185,6 +187,8 @@ int validate_config(const lk_config *cfg) {
 // Only called once the persistent dispatch has ended (or was never made).
 void release_gpu(lk_ctx *c) {
   c->wq.close();
+  if (c->d_batch_counters) (void)hipFree(c->d_batch_counters);
+  c->d_batch_counters = nullptr;
   if (c->d_log) (void)hipFree(c->d_log);
   if (c->d_claim) (void)hipFree(c->d_claim);
   if (c->host_region) (void)hipHostFree(c->host_region);
@@ -304,6 +308,15 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
 
   if ((e = hipMalloc(&c->d_claim, 256)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(claim)"));
   if ((e = hipMemset(c->d_claim, 0, 256)) != hipSuccess) return bail(hip_fail(e, "hipMemset(claim)"));
+  // Tile counters of batches: one per (cluster, ring slot) -- there are at most n_workers
+  // clusters -- 128 bytes apart and never reset: each batch advances its counter by
+  // n_tiles + members (every member's last claim overshoots once), which the host adds to
+  // that slot's base.
+  {
+    const size_t cb = static_cast<size_t>(c->n_workers) * c->depth * 128;
+    if ((e = hipMalloc(&c->d_batch_counters, cb)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(batch counters)"));
+    if ((e = hipMemset(c->d_batch_counters, 0, cb)) != hipSuccess) return bail(hip_fail(e, "hipMemset(batch counters)"));
+  }
   if (c->log_cap) {
     const size_t lb = sizeof(lkw_log) * c->n_workers * static_cast<size_t>(c->log_cap);
     if ((e = hipMalloc(&c->d_log, lb)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(log)"));
@@ -435,6 +448,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
       c->cluster_of_mbox[ws[w].mailbox] = k;
     }
   c->seqs.assign(c->n_clusters, ClusterSeq{});
+  c->batch_base.assign(static_cast<size_t>(c->n_clusters) * c->depth, 0);
   c->init_ms = std::chrono::duration<double, std::milli>(clk::now() - t_begin).count();
   *out = c;
   g_last_error.clear();
@@ -446,6 +460,7 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
   if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
   if (d->op >= LK_OP_COUNT) return fail(LK_EINVAL, "unknown op %u", d->op);
+  if (d->op == LK_OP_BATCH) return fail(LK_EINVAL, "batches go through lk_submit_batch");
   if (d->flags || d->reserved) return fail(LK_EINVAL, "flags/reserved must be 0");
   if (d->n > LK_MAX_N) return fail(LK_EINVAL, "n %llu > LK_MAX_N", static_cast<unsigned long long>(d->n));
   const uint64_t ia = reinterpret_cast<uint64_t>(in), oa = reinterpret_cast<uint64_t>(out);
@@ -475,6 +490,69 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   }
   cs.posted = t;
   *ticket = t;
+  return LK_OK;
+}
+
+int lk_submit_batch(lk_ctx *c, uint32_t cluster, const lk_tile *tiles, uint32_t n_tiles, int64_t *partials,
+                    uint64_t *ticket) {
+  if (!c || !ticket) return fail(LK_EINVAL, "NULL argument");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  const uint64_t ta = reinterpret_cast<uint64_t>(tiles), pa = reinterpret_cast<uint64_t>(partials);
+  if (n_tiles && (!tiles || (ta & 15u) || !partials || (pa & 7u)))
+    return fail(LK_EINVAL, "tiles must be 16-byte aligned and partials 8-byte aligned, non-NULL");
+  if ((ta | pa) >> LKW_TAG_SHIFT) return fail(LK_EINVAL, "pointer outside the 48-bit address range");
+  ClusterSeq &cs = c->seqs[cluster];
+  const uint64_t t = cs.posted + 1;
+  if (t - cs.consumed > c->depth) return fail(LK_EAGAIN, "ring full (depth %u)", c->depth);
+  const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
+  for (uint32_t mb : mbs)
+    if (exited_code(worker_code(c, mb))) return fail(LK_ESTATE, "worker of mailbox %u has exited", mb);
+  const size_t slot = static_cast<size_t>(cluster) * c->depth + t % c->depth;
+  uint64_t &base = c->batch_base[slot];
+  const uint64_t counter = reinterpret_cast<uint64_t>(c->d_batch_counters) + slot * 128;
+  for (uint32_t j = 0; j < mbs.size(); ++j)
+    post_cmd(c, mbs[j], t, LKW_TO_WORK + LK_OP_BATCH, n_tiles, ta, pa, counter, static_cast<uint32_t>(base),
+             static_cast<uint32_t>(base >> 32), 0.f, j);
+  base += static_cast<uint64_t>(n_tiles) + mbs.size();
+  cs.posted = t;
+  *ticket = t;
+  return LK_OK;
+}
+
+int lk_batch_plan(const lk_desc *items, const uint64_t *in_addr, const uint64_t *out_addr, uint32_t count,
+                  uint64_t tile_elems, lk_tile *tiles, uint32_t *tile_item, uint32_t cap, uint32_t *n_tiles) {
+  if (!n_tiles || (count && (!items || !in_addr || !out_addr))) return fail(LK_EINVAL, "NULL argument");
+  if (tile_elems == 0 || tile_elems % 256 || tile_elems > (1ull << 31)) return fail(LK_EINVAL, "tile_elems must be a positive multiple of 256 up to 2^31");
+  uint64_t need = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const lk_desc &d = items[i];
+    if (d.op >= LK_OP_COUNT || d.op == LK_OP_BATCH) return fail(LK_EINVAL, "item %u: op %u cannot be tiled", i, d.op);
+    if ((in_addr[i] | out_addr[i]) & 3u) return fail(LK_EINVAL, "item %u: pointers must be 4-byte aligned", i);
+    need += d.n == 0 ? 1 : (d.n + tile_elems - 1) / tile_elems;
+  }
+  *n_tiles = static_cast<uint32_t>(need);
+  if (need > cap || need > 0xffffffffull) return fail(LK_EINVAL, "%llu tiles exceed cap %u", static_cast<unsigned long long>(need), cap);
+  uint32_t k = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const lk_desc &d = items[i];
+    uint32_t bbits;
+    memcpy(&bbits, &d.alpha, 4);
+    if (d.op != LK_OP_SAXPY_F32) bbits = static_cast<uint32_t>(d.b);
+    const uint64_t parts = d.n == 0 ? 1 : (d.n + tile_elems - 1) / tile_elems;
+    for (uint64_t p = 0; p < parts; ++p) {
+      const uint64_t lo = p * tile_elems, len = std::min<uint64_t>(tile_elems, d.n - std::min(d.n, lo));
+      lk_tile &tl = tiles[k];
+      tl.in = op_reads(d.op) ? in_addr[i] + lo * 4 : 0;
+      tl.out = op_writes(d.op) ? out_addr[i] + lo * 4 : 0;
+      tl.n = static_cast<uint32_t>(len);
+      tl.op = d.op;
+      tl.a = d.a;
+      tl.b = bbits;
+      if (tile_item) tile_item[k] = i;
+      ++k;
+    }
+  }
   return LK_OK;
 }
 

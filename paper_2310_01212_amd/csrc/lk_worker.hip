@@ -29,6 +29,45 @@
 
 using namespace lkdev;
 
+// BATCH: claim tiles one at a time from the shared counter (value - base = tile index)
+// until the table is exhausted; every claim past the end is the member's last.  The
+// claim is a system-scope atomic so that it is performed at memory, one counter for the
+// members on all XCDs whatever their private L2s hold.  The
+// claim for the next tile is issued before the current tile runs so that the atomic's
+// round trip overlaps the tile's own loads.  Returns (in thread 0) the number of tiles
+// this member executed.
+__device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_tiles, int64_t *partials,
+                                             uint64_t *counter, uint64_t base, int64_t *s_red, uint64_t *s_next,
+                                             uint32_t nt) {
+  int64_t executed = 0;
+  if (threadIdx.x == 0)
+    *s_next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) - base;
+  __syncthreads();
+  for (;;) {
+    const uint64_t t = *s_next;
+    if (t >= n_tiles) break;
+    const lkd::Tile tile = tiles[t];
+    uint64_t next = 0;
+    if (threadIdx.x == 0) next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    lkops::Slice sl;
+    sl.op = tile.op < lkd::kOpBatch ? tile.op : 0u;
+    sl.n = tile.n;
+    sl.in = reinterpret_cast<const void *>(tile.in);
+    sl.out = reinterpret_cast<void *>(tile.out);
+    sl.a = static_cast<uint32_t>(tile.a);
+    sl.b = tile.b;
+    sl.alpha = __uint_as_float(tile.b);
+    const int64_t part = lkops::run_slice<lkops::SystemStore>(sl, s_red, nt);  // ends with a barrier
+    if (threadIdx.x == 0) {
+      st_sys_i64(partials + t, part);
+      *s_next = next - base;
+    }
+    ++executed;
+    __syncthreads();
+  }
+  return executed;
+}
+
 // Lanes 0..7 of wave 0 write the eight tagged words of a status record in one store.
 __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uint32_t code, int64_t partial,
                                                uint64_t t_pick, uint64_t t_done, uint32_t hw, uint32_t xcc) {
@@ -52,7 +91,7 @@ __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uin
 extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   extern __shared__ uint64_t lds_reserve[];  // only holds the CU: one worker per CU
   __shared__ uint64_t s_w[LKW_CMD_WORDS];
-  __shared__ uint64_t s_t_pick, s_t_done;
+  __shared__ uint64_t s_t_pick, s_t_done, s_batch_next;
   __shared__ int64_t s_partial;
   __shared__ uint32_t s_mb, s_go, s_hw, s_xcc;
   __shared__ int64_t s_red[lkops::kMaxWaves];
@@ -162,7 +201,13 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     } else {
       reply = LKW_FROM_ERROR;
     }
-    const int64_t partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
+    const bool batch = s.op == lkd::kOpBatch;
+    const int64_t partial =
+        batch ? run_batch(static_cast<const lkd::Tile *>(s.in), s.n, static_cast<int64_t *>(s.out),
+                          reinterpret_cast<uint64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK),
+                          static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, &s_batch_next,
+                          p.threads)
+              : lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
 
     // ---- complete.  Thread 0 writes the optional per-member partial and the log record
     // with system-coherent stores; every wave then waits until all of its stores have
@@ -172,7 +217,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       s_t_done = t_done;
       s_partial = partial;
       int64_t *aux = reinterpret_cast<int64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
-      if (aux) st_sys_i64(aux, partial);
+      if (aux && !batch) st_sys_i64(aux, partial);
       if (p.log) {
         lkw_log *e = p.log + static_cast<uint64_t>(m) * p.log_cap + (seq % p.log_cap);
         const uint64_t head = static_cast<uint64_t>(static_cast<uint32_t>(want)) |

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblk.so")
 
 OK, EINVAL, EAGAIN, ETIMEDOUT, ESTATE, ENODEV, EHIP, EFAULT = 0, -1, -2, -3, -4, -5, -6, -7
-OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN = range(6)
+OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, OP_BATCH = range(7)
 CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
 F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
 COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
@@ -23,10 +23,11 @@ COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
 CODE_NOP, CODE_EXIT, CODE_WORK = 4, 8, 16
 
 EXPORTED = [
-    "lk_config_default", "lk_init", "lk_submit", "lk_wait", "lk_wait_info", "lk_poll",
+    "lk_config_default", "lk_init", "lk_submit", "lk_submit_batch", "lk_batch_plan", "lk_wait", "lk_wait_info", "lk_poll",
     "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
-    "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
+    "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_replay", "lkb_batch", "lkb_launch_burst",
+    "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
     "lkb_copy",
 ]
 
@@ -81,6 +82,7 @@ ITEM_DTYPE = np.dtype([("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4
                        ("n", "<u8"), ("inp", "<u8"), ("out", "<u8")])
 COMPLETION_DTYPE = np.dtype([("result", "<i8"), ("t_pick_min", "<u8"), ("t_pick_max", "<u8"),
                              ("t_done_min", "<u8"), ("t_done_max", "<u8")])
+TILE_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("n", "<u4"), ("op", "<u4"), ("a", "<i4"), ("b", "<u4")])
 LOG_DTYPE = np.dtype([("seq", "<u4"), ("code", "<u2"), ("worker", "<u2"), ("xcc", "<u4"),
                       ("hwid", "<u4"), ("t_pick", "<u8"), ("t_done", "<u8")])
 
@@ -109,6 +111,8 @@ def lib():
         "lk_config_default": (None, [ctypes.POINTER(Config)]),
         "lk_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(P)]),
         "lk_submit": (ctypes.c_int, [P, U32, ctypes.POINTER(Desc), P, P, PU64]),
+        "lk_submit_batch": (ctypes.c_int, [P, U32, P, U32, P, PU64]),
+        "lk_batch_plan": (ctypes.c_int, [P, P, P, U32, U64, P, P, U32, PU32]),
         "lk_wait": (ctypes.c_int, [P, U32, U64, I64, PI64]),
         "lk_wait_info": (ctypes.c_int, [P, U32, U64, I64, ctypes.POINTER(Completion)]),
         "lk_poll": (ctypes.c_int, [P, U32, U64, ctypes.POINTER(ctypes.c_int)]),
@@ -124,6 +128,9 @@ def lib():
         "lkb_serial": (ctypes.c_int, [P, U32, P, U64, I64, P, P, P, P]),
         "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD, P]),
         "lkb_isolation": (ctypes.c_int, [P, U32, P, U64, I64, P, U32, P, P, P, P, P, P, PD]),
+        "lkb_replay": (ctypes.c_int, [I32, U32, U32, U32, P, P, P, P]),
+        "lkb_batch": (ctypes.c_int, [P, U32, P, U32, P, U32, I64, P, P]),
+        "lkb_launch_burst": (ctypes.c_int, [I32, P, U32, U64, U32, U32, U32, P]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
@@ -247,6 +254,22 @@ class Context:
         rc = lib().lk_submit(self._h, cluster, ctypes.byref(d), _ptr(x), _ptr(y), ctypes.byref(t))
         _check(rc, "lk_submit")
         return t.value
+
+    def submit_batch(self, cluster, tiles, n_tiles, partials):
+        """Trigger a batch: tiles = device array of lk_tile records (tensor or address),
+        partials = device or host-coherent int64 array of n_tiles entries."""
+        t = ctypes.c_uint64()
+        _check(lib().lk_submit_batch(self._h, cluster, _ptr(tiles), n_tiles, _ptr(partials), ctypes.byref(t)),
+               "lk_submit_batch")
+        return t.value
+
+    def run_batch(self, cluster, tiles, n_tiles, partials, reps=1, timeout=30.0, with_info=False):
+        """Submit-then-wait the same batch `reps` times natively; returns makespans (us)."""
+        ms = np.zeros(reps, np.float64)
+        info = np.zeros(reps, COMPLETION_DTYPE)
+        _check(lib().lkb_batch(self._h, cluster, _ptr(tiles), n_tiles, _ptr(partials), reps, int(timeout * 1e9),
+                               _np_ptr(ms), _np_ptr(info)), "lkb_batch")
+        return (ms, info) if with_info else ms
 
     def try_submit(self, cluster, op, **kw):
         """Like submit but returns None when the ring is full."""
@@ -391,6 +414,36 @@ def launch_serial(items, k=1, threads=256, mode=COMPLETE_SYNC, device=0):
     return res, lat, lau
 
 
+def batch_plan(items, tile_elems):
+    """Cut ITEM_DTYPE items into tiles (lk_batch_plan).  Returns (tiles TILE_DTYPE array,
+    tile_item uint32 array)."""
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE).ravel()
+    count = items.size
+    descs = (Desc * max(count, 1))()
+    for i in range(count):
+        descs[i] = Desc(int(items["op"][i]), 0, int(items["n"][i]), int(items["a"][i]), int(items["b"][i]),
+                        float(items["alpha"][i]), 0, 0, 0)
+    ins = np.ascontiguousarray(items["inp"], dtype=np.uint64)
+    outs = np.ascontiguousarray(items["out"], dtype=np.uint64)
+    need = ctypes.c_uint32()
+    L = lib()
+    cap = int(sum(max(1, -(-int(n) // tile_elems)) for n in items["n"]))
+    tiles = np.zeros(max(cap, 1), TILE_DTYPE)
+    tile_item = np.zeros(max(cap, 1), np.uint32)
+    _check(L.lk_batch_plan(descs, _np_ptr(ins), _np_ptr(outs), count, tile_elems, _np_ptr(tiles),
+                           _np_ptr(tile_item), cap, ctypes.byref(need)), "lk_batch_plan")
+    return tiles[:need.value], tile_item[:need.value]
+
+
+def launch_burst(items, elems_per_wg=16384, threads=256, graph=True, reps=1, device=0):
+    """The burst as per-item launches (graph=False) or one captured hipGraph; makespans (us)."""
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE).ravel()
+    ms = np.zeros(reps, np.float64)
+    _check(lib().lkb_launch_burst(device, _np_ptr(items), items.size, elems_per_wg, threads,
+                                  USE_GRAPH if graph else 0, reps, _np_ptr(ms)), "lkb_launch_burst")
+    return ms
+
+
 def launch_lanes(items, streams=4, threads_host=8, threads=256, mode=0, device=0):
     items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
     lanes, per = items.shape
@@ -401,6 +454,21 @@ def launch_lanes(items, streams=4, threads_host=8, threads=256, mode=0, device=0
                                   mode, _np_ptr(res), _np_ptr(lat), ctypes.byref(el)),
            "lkb_launch_lanes")
     return res, lat, el.value
+
+
+REPLAY_PHASES_LK = ("Init", "Trigger", "Wait", "Dispose")
+REPLAY_PHASES_HIP = ("Alloc", "Spawn", "Wait", "Dispose")
+
+
+def replay(n_workers, spin_iters=20000, runs=100, device=0):
+    """The paper's phase protocol; returns (lk_us, hip_us, lk_cycles, hip_cycles), each (runs, 4)."""
+    lk_us = np.zeros((runs, 4), np.float64)
+    hip_us = np.zeros((runs, 4), np.float64)
+    lk_cy = np.zeros((runs, 4), np.uint64)
+    hip_cy = np.zeros((runs, 4), np.uint64)
+    _check(lib().lkb_replay(device, n_workers, spin_iters, runs, _np_ptr(lk_us), _np_ptr(hip_us),
+                            _np_ptr(lk_cy), _np_ptr(hip_cy)), "lkb_replay")
+    return lk_us, hip_us, lk_cy, hip_cy
 
 
 def pingpong(workers=1, iters=10000, poll_sleep=0, spread=True, device=0):

@@ -12,6 +12,9 @@ import numpy as np
 PLAIN_ITEMS, PLAIN_N = 1000, 4096
 # all CUs: one worker per CU, 10,000 SAXPY items per mailbox over 16,384 fp32
 ALLCU_ITEMS, ALLCU_N = 10000, 16384
+# batching: bursts of uneven items, log-uniform 256 .. 2^20 elements, affine / SAXPY 50/50
+BATCH_SIZES = (1, 4, 16, 64, 256, 1024, 4096)
+BATCH_LOG2_RANGE = (8, 20)
 # cluster isolation: critical int32 affine+sum over 262,144 elements, 1 ms period;
 # interference: 256 MiB fp32 copies on the other clusters
 ISO_N, ISO_PERIOD_S, ISO_COPY_ELEMS = 262144, 1e-3, (256 << 20) // 4
@@ -59,3 +62,25 @@ def isolation_copy_source_device(cluster, elems=ISO_COPY_ELEMS, device="cuda", s
     g = torch.Generator(device=device)
     g.manual_seed(seed * 1000 + 100 + cluster)
     return torch.randn(elems, generator=g, device=device, dtype=torch.float32)
+
+
+def batching(count, seed=5, log2_range=BATCH_LOG2_RANGE):
+    """A burst of `count` uneven items: ops (1 = int32 affine + sum, 3 = fp32 SAXPY, each
+    with probability 1/2), element counts round(2**U(lo, hi)), per-item a, b (int32) and
+    alpha ~ U(-2, 2)."""
+    rng = np.random.default_rng(seed)
+    ops = np.where(rng.random(count) < 0.5, 1, 3).astype(np.uint32)
+    n = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], count)).astype(np.uint64)
+    ab = uniform_i32(rng, (count, 2))
+    alpha = rng.uniform(-2, 2, count).astype(np.float32)
+    return ops, n, ab, alpha
+
+
+def device_arena(elems, seed, device="cuda"):
+    """Seeded device buffers for burst inputs: x as random 32-bit words, y ~ N(0,1) fp32."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed * 7919 + 1)
+    x = torch.randint(-2 ** 31, 2 ** 31 - 1, (elems,), generator=g, device=device, dtype=torch.int32)
+    y = torch.randn(elems, generator=g, device=device, dtype=torch.float32)
+    return x, y

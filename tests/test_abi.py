@@ -162,3 +162,55 @@ def test_make_items_marshals_int32_and_addresses():
     assert it["a"].tolist() == [-1, 5] and it["b"].tolist() == [-7, -7]
     assert it["inp"].tolist() == [0x1000, 0x2000] and it["out"].tolist() == [0x3000, 0x4000]
     assert lk._i32(2 ** 31) == -2 ** 31 and lk._i32(-1) == -1
+
+
+def test_bench_quotes_the_paper_tables_as_printed():
+    import bench
+    golden = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_phase_cycles.txt")):
+        if line.strip() and not line.startswith("#"):
+            table, scope, system, phase, cycles = line.split()
+            golden[(table, scope, system, phase)] = float(cycles)
+    seen = 0
+    for (kind, scope, system), phases in bench.PAPER_CYCLES.items():
+        table = "table2" if kind == "avg" else "table3"
+        sc = "single_sm" if scope == "single" else "full_gpu"
+        for phase, v in phases.items():
+            assert golden[(table, sc, system, phase)] == v
+            seen += 1
+    assert seen == len(golden) == 24
+
+
+def test_batch_plan_cuts_items_into_tiles():
+    items = lk.make_items(np.array([lk.OP_AFFINE_SUM_I32, lk.OP_SAXPY_F32, lk.OP_COPY_F32, lk.OP_NOP]),
+                          np.array([1000, 256, 513, 0], np.uint64), np.array([0x1000, 0x8000, 0x20000, 0]),
+                          np.array([0x4000, 0x9000, 0x40000, 0]), a=np.array([3, 0, 0, 0]),
+                          b=np.array([-5, 0, 0, 0]), alpha=np.array([0, 1.5, 0, 0], np.float32))
+    tiles, owner = lk.batch_plan(items, 256)
+    assert owner.tolist() == [0, 0, 0, 0, 1, 2, 2, 2, 3]
+    assert tiles["n"].tolist() == [256, 256, 256, 232, 256, 256, 256, 1, 0]
+    assert tiles["inp"][:4].tolist() == [0x1000 + 256 * 4 * k for k in range(4)]
+    assert tiles["out"][:4].tolist() == [0x4000 + 256 * 4 * k for k in range(4)]
+    assert tiles["a"][0] == 3 and tiles["b"][0] == np.uint32(np.int32(-5).view(np.uint32))
+    assert tiles["b"][4] == np.float32(1.5).view(np.uint32)
+    for i, it in enumerate(items):
+        assert tiles["n"][owner == i].sum() == it["n"]
+    with pytest.raises(lk.LKError):
+        lk.batch_plan(items, 100)   # not a multiple of 256
+    assert lk.TILE_DTYPE.itemsize == 32
+
+
+def test_autotuner_picks_the_fastest_median_with_stable_ties():
+    from paper_2310_01212_amd import autotune
+    t = {(4096, 0): [10, 11, 50], (16384, 0): [9, 12, 12], (65536, 8): [11, 11, 11], (65536, 0): [30, 30, 30]}
+    assert autotune.pick_best(t) == (65536, 8)   # medians 11 tie; larger tile wins
+    t2 = {(4096, 0): [5.0], (16384, 0): [5.0], (16384, 8): [5.0]}
+    assert autotune.pick_best(t2) == (16384, 8)   # tie: larger tile, then longer sleep
+    calls = []
+
+    def fake(size, tile, sleep, reps):
+        calls.append((size, tile, sleep))
+        return [abs(tile - 16384 * size) / 1e3 + sleep + 1] * reps
+    table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), sleeps=(0, 8), reps=2)
+    assert table[1]["tile"] == 16384 and table[1]["poll_sleep"] == 0
+    assert table[4]["tile"] == 65536 and len(calls) == 12

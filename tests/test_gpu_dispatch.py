@@ -452,3 +452,108 @@ def test_isolation_runner_critical_items_and_copies_exact():
         assert np.array_equal(s.cpu().numpy().view(np.uint32), d.cpu().numpy().view(np.uint32))
     assert np.all(r["bg_done"] > 0)
     assert np.all(r["lat_us"] > 0) and np.all(r["late_us"] < r["lat_us"])
+
+
+# ------------------------------------------------------------------ paper replay protocol
+def test_replay_protocol_runs_on_one_cu_and_all_cus():
+    say("replay: 3 runs of Init/Trigger/Wait/Dispose vs Alloc/Spawn/Wait/Dispose, SPIN 20000")
+    for nw in (1, torch.cuda.get_device_properties(0).multi_processor_count):
+        lk_us, hip_us, lk_cy, hip_cy = lk.replay(nw, 20000, 3)
+        assert np.all(lk_us > 0) and np.all(hip_us > 0)
+        assert np.all(lk_cy > 0) and np.all(hip_cy > 0)
+        # the loop dominates Wait; Trigger is a few host stores
+        assert np.all(lk_us[:, 1] < lk_us[:, 2])
+
+
+# ------------------------------------------------------------------ batches
+def _burst(count, seed, log2_range=(8, 16)):
+    ops, n, ab, alpha = workloads.batching(count, seed=seed, log2_range=log2_range)
+    off = np.concatenate([[0], np.cumsum((n + 255) // 256 * 256)])
+    rng = np.random.default_rng(seed + 1000)
+    total = int(off[-1])
+    xi = rng.integers(-2 ** 31, 2 ** 31, total, dtype=np.int64).astype(np.int32)
+    xf = rng.standard_normal(total).astype(np.float32)
+    yf = rng.standard_normal(total).astype(np.float32)
+    return ops, n, ab, alpha, off, xi, xf, yf
+
+
+def test_batches_of_uneven_items_bit_exact_over_all_cus_and_one_xcd():
+    ops, n, ab, alpha, off, xi, xf, yf = _burst(64, 11)
+    say(f"batch: 64 uneven items ({int(n.sum())} elements), tiles of 4096, cluster ONE and XCD 0, 3 reps")
+    for policy, cluster in ((lk.CLUSTERS_ONE, 0), (lk.CLUSTERS_PER_XCD, 0)):
+        d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf.copy())
+        d_z = sentinel_i32(xi.shape)
+        ins = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_xi), addr(d_xf)) + off[:-1].astype(np.uint64) * 4
+        outs = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_z), addr(d_yf)) + off[:-1].astype(np.uint64) * 4
+        items = lk.make_items(ops, n, ins.astype(np.uint64), outs.astype(np.uint64), ab[:, 0], ab[:, 1], alpha)
+        tiles, owner = lk.batch_plan(items, 4096)
+        d_tiles = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
+        partials = torch.zeros(tiles.size, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        with lk.Context(n_workers=0, clusters=policy, idle_timeout_ms=20000) as ctx:
+            ms = ctx.run_batch(cluster, d_tiles, tiles.size, partials, reps=3)
+        assert ms.size == 3 and np.all(ms > 0)
+        P = partials.cpu().numpy()
+        Z, YF = d_z.cpu().numpy(), d_yf.cpu().numpy()
+        for i in range(64):
+            lo, hi = int(off[i]), int(off[i]) + int(n[i])
+            if ops[i] == lk.OP_AFFINE_SUM_I32:
+                yr, sr = oracle.affine_sum_i32(xi[lo:hi].copy(), int(ab[i, 0]), int(ab[i, 1]))
+                assert int(P[owner == i].sum()) == sr, (policy, i)
+                assert np.array_equal(Z[lo:hi], yr), (policy, i)
+            else:
+                want = yf[lo:hi].copy()
+                for _ in range(3):
+                    oracle.saxpy_f32(alpha[i], xf[lo:hi].copy(), want)
+                assert np.array_equal(YF[lo:hi].view(np.uint32), want.view(np.uint32)), (policy, i)
+
+
+def test_batches_in_flight_two_deep_keep_their_own_counters():
+    ops, n, ab, alpha, off, xi, xf, yf = _burst(16, 12)
+    ops[:] = lk.OP_AFFINE_SUM_I32
+    say("batch: two different batches in flight on one cluster (depth 2), 5 rounds")
+    d_xi = to_dev(xi)
+    d_z1, d_z2 = sentinel_i32(xi.shape), sentinel_i32(xi.shape)
+    plans = []
+    for d_z, shift in ((d_z1, 0), (d_z2, 1)):
+        items = lk.make_items(ops, n, addr(d_xi) + off[:-1].astype(np.uint64) * 4,
+                              addr(d_z) + off[:-1].astype(np.uint64) * 4, ab[:, 0].astype(np.int64) + shift, ab[:, 1])
+        tiles, owner = lk.batch_plan(items, 1024)
+        plans.append((torch.from_numpy(tiles.view(np.uint8)).to("cuda"), tiles.size, owner,
+                      torch.zeros(tiles.size, dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, depth=2, idle_timeout_ms=20000) as ctx:
+        for _ in range(5):
+            t1 = ctx.submit_batch(0, plans[0][0], plans[0][1], plans[0][3])
+            t2 = ctx.submit_batch(0, plans[1][0], plans[1][1], plans[1][3])
+            assert ctx.wait(0, t1) == plans[0][1]
+            assert ctx.wait(0, t2) == plans[1][1]
+    for (dt, nt, owner, part), d_z, shift in zip(plans, (d_z1, d_z2), (0, 1)):
+        P, Z = part.cpu().numpy(), d_z.cpu().numpy()
+        for i in range(16):
+            lo, hi = int(off[i]), int(off[i]) + int(n[i])
+            yr, sr = oracle.affine_sum_i32(xi[lo:hi].copy(), lk._i32(int(ab[i, 0]) + shift), int(ab[i, 1]))
+            assert int(P[owner == i].sum()) == sr and np.array_equal(Z[lo:hi], yr)
+
+
+def test_launch_burst_baseline_matches_oracle():
+    ops, n, ab, alpha, off, xi, xf, yf = _burst(32, 13)
+    say("launch burst: 32 uneven items as per-item launches and as a captured graph")
+    for graph in (False, True):
+        d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf.copy())
+        d_z = sentinel_i32(xi.shape)
+        ins = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_xi), addr(d_xf)) + off[:-1].astype(np.uint64) * 4
+        outs = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_z), addr(d_yf)) + off[:-1].astype(np.uint64) * 4
+        items = lk.make_items(ops, n, ins.astype(np.uint64), outs.astype(np.uint64), ab[:, 0], ab[:, 1], alpha)
+        ms = lk.launch_burst(items, elems_per_wg=4096, graph=graph, reps=2)
+        assert np.all(ms > 0)
+        Z, YF = d_z.cpu().numpy(), d_yf.cpu().numpy()
+        for i in range(32):
+            lo, hi = int(off[i]), int(off[i]) + int(n[i])
+            if ops[i] == lk.OP_AFFINE_SUM_I32:
+                assert np.array_equal(Z[lo:hi], oracle.affine_sum_i32(xi[lo:hi].copy(), int(ab[i, 0]), int(ab[i, 1]))[0])
+            else:
+                want = yf[lo:hi].copy()
+                for _ in range(2):
+                    oracle.saxpy_f32(alpha[i], xf[lo:hi].copy(), want)
+                assert np.array_equal(YF[lo:hi].view(np.uint32), want.view(np.uint32)), (graph, i)
