@@ -101,11 +101,15 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=1000, help="items per mailbox in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=1024)
-    ap.add_argument("--workload", choices=["allcu", "isolation", "replay", "batching"], default="allcu",
+    ap.add_argument("--workload", choices=["allcu", "isolation", "replay", "batching", "serving"], default="allcu",
                     help="allcu: the headline all-CU workload; isolation: cluster 0 critical "
                          "item every period beside streaming copies on the other XCDs; replay: the "
                          "paper's phase protocol with its compute-only item")
     ap.add_argument("--runs", type=int, default=100, help="replay: runs per configuration")
+    ap.add_argument("--rates", type=str, default="10000,100000,1000000", help="serving: arrival rates (req/s)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving: trace length per rate")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: device-memory budget for outputs")
+    ap.add_argument("--tile", type=int, default=65536, help="serving: elements per tile")
     ap.add_argument("--bursts", type=str, default="1,4,16,64,256,1024,4096", help="batching: burst sizes")
     ap.add_argument("--burst-reps", type=int, default=5, help="batching: timed repetitions per burst")
     ap.add_argument("--spin-iters", type=int, default=20000, help="replay: loop iterations of the item")
@@ -129,6 +133,8 @@ def main():
         return bench_replay(args)
     if args.workload == "batching":
         return bench_batching(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     return bench_allcu(args)
 
 
@@ -196,7 +202,10 @@ def bench_batching(args):
     ctxs = {}
 
     def ctx_for(sleep):
+        # one context at a time: each holds every CU until it is closed
         if sleep not in ctxs:
+            for old in list(ctxs):
+                ctxs.pop(old).close()
             ctxs[sleep] = lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=sleep, idle_timeout_ms=120000)
         return ctxs[sleep]
 
@@ -247,6 +256,78 @@ def bench_batching(args):
     out["roofline"] = {"bound": "hbm", "achieved": big["persistent"]["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac": round(big["persistent"]["gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
                        "kernel": "lk_worker (one batch)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Serving with continuous batching: Poisson arrivals of mixed requests (40% int32
+    affine + sum, 30% int64 sum, 30% fp32 SAXPY written out of place), log-uniform
+    256 .. 2^22 elements, inputs resident in device pools, outputs admitted against a
+    device-memory budget; latency is arrival to completion observed."""
+    import torch
+    import oracle
+    from paper_2310_01212_amd import lk, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lk.lib()
+    oracle.build(force=False)
+    dev = torch.device("cuda:0")
+    rates = [float(v) for v in args.rates.split(",")]
+    pool_elems = 1 << 26
+    log(f"serving: pools of {pool_elems} elements, budget {args.budget_gib} GiB")
+    xi, xf = workloads.device_arena(pool_elems, seed=7, device=dev)
+    yf = workloads.device_arena(pool_elems, seed=8, device=dev)[1]
+    budget = int(args.budget_gib * (1 << 30)) // 256 * 256
+    arena = torch.empty(budget // 4, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    xi_host = xi.cpu().numpy()
+    out = {"metric": "request latency p50/p99/p99.9/max (µs) and items/s under Poisson arrivals",
+           "unit": "items/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int32/int64/f32",
+           "data": "synthetic (seeded, seed 7)", "steps": len(rates), "warmup": 0, "scaling": "weak",
+           "vs_baseline": None,
+           "config": {"workload": "serving with continuous batching: mixed requests (40% affine+sum, 30% sum, 30% "
+                                  "SAXPY), log-uniform 256..2^22 elements, Poisson arrivals, outputs admitted against "
+                                  f"a {args.budget_gib} GiB device-memory budget", "seconds_per_rate": args.serve_seconds,
+                      "tile_elems": args.tile, "host_threads": args.threads},
+           "rates": {}}
+    with lk.Context(n_workers=0, depth=4, idle_timeout_ms=600000) as ctx:
+        for rate in rates:
+            tr = workloads.serving(rate, args.serve_seconds, pool_elems, seed=7)
+            kind = tr["kind"]
+            req = np.zeros(kind.size, lk.REQUEST_DTYPE)
+            req["arrival_us"] = tr["arrival_us"]
+            req["op"] = np.choose(kind, [lk.OP_AFFINE_SUM_I32, lk.OP_SUM_I32_I64, lk.OP_AXPY_F32])
+            req["a"], req["b"], req["alpha"], req["n"] = tr["ab"][:, 0], tr["ab"][:, 1], tr["alpha"], tr["n"]
+            req["inp"] = np.where(kind == 2, xf.data_ptr(), xi.data_ptr()).astype(np.uint64) + tr["off_x"] * 4
+            req["in2"] = np.where(kind == 2, yf.data_ptr() + tr["off_y"].astype(np.int64) * 4, 0).astype(np.uint64)
+            log(f"serving: {rate:.0f} req/s, {kind.size} requests")
+            outc, st = ctx.serve(req, arena, budget, tile_elems=args.tile, threads=args.threads, timeout=30.0)
+            lat = outc["done_us"] - tr["arrival_us"]
+            n = tr["n"].astype(np.float64)
+            nbytes = float(np.sum(np.where(kind == 0, 8 * n + 8, np.where(kind == 1, 4 * n + 8, 12 * n))))
+            row = {"requests": int(kind.size), "latency_us": lat_summary(lat),
+                   "queue_us": lat_summary(outc["admit_us"] - tr["arrival_us"]),
+                   "items_per_s": round(kind.size / st["elapsed_s"], 1),
+                   "achieved_gbps": round(nbytes / st["elapsed_s"] / 1e9, 1),
+                   "offered_gbps": round(nbytes / (tr["arrival_us"][-1] * 1e-6) / 1e9, 1),
+                   "tiles": int(st["tiles"]), "deferred": int(st["deferred"]),
+                   "peak_output_bytes": int(st["peak_bytes"])}
+            # spot parity of int64 results against the oracle
+            sample = np.flatnonzero(kind != 2)[:: max(1, int(np.sum(kind != 2)) // 40)][:40]
+            bad = 0
+            for i in sample:
+                ox, nn = int(tr["off_x"][i]), int(tr["n"][i])
+                xs = xi_host[ox:ox + nn].copy()
+                want = (oracle.affine_sum_i32(xs, int(tr["ab"][i, 0]), int(tr["ab"][i, 1]))[1] if kind[i] == 0
+                        else oracle.sum_i32_i64(xs))
+                bad += int(outc["result"][i] != want)
+            row["sampled_result_mismatches"] = bad
+            out["rates"][str(int(rate))] = row
+            log(f"  p50 {row['latency_us']['p50']} us p99 {row['latency_us']['p99']} us, "
+                f"{row['items_per_s']:,.0f} items/s, {row['achieved_gbps']} GB/s")
+    top = out["rates"][str(int(max(rates)))]
+    out["value"] = top["items_per_s"]
+    out["ms_per_step"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,9 @@ enum {
  *                       benchmark item, Sec. 3); no memory effect; result 0.
  *  LK_OP_BATCH          many items in one dispatch: submitted only through
  *                       lk_submit_batch (see "batches" below).
+ *  LK_OP_AXPY_F32       in = x (float[n]), aux = y (float[n], device address), out = result
+ *                       (float[n]): out[i] = fmaf(alpha, x[i], y[i]); x and y are only read
+ *                       (the out-of-place form of SAXPY, for inputs shared between items).
  */
 enum {
   LK_OP_NOP = 0,
@@ -81,7 +84,8 @@ enum {
   LK_OP_COPY_F32 = 4,
   LK_OP_SPIN = 5,
   LK_OP_BATCH = 6,
-  LK_OP_COUNT = 7
+  LK_OP_AXPY_F32 = 7,
+  LK_OP_COUNT = 8
 };
 
 /* Descriptor of one work item, copied by value at submission (Sec. 1: "a descriptor of
@@ -93,8 +97,9 @@ typedef struct lk_desc {
   int32_t a, b;       /* AFFINE_SUM_I32 coefficients; SPIN: a = iterations */
   float alpha;        /* SAXPY_F32 coefficient */
   uint32_t reserved;  /* must be 0 */
-  uint64_t aux;       /* optional device int64* with one entry per cluster member:
-                         member j writes its partial result to aux[j]; 0 = none */
+  uint64_t aux;       /* AFFINE_SUM_I32 / SUM_I32_I64: optional device int64* with one entry
+                         per cluster member (member j writes its partial result to aux[j]),
+                         0 = none; AXPY_F32: the device address of y (required) */
   uint64_t user_tag;  /* opaque to the library; not interpreted */
 } lk_desc;
 
@@ -184,16 +189,20 @@ LK_API int lk_wait(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int64_t timeo
  * single persistent dispatch.  Tile t runs op `op` over n elements of in/out (the same
  * bodies and layouts as the single-item ops; NOP, AFFINE_SUM_I32, SUM_I32_I64,
  * SAXPY_F32, COPY_F32 or SPIN) and writes its int64 result to partials[t].
- * lk_batch_plan cuts items into such tiles. */
+ * lk_batch_plan cuts items into such tiles (for AXPY_F32 items, in_addr/out_addr are x and
+ * the result, and the item's aux field is y). */
 typedef struct lk_tile {
   uint64_t in, out;   /* device addresses of the tile's first element (4-byte aligned) */
+  uint64_t in2;       /* AXPY_F32: y of the tile; 0 otherwise */
   uint32_t n;         /* elements in the tile */
   uint32_t op;        /* LK_OP_* of the tile (not BATCH) */
   int32_t a;          /* AFFINE_SUM_I32 a; SPIN iterations */
-  uint32_t b;         /* AFFINE_SUM_I32 b, or the bits of SAXPY_F32 alpha */
-} lk_tile; /* 32 bytes */
+  uint32_t b;         /* AFFINE_SUM_I32 b, or the bits of SAXPY_F32 / AXPY_F32 alpha */
+  uint64_t reserved;
+} lk_tile; /* 48 bytes */
 
-/* Trigger phase for a batch: `tiles` is a device array of n_tiles lk_tile records and
+/* Trigger phase for a batch: `tiles` is a 16-byte aligned device array of n_tiles lk_tile
+ * records and
  * `partials` a device or host-coherent int64 array of n_tiles entries; both must stay
  * untouched until lk_wait returns for the ticket.  lk_wait's result is the number of
  * tiles executed (n_tiles), summed over the members.  Errors as lk_submit. */

@@ -34,13 +34,14 @@
 extern "C" {
 #endif
 
-/* One work item with its in/out references (40 bytes). */
+/* One work item with its in/out references (48 bytes). */
 typedef struct lkb_item {
   uint32_t op;      /* LK_OP_* */
   int32_t a, b;     /* AFFINE_SUM_I32 coefficients; SPIN: a = iterations */
-  float alpha;      /* SAXPY_F32 */
+  float alpha;      /* SAXPY_F32 / AXPY_F32 */
   uint64_t n;       /* elements */
   uint64_t in, out; /* device addresses */
+  uint64_t in2;     /* AXPY_F32: device address of y; 0 otherwise */
 } lkb_item;
 
 /* Submit-then-wait each item on `cluster` in order (the paper's Trigger then Wait).

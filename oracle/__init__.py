@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32 = 0, 1, 2, 3, 4
+NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, AXPY_F32 = 0, 1, 2, 3, 4, 7
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",
           "-shared", "-fPIC"]
@@ -45,7 +45,7 @@ def build(force=True):
 class _Item(ctypes.Structure):
     _fields_ = [("op", ctypes.c_uint32), ("n", ctypes.c_uint64), ("a", ctypes.c_int32),
                 ("b", ctypes.c_int32), ("alpha", ctypes.c_float), ("inp", ctypes.c_void_p),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("in2", ctypes.c_void_p)]
 
 
 _lib = None
@@ -64,6 +64,8 @@ def lib():
         L.orc_sum_i32_i64.restype = ctypes.c_int64
         L.orc_saxpy_f32.argtypes = [P, P, ctypes.c_uint64, ctypes.c_float]
         L.orc_saxpy_f32.restype = None
+        L.orc_axpy_f32.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_float]
+        L.orc_axpy_f32.restype = None
         L.orc_copy_f32.argtypes = [P, P, ctypes.c_uint64]
         L.orc_copy_f32.restype = None
         L.orc_slice.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -115,6 +117,18 @@ def saxpy_f32(alpha, x, y):
     return y
 
 
+def axpy_f32(alpha, x, y, out=None):
+    """out <- fmaf(alpha, x, y), y unchanged."""
+    _check(x, np.float32)
+    _check(y, np.float32)
+    assert x.size == y.size
+    if out is None:
+        out = np.empty_like(y)
+    _check(out, np.float32)
+    lib().orc_axpy_f32(_ptr(x), _ptr(y), _ptr(out), x.size, float(np.float32(alpha)))
+    return out
+
+
 def copy_f32(src, dst=None):
     _check(src, np.float32)
     if dst is None:
@@ -130,14 +144,14 @@ def slice_bounds(n, k, j):
     return lo.value, hi.value
 
 
-def _item(op, n, a=0, b=0, alpha=0.0, inp=None, out=None):
-    return _Item(op, n, int(a), int(b), float(np.float32(alpha)), _ptr(inp), _ptr(out))
+def _item(op, n, a=0, b=0, alpha=0.0, inp=None, out=None, in2=None):
+    return _Item(op, n, int(a), int(b), float(np.float32(alpha)), _ptr(inp), _ptr(out), _ptr(in2))
 
 
-def exec_item(op, inp=None, out=None, a=0, b=0, alpha=0.0, n=None):
+def exec_item(op, inp=None, out=None, a=0, b=0, alpha=0.0, n=None, in2=None):
     if n is None:
         n = (inp if inp is not None else out).size
-    it = _item(op, n, a, b, alpha, inp, out)
+    it = _item(op, n, a, b, alpha, inp, out, in2)
     return int(lib().orc_exec(ctypes.byref(it)))
 
 
@@ -157,7 +171,7 @@ def run_fifo(items):
             src = d.get("inp") if d.get("inp") is not None else d.get("out")
             n = 0 if src is None else src.size
         arr[i] = _item(d["op"], n, d.get("a", 0), d.get("b", 0), d.get("alpha", 0.0),
-                       d.get("inp"), d.get("out"))
+                       d.get("inp"), d.get("out"), d.get("in2"))
     res = np.zeros(len(items), dtype=np.int64)
     rc = lib().orc_run_fifo(arr, len(items), _ptr(res))
     if rc != 0:

@@ -35,6 +35,11 @@ void orc_saxpy_f32(const float *x, float *y, uint64_t n, float alpha) {
   for (uint64_t i = 0; i < n; i++) y[i] = fmaf(alpha, x[i], y[i]);
 }
 
+/* Work-item body "fp32 AXPY, out of place": as SAXPY, with y and the result apart. */
+void orc_axpy_f32(const float *x, const float *y, float *out, uint64_t n, float alpha) {
+  for (uint64_t i = 0; i < n; i++) out[i] = fmaf(alpha, x[i], y[i]);
+}
+
 /* Work-item body "fp32 copy". */
 void orc_copy_f32(const float *in, float *out, uint64_t n) {
   for (uint64_t i = 0; i < n; i++) out[i] = in[i];
@@ -71,6 +76,9 @@ static int64_t exec_range(const orc_item *it, uint64_t lo, uint64_t hi) {
     case ORC_COPY_F32:
       orc_copy_f32((const float *)it->in + lo, (float *)it->out + lo, len);
       return 0;
+    case ORC_AXPY_F32:
+      orc_axpy_f32((const float *)it->in + lo, (const float *)it->in2 + lo, (float *)it->out + lo, len, it->alpha);
+      return 0;
     default:
       return 0;
   }
@@ -93,7 +101,7 @@ int64_t orc_exec_cluster(const orc_item *it, uint32_t k) {
  * each exactly once. */
 int orc_run_fifo(const orc_item *items, uint64_t count, int64_t *results) {
   for (uint64_t i = 0; i < count; i++) {
-    if (items[i].op > ORC_COPY_F32) return -1;
+    if (items[i].op > ORC_COPY_F32 && items[i].op != ORC_AXPY_F32) return -1;
     int64_t r = orc_exec(&items[i]);
     if (results) results[i] = r;
   }

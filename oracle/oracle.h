@@ -27,7 +27,8 @@ extern "C" {
 #endif
 
 /* Work-item operation identifiers as the oracle numbers them (its own numbering). */
-enum { ORC_NOP = 0, ORC_AFFINE_SUM_I32 = 1, ORC_SUM_I32_I64 = 2, ORC_SAXPY_F32 = 3, ORC_COPY_F32 = 4 };
+enum { ORC_NOP = 0, ORC_AFFINE_SUM_I32 = 1, ORC_SUM_I32_I64 = 2, ORC_SAXPY_F32 = 3, ORC_COPY_F32 = 4,
+       ORC_AXPY_F32 = 7 };
 
 /* y[i] = (a*x[i] + b) mod 2^32, read as two's complement; returns sum of (int64)y[i]. */
 int64_t orc_affine_sum_i32(const int32_t *x, int32_t *y, uint64_t n, int32_t a, int32_t b);
@@ -35,6 +36,9 @@ int64_t orc_affine_sum_i32(const int32_t *x, int32_t *y, uint64_t n, int32_t a, 
 int64_t orc_sum_i32_i64(const int32_t *x, uint64_t n);
 /* y[i] = fmaf(alpha, x[i], y[i]): one binary32 fused multiply-add, round to nearest even. */
 void orc_saxpy_f32(const float *x, float *y, uint64_t n, float alpha);
+/* out[i] = fmaf(alpha, x[i], y[i]): the same single fused multiply-add with y read from
+ * its own buffer and the result written to a third one. */
+void orc_axpy_f32(const float *x, const float *y, float *out, uint64_t n, float alpha);
 /* out[i] = in[i], bit for bit. */
 void orc_copy_f32(const float *in, float *out, uint64_t n);
 
@@ -50,6 +54,7 @@ typedef struct {
   float alpha;
   const void *in;
   void *out;
+  const void *in2;  /* AXPY_F32: y */
 } orc_item;
 
 /* Execute one item over its whole range; returns its int64 result (0 for ops without one). */

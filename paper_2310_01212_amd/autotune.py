@@ -28,17 +28,20 @@ def pick_best(timings):
 
 def tune(run_burst, sizes, tiles=TILE_CANDIDATES, sleeps=SLEEP_CANDIDATES, reps=5):
     """run_burst(size, tile, sleep, reps) -> list of makespans (us) of a training burst.
-    Returns {size: {"tile": t, "poll_sleep": s, "median_us": m, "grid": {...}}}."""
+    The polling interval is a property of a running context, so it is the outermost loop
+    (one context per interval).  Returns {size: {"tile": t, "poll_sleep": s,
+    "median_us": m, "grid": {...}}}."""
+    timings = {size: {} for size in sizes}
+    for sleep in sleeps:
+        for size in sizes:
+            for tile in tiles:
+                timings[size][(tile, sleep)] = list(run_burst(size, tile, sleep, reps))
     table = {}
     for size in sizes:
-        timings = {}
-        for sleep in sleeps:
-            for tile in tiles:
-                timings[(tile, sleep)] = list(run_burst(size, tile, sleep, reps))
-        tile, sleep = pick_best(timings)
+        tile, sleep = pick_best(timings[size])
         table[int(size)] = {"tile": int(tile), "poll_sleep": int(sleep),
-                            "median_us": float(np.median(timings[(tile, sleep)])),
-                            "grid": {f"{t}/{s}": float(np.median(v)) for (t, s), v in timings.items()}}
+                            "median_us": float(np.median(timings[size][(tile, sleep)])),
+                            "grid": {f"{t}/{s}": float(np.median(v)) for (t, s), v in timings[size].items()}}
     return table
 
 

@@ -52,12 +52,13 @@ lk_desc to_desc(const lkb_item &it) {
   d.a = it.a;
   d.b = it.b;
   d.alpha = it.alpha;
+  d.aux = it.op == LK_OP_AXPY_F32 ? it.in2 : 0;
   return d;
 }
 
 bool valid_item(const lkb_item &it) {
   if (it.op >= LK_OP_COUNT) return false;
-  if ((it.in | it.out) & 3u) return false;
+  if ((it.in | it.out | it.in2) & 3u) return false;
   return true;
 }
 
@@ -129,6 +130,7 @@ lkd::ItemArgs item_args(const lkb_item &it, uint32_t k) {
   a.n = it.n;
   a.in = reinterpret_cast<const void *>(it.in);
   a.out = reinterpret_cast<void *>(it.out);
+  a.in2 = reinterpret_cast<const void *>(it.in2);
   a.a = static_cast<uint32_t>(it.a);
   a.b = static_cast<uint32_t>(it.b);
   a.alpha = it.alpha;

@@ -11,17 +11,19 @@
 
 namespace lkd {
 
-constexpr uint32_t kOpCount = 7;  // NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN, BATCH
+constexpr uint32_t kOpCount = 8;  // NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN, BATCH, AXPY_F32
 constexpr uint32_t kOpBatch = 6;
+constexpr uint32_t kOpAxpy = 7;
 
 // Tile record of a batch (same layout as lk_tile in lk.h).
 struct Tile {
-  uint64_t in, out;
+  uint64_t in, out, in2;
   uint32_t n, op;
   int32_t a;
   uint32_t b;
+  uint64_t reserved;
 };
-static_assert(sizeof(Tile) == 32, "tile record is 32 bytes");
+static_assert(sizeof(Tile) == 48, "tile record is 48 bytes");
 
 // Slicing rule of a cluster item: m = ceil(n/k) rounded up to a multiple of 256 elements,
 // slice j = [min(n, j*m), min(n, (j+1)*m)).  Used by the host to cut descriptors and by
@@ -45,6 +47,7 @@ struct ItemArgs {
   uint64_t n;
   const void *in;
   void *out;
+  const void *in2;      // AXPY_F32: y
   uint32_t a, b;
   float alpha;
   uint32_t pad;

@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(1024) lk_item(lkd::ItemArgs a) {
   const uint32_t esz = 4;
   s.in = a.in ? static_cast<const char *>(a.in) + lo * esz : nullptr;
   s.out = a.out ? static_cast<char *>(a.out) + lo * esz : nullptr;
+  s.in2 = a.in2 ? static_cast<const char *>(a.in2) + lo * esz : nullptr;
   s.a = a.a;
   s.b = a.b;
   s.alpha = a.alpha;
@@ -44,13 +45,17 @@ __global__ void __launch_bounds__(1024) lk_item(lkd::ItemArgs a) {
   if (threadIdx.x == 0) {
     if (a.aux) a.aux[j] = partial;
     if (a.partials) st_sys_i64(a.partials + j, partial);
-    uint32_t last = 1;
-    if (a.k > 1) {
-      const uint32_t prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      last = prev == a.k - 1;
-      if (last) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Completion word: written once by the last workgroup to finish, found through the
+    // counter (which the launcher guarantees whenever done_word is set and k > 1).
+    if (a.done_word) {
+      uint32_t last = 1;
+      if (a.k > 1) {
+        const uint32_t prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == a.k - 1;
+        if (last) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (last) st_sys_release(a.done_word, a.done_value);
     }
-    if (last && a.done_word) st_sys_release(a.done_word, a.done_value);
   }
 }
 
@@ -105,6 +110,15 @@ namespace lkd {
 const void *item_kernel() { return reinterpret_cast<const void *>(lk_item); }
 
 hipError_t launch_item(const ItemArgs &a, uint32_t threads, hipStream_t s) {
+  // Host-side check of what the kernel assumes: k workgroups (one slice each), a counter
+  // whenever more than one workgroup must agree on who writes the completion word, and
+  // the pointers every op reads or writes.
+  if (a.k == 0 || threads == 0 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+  if (a.done_word && a.k > 1 && !a.counter) return hipErrorInvalidValue;
+  const bool reads = a.op == 1 || a.op == 2 || a.op == 3 || a.op == 4 || a.op == 7;
+  const bool writes = a.op == 1 || a.op == 3 || a.op == 4 || a.op == 7;
+  if (a.op >= kOpCount || a.op == kOpBatch) return hipErrorInvalidValue;
+  if (a.n && ((reads && !a.in) || (writes && !a.out) || (a.op == 7 && !a.in2))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(lk_item, dim3(a.k), dim3(threads), 0, s, a);
   return hipGetLastError();
 }

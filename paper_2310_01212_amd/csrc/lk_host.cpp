@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdarg>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -75,6 +77,27 @@ struct Status {
 
 inline bool exited_code(uint32_t code) { return code == LKW_FROM_EXITED || code == LKW_FROM_TIMEDOUT; }
 
+// Workers of the live persistent dispatches of this process, per device.  Every worker
+// holds a whole CU until its dispatch ends, so a context that would need more CUs than
+// are left can never boot: lk_init refuses it at once instead of timing out.
+std::mutex g_cu_mutex;
+std::map<int, uint32_t> g_cu_in_use;
+
+bool reserve_cus(int device, uint32_t n, uint32_t cu_count, uint32_t *in_use) {
+  std::lock_guard<std::mutex> lock(g_cu_mutex);
+  uint32_t &u = g_cu_in_use[device];
+  *in_use = u;
+  if (u + n > cu_count) return false;
+  u += n;
+  return true;
+}
+
+void release_cus(int device, uint32_t n) {
+  std::lock_guard<std::mutex> lock(g_cu_mutex);
+  uint32_t &u = g_cu_in_use[device];
+  u = u >= n ? u - n : 0;
+}
+
 }  // namespace
 
 struct lk_ctx {
@@ -100,6 +123,7 @@ struct lk_ctx {
   std::vector<uint32_t> cluster_of_mbox;
   std::vector<lkw_log> host_log;                    // copied at dispose
   double init_ms = 0, dispose_ms = 0, kernel_ms = 0, device_span_ms = 0;
+  bool cus_reserved = false;  // counted in g_cu_in_use until the dispatch has ended
   bool kernel_launched = false;
   uint32_t exited_at_dispose = 0;
 };
@@ -151,8 +175,14 @@ void post_cmd(lk_ctx *c, uint32_t mb, uint64_t seq, uint32_t code, uint64_t n, u
   store_release(&s->w[LKW_W_DOORBELL], LKW_WORD(seq, code));
 }
 
-bool op_reads(uint32_t op) { return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32; }
-bool op_writes(uint32_t op) { return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32; }
+bool op_reads(uint32_t op) {
+  return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32 ||
+         op == LK_OP_AXPY_F32;
+}
+bool op_writes(uint32_t op) {
+  return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SAXPY_F32 || op == LK_OP_COPY_F32 || op == LK_OP_AXPY_F32;
+}
+bool op_has_result(uint32_t op) { return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64; }
 
 int validate_config(const lk_config *cfg) {
   if (!cfg) return fail(LK_EINVAL, "config is NULL");
@@ -186,6 +216,8 @@ int validate_config(const lk_config *cfg) {
 
 // Only called once the persistent dispatch has ended (or was never made).
 void release_gpu(lk_ctx *c) {
+  if (c->cus_reserved) release_cus(c->device, c->n_workers);
+  c->cus_reserved = false;
   c->wq.close();
   if (c->d_batch_counters) (void)hipFree(c->d_batch_counters);
   c->d_batch_counters = nullptr;
@@ -279,6 +311,15 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   if (c->n_workers > c->cu_count || c->n_workers > LK_MAX_WORKERS) {
     delete c;
     return fail(LK_EINVAL, "n_workers %u exceeds the %u CUs", cfg.n_workers, c->cu_count);
+  }
+  {
+    uint32_t in_use = 0;
+    if (!reserve_cus(cfg.device, c->n_workers, c->cu_count, &in_use)) {
+      delete c;
+      return fail(LK_ENODEV, "%u workers requested but this process's running contexts already hold %u of the %u CUs",
+                  cfg.n_workers ? cfg.n_workers : c->cu_count, in_use, c->cu_count);
+    }
+    c->cus_reserved = true;
   }
   int wc_khz = 0;
   if (hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, cfg.device) == hipSuccess && wc_khz > 0)
@@ -467,7 +508,11 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   if (d->n && op_reads(d->op) && (!in || (ia & 3u))) return fail(LK_EINVAL, "input pointer NULL or not 4-byte aligned");
   if (d->n && op_writes(d->op) && (!out || (oa & 3u))) return fail(LK_EINVAL, "output pointer NULL or not 4-byte aligned");
   if ((ia | oa | d->aux) >> LKW_TAG_SHIFT) return fail(LK_EINVAL, "pointer outside the 48-bit address range");
-  if (d->aux & 7u) return fail(LK_EINVAL, "aux not 8-byte aligned");
+  if (d->op == LK_OP_AXPY_F32) {
+    if (d->n && (!d->aux || (d->aux & 3u))) return fail(LK_EINVAL, "AXPY_F32 needs y (aux) 4-byte aligned");
+  } else if (d->aux & 7u) {
+    return fail(LK_EINVAL, "aux not 8-byte aligned");
+  }
   if (d->op == LK_OP_SPIN && d->a < 0) return fail(LK_EINVAL, "SPIN iterations < 0");
 
   const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
@@ -484,7 +529,9 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
     lkd::slice_bounds(d->n, k, j, &lo, &hi);
     const uint64_t sin = (op_reads(d->op) && in) ? ia + lo * esz : 0;
     const uint64_t sout = (op_writes(d->op) && out) ? oa + lo * esz : 0;
-    const uint64_t saux = d->aux ? d->aux + 8ull * j : 0;
+    uint64_t saux = 0;
+    if (d->aux && op_has_result(d->op)) saux = d->aux + 8ull * j;
+    if (d->aux && d->op == LK_OP_AXPY_F32) saux = d->aux + lo * esz;
     post_cmd(c, mbs[j], t, LKW_TO_WORK + d->op, hi - lo, sin, sout, saux, static_cast<uint32_t>(d->a),
              static_cast<uint32_t>(d->b), d->alpha, j);
   }
@@ -538,13 +585,17 @@ int lk_batch_plan(const lk_desc *items, const uint64_t *in_addr, const uint64_t 
     const lk_desc &d = items[i];
     uint32_t bbits;
     memcpy(&bbits, &d.alpha, 4);
-    if (d.op != LK_OP_SAXPY_F32) bbits = static_cast<uint32_t>(d.b);
+    if (d.op != LK_OP_SAXPY_F32 && d.op != LK_OP_AXPY_F32) bbits = static_cast<uint32_t>(d.b);
+    if (d.op == LK_OP_AXPY_F32 && (d.n && (!d.aux || (d.aux & 3u))))
+      return fail(LK_EINVAL, "item %u: AXPY_F32 needs y (aux) 4-byte aligned", i);
     const uint64_t parts = d.n == 0 ? 1 : (d.n + tile_elems - 1) / tile_elems;
     for (uint64_t p = 0; p < parts; ++p) {
       const uint64_t lo = p * tile_elems, len = std::min<uint64_t>(tile_elems, d.n - std::min(d.n, lo));
       lk_tile &tl = tiles[k];
       tl.in = op_reads(d.op) ? in_addr[i] + lo * 4 : 0;
       tl.out = op_writes(d.op) ? out_addr[i] + lo * 4 : 0;
+      tl.in2 = d.op == LK_OP_AXPY_F32 ? d.aux + lo * 4 : 0;
+      tl.reserved = 0;
       tl.n = static_cast<uint32_t>(len);
       tl.op = d.op;
       tl.a = d.a;

@@ -41,6 +41,7 @@ struct Slice {
   uint64_t n;
   const void *in;
   void *out;
+  const void *in2;  // AXPY_F32: y
   uint32_t a, b;
   float alpha;
 };
@@ -228,6 +229,40 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
   for (uint64_t i = done + tid; i < n; i += nt) st.put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
 }
 
+// out[i] = fma(alpha, x[i], y[i]): SAXPY with y read from its own buffer.
+template <class St>
+__device__ __forceinline__ void axpy(const float *__restrict__ x, const float *__restrict__ y, float *__restrict__ out,
+                                     uint64_t n, float alpha, uint64_t nt) {
+  constexpr int U = 4;
+  const St st(out, n * 4);
+  const uint64_t tid = threadIdx.x;
+  uint64_t done = 0;
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(x) & 15u;
+  if (xa == (reinterpret_cast<uintptr_t>(y) & 15u) && xa == (reinterpret_cast<uintptr_t>(out) & 15u)) {
+    uint64_t head = ((16u - xa) & 15u) >> 2;
+    if (head > n) head = n;
+    if (tid < head) st.put(out + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
+    const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
+    const float4 *__restrict__ yv = reinterpret_cast<const float4 *>(y + head);
+    float4 *__restrict__ ov = reinterpret_cast<float4 *>(out + head);
+    const uint64_t nv = (n - head) >> 2;
+    uint64_t k = tid;
+    for (; k + (U - 1) * nt < nv; k += U * nt) {
+      float4 rx[U], ry[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rx[u] = xv[k + u * nt];
+        ry[u] = yv[k + u * nt];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) st.put(ov + k + u * nt, fma4(alpha, rx[u], ry[u]));
+    }
+    for (; k < nv; k += nt) st.put(ov + k, fma4(alpha, xv[k], yv[k]));
+    done = head + nv * 4;
+  }
+  for (uint64_t i = done + tid; i < n; i += nt) st.put(out + i, __builtin_fmaf(alpha, x[i], y[i]));
+}
+
 // out[i] = in[i] as raw 32-bit words.
 template <class St>
 __device__ __forceinline__ void copy32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
@@ -291,6 +326,10 @@ __device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uin
           break;
         case 4:  // COPY_F32
           copy32<St>(static_cast<const uint32_t *>(s.in) + off, static_cast<uint32_t *>(s.out) + off, len, nt);
+          break;
+        case 7:  // AXPY_F32
+          axpy<St>(static_cast<const float *>(s.in) + off, static_cast<const float *>(s.in2) + off,
+                   static_cast<float *>(s.out) + off, len, s.alpha, nt);
           break;
         default:
           break;

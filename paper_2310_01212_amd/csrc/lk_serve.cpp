@@ -1,0 +1,257 @@
+/*
+ * lk_serve.cpp -- continuous-batching serving loop over the persistent workers
+ * (include/lk_serve.h).
+ */
+#include "lk_serve.h"
+
+#include <immintrin.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "lk.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+constexpr uint64_t kGranule = 256;  // bytes; output buffers start 256-byte aligned
+
+// First-fit allocator over one shard's slice of the arena (offsets in bytes).
+class Arena {
+ public:
+  Arena(uint64_t base, uint64_t size) : base_(base), size_(size) {
+    if (size) free_[0] = size;
+  }
+  // Returns false if no free block is large enough.
+  bool alloc(uint64_t bytes, uint64_t *addr) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const uint64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        *addr = base_ + off;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t addr, uint64_t bytes) {
+    bytes = round(bytes);
+    uint64_t off = addr - base_;
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  uint64_t size() const { return size_; }
+  uint64_t peak() const { return peak_; }
+  static uint64_t round(uint64_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
+
+ private:
+  uint64_t base_, size_, used_ = 0, peak_ = 0;
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
+
+bool op_allowed(uint32_t op) {
+  return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64 || op == LK_OP_AXPY_F32 || op == LK_OP_COPY_F32;
+}
+uint64_t out_bytes(const lks_request &r) { return r.op == LK_OP_SUM_I32_I64 ? 0 : r.n * 4; }
+
+struct Tile {
+  uint64_t req;  // request index
+  uint64_t lo, len;
+};
+
+struct Active {
+  uint64_t remaining = 0;
+  int64_t sum = 0;
+  uint64_t out = 0;
+};
+
+struct Posted {
+  uint64_t ticket;
+  uint64_t req;
+  clk::time_point t_post;
+};
+
+}  // namespace
+
+extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs, uint64_t count, lks_outcome *out,
+                       lks_stats *stats) {
+  if (!c || !cfg || (!reqs && count) || (!out && count)) return LK_EINVAL;
+  lk_info info;
+  if (lk_get_info(c, &info) != LK_OK || info.state != 0) return LK_ESTATE;
+  if (info.n_clusters != info.n_workers) return LK_EINVAL;  // needs one cluster per worker
+  const uint32_t T = cfg->threads;
+  if (T == 0 || T > 64 || T > info.n_workers) return LK_EINVAL;
+  if (cfg->tile_elems == 0 || cfg->tile_elems % 256 || cfg->tile_elems > (1ull << 31)) return LK_EINVAL;
+  if ((cfg->arena & (kGranule - 1)) || (cfg->arena_bytes && !cfg->arena)) return LK_EINVAL;
+  for (uint64_t i = 0; i < count; ++i) {
+    const lks_request &r = reqs[i];
+    if (!op_allowed(r.op) || ((r.in | r.in2) & 3u) || (r.n && !r.in) || (r.op == LK_OP_AXPY_F32 && r.n && !r.in2))
+      return LK_EINVAL;
+    if (i && r.arrival_us < reqs[i - 1].arrival_us) return LK_EINVAL;
+    out[i] = lks_outcome{0, 0, -1.0, -1.0, LK_OK, 0};
+  }
+  const uint64_t slice = cfg->arena_bytes / T / kGranule * kGranule;
+  const uint32_t depth = info.queue_depth;
+  std::atomic<int> error{LK_OK};
+  std::vector<uint64_t> tiles_done(T, 0), deferred(T, 0), peak(T, 0);
+  const auto t0 = clk::now() + std::chrono::milliseconds(2);
+  auto us_since = [&](clk::time_point t) { return std::chrono::duration<double, std::micro>(t - t0).count(); };
+
+  auto shard = [&](uint32_t s) {
+    Arena arena(cfg->arena + s * slice, slice);
+    std::vector<uint32_t> workers;
+    for (uint32_t w = s; w < info.n_workers; w += T) workers.push_back(w);
+    std::vector<std::deque<Posted>> posted(workers.size());
+    std::vector<uint64_t> mine;  // request indices of this shard, arrival order
+    for (uint64_t i = s; i < count; i += T) mine.push_back(i);
+    size_t next_arrival = 0;
+    std::deque<uint64_t> waiting;   // arrived, not admitted
+    std::deque<Tile> queue;         // tiles of admitted requests, admission order
+    std::map<uint64_t, Active> active;
+    uint64_t finished = 0;
+    uint64_t last_deferred = ~0ull;  // the waiting head already counted as deferred
+    uint32_t rr = 0;
+    auto fail = [&](int rc) {
+      int expected = LK_OK;
+      error.compare_exchange_strong(expected, rc);
+    };
+    while (finished < mine.size() && error.load(std::memory_order_relaxed) == LK_OK) {
+      const auto now = clk::now();
+      const double now_us = us_since(now);
+      // 1. arrivals
+      while (next_arrival < mine.size() && reqs[mine[next_arrival]].arrival_us <= now_us) waiting.push_back(mine[next_arrival++]);
+      // 2. admission, first come first served, against the shard's memory budget
+      while (!waiting.empty()) {
+        const uint64_t i = waiting.front();
+        const lks_request &r = reqs[i];
+        uint64_t addr = 0;
+        const uint64_t need = out_bytes(r);
+        if (need) {
+          if (Arena::round(need) > arena.size()) return fail(LK_EINVAL);  // can never fit
+          if (!arena.alloc(need, &addr)) {
+            // Nothing in flight in this shard means nothing will ever be freed: the
+            // budget is exhausted for good (possible only with `retain`).
+            if (active.empty()) return fail(LK_EINVAL);
+            if (i != last_deferred) {
+              ++deferred[s];
+              last_deferred = i;
+            }
+            break;
+          }
+        }
+        waiting.pop_front();
+        const uint64_t nt = r.n == 0 ? 1 : (r.n + cfg->tile_elems - 1) / cfg->tile_elems;
+        Active a;
+        a.remaining = nt;
+        a.out = addr;
+        active[i] = a;
+        out[i].admit_us = now_us;
+        out[i].out = addr;
+        out[i].tiles = static_cast<uint32_t>(nt);
+        for (uint64_t k = 0; k < nt; ++k) {
+          const uint64_t lo = k * cfg->tile_elems;
+          queue.push_back(Tile{i, lo, std::min(cfg->tile_elems, r.n - std::min(r.n, lo))});
+        }
+      }
+      // 3. completions
+      for (size_t w = 0; w < workers.size(); ++w) {
+        auto &pq = posted[w];
+        while (!pq.empty()) {
+          int fin = 0;
+          int rc = lk_poll(c, workers[w], pq.front().ticket, &fin);
+          if (rc) return fail(rc);
+          if (!fin) {
+            if (cfg->timeout_ns >= 0 && now - pq.front().t_post > std::chrono::nanoseconds(cfg->timeout_ns))
+              return fail(LK_ETIMEDOUT);
+            break;
+          }
+          int64_t part = 0;
+          rc = lk_wait(c, workers[w], pq.front().ticket, 0, &part);
+          if (rc) return fail(rc);
+          const uint64_t i = pq.front().req;
+          pq.pop_front();
+          ++tiles_done[s];
+          Active &a = active[i];
+          a.sum += part;
+          if (--a.remaining == 0) {
+            out[i].result = a.sum;
+            out[i].done_us = us_since(clk::now());
+            if (!cfg->retain && a.out) arena.release(a.out, out_bytes(reqs[i]));
+            active.erase(i);
+            ++finished;
+          }
+        }
+      }
+      // 4. dispatch: fill free mailbox slots round-robin
+      for (size_t k = 0; k < workers.size() && !queue.empty(); ++k) {
+        const size_t w = (rr + k) % workers.size();
+        while (!queue.empty() && posted[w].size() < depth) {
+          const Tile tl = queue.front();
+          const lks_request &r = reqs[tl.req];
+          lk_desc d{};
+          d.op = r.op;
+          d.n = tl.len;
+          d.a = r.a;
+          d.b = r.b;
+          d.alpha = r.alpha;
+          d.aux = r.op == LK_OP_AXPY_F32 ? r.in2 + tl.lo * 4 : 0;
+          const uint64_t in = r.in + tl.lo * 4;
+          const uint64_t o = active[tl.req].out ? active[tl.req].out + tl.lo * 4 : 0;
+          uint64_t t;
+          const int rc = lk_submit(c, workers[w], &d, reinterpret_cast<const void *>(in), reinterpret_cast<void *>(o), &t);
+          if (rc == LK_EAGAIN) break;
+          if (rc) return fail(rc);
+          posted[w].push_back(Posted{t, tl.req, clk::now()});
+          queue.pop_front();
+        }
+      }
+      rr = workers.empty() ? 0 : (rr + 1) % workers.size();
+      _mm_pause();
+    }
+    peak[s] = arena.peak();
+    // On error, drain what this shard still has posted so its workers are idle.
+    for (size_t w = 0; w < workers.size(); ++w)
+      for (const Posted &p : posted[w]) (void)lk_wait(c, workers[w], p.ticket, 2000000000ll, nullptr);
+  };
+  std::vector<std::thread> th;
+  for (uint32_t s = 0; s < T; ++s) th.emplace_back(shard, s);
+  for (auto &t : th) t.join();
+  const int rc = error.load();
+  if (stats) {
+    double last = 0;
+    for (uint64_t i = 0; i < count; ++i) last = std::max(last, out[i].done_us);
+    stats->elapsed_s = (last - (count ? reqs[0].arrival_us : 0.0)) * 1e-6;
+    stats->tiles = stats->deferred = stats->peak_bytes = 0;
+    for (uint32_t s = 0; s < T; ++s) {
+      stats->tiles += tiles_done[s];
+      stats->deferred += deferred[s];
+      stats->peak_bytes += peak[s];
+    }
+  }
+  if (rc)
+    for (uint64_t i = 0; i < count; ++i)
+      if (out[i].done_us < 0) out[i].status = rc;
+  return rc;
+}

@@ -53,7 +53,8 @@ enum {
   LKW_W_N = 1,        /* element count of this slice */
   LKW_W_IN = 2,       /* device address of the slice's input */
   LKW_W_OUT = 3,      /* device address of the slice's output */
-  LKW_W_AUX = 4,      /* device address of this member's partial-result entry, or 0 */
+  LKW_W_AUX = 4,      /* device address: this member's partial-result entry (AFFINE, SUM),
+                         the slice's y (AXPY), the tile counter (BATCH), or 0 */
   LKW_W_A = 5,        /* uint32 a | (member index << 32) */
   LKW_W_B = 6,        /* uint32 b */
   LKW_W_ALPHA = 7,    /* float alpha bits */

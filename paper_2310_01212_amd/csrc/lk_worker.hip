@@ -50,10 +50,11 @@ __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_
     uint64_t next = 0;
     if (threadIdx.x == 0) next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     lkops::Slice sl;
-    sl.op = tile.op < lkd::kOpBatch ? tile.op : 0u;
+    sl.op = (tile.op == lkd::kOpBatch || tile.op >= lkd::kOpCount) ? 0u : tile.op;  // no nested batches
     sl.n = tile.n;
     sl.in = reinterpret_cast<const void *>(tile.in);
     sl.out = reinterpret_cast<void *>(tile.out);
+    sl.in2 = reinterpret_cast<const void *>(tile.in2);
     sl.a = static_cast<uint32_t>(tile.a);
     sl.b = tile.b;
     sl.alpha = __uint_as_float(tile.b);
@@ -191,6 +192,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     s.n = s_w[LKW_W_N] & LKW_PAYLOAD_MASK;
     s.in = reinterpret_cast<const void *>(s_w[LKW_W_IN] & LKW_PAYLOAD_MASK);
     s.out = reinterpret_cast<void *>(s_w[LKW_W_OUT] & LKW_PAYLOAD_MASK);
+    s.in2 = reinterpret_cast<const void *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
     s.a = static_cast<uint32_t>(s_w[LKW_W_A]);
     s.b = static_cast<uint32_t>(s_w[LKW_W_B]);
     s.alpha = __uint_as_float(static_cast<uint32_t>(s_w[LKW_W_ALPHA]));
@@ -217,7 +219,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       s_t_done = t_done;
       s_partial = partial;
       int64_t *aux = reinterpret_cast<int64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
-      if (aux && !batch) st_sys_i64(aux, partial);
+      if (aux && (s.op == 1 || s.op == 2)) st_sys_i64(aux, partial);  // ops with an int64 result
       if (p.log) {
         lkw_log *e = p.log + static_cast<uint64_t>(m) * p.log_cap + (seq % p.log_cap);
         const uint64_t head = static_cast<uint64_t>(static_cast<uint32_t>(want)) |

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblk.so")
 
 OK, EINVAL, EAGAIN, ETIMEDOUT, ESTATE, ENODEV, EHIP, EFAULT = 0, -1, -2, -3, -4, -5, -6, -7
-OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, OP_BATCH = range(7)
+OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, OP_BATCH, OP_AXPY_F32 = range(8)
 CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
 F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
 COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
@@ -27,7 +27,7 @@ EXPORTED = [
     "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
     "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_replay", "lkb_batch", "lkb_launch_burst",
-    "lkb_launch_serial", "lkb_launch_lanes", "lkb_pingpong",
+    "lkb_launch_serial", "lks_run", "lkb_launch_lanes", "lkb_pingpong",
     "lkb_copy",
 ]
 
@@ -77,12 +77,28 @@ class LogEntry(ctypes.Structure):
                 ("t_done", ctypes.c_uint64)]
 
 
-# numpy view of lkb_item (40 bytes)
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64), ("tile_elems", ctypes.c_uint64),
+                ("threads", ctypes.c_uint32), ("retain", ctypes.c_uint32), ("timeout_ns", ctypes.c_int64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("elapsed_s", ctypes.c_double), ("tiles", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64)]
+
+
+REQUEST_DTYPE = np.dtype([("arrival_us", "<f8"), ("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4"),
+                          ("n", "<u8"), ("inp", "<u8"), ("in2", "<u8")])
+OUTCOME_DTYPE = np.dtype([("result", "<i8"), ("out", "<u8"), ("admit_us", "<f8"), ("done_us", "<f8"),
+                          ("status", "<i4"), ("tiles", "<u4")])
+
+# numpy view of lkb_item (48 bytes)
 ITEM_DTYPE = np.dtype([("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4"),
-                       ("n", "<u8"), ("inp", "<u8"), ("out", "<u8")])
+                       ("n", "<u8"), ("inp", "<u8"), ("out", "<u8"), ("in2", "<u8")])
 COMPLETION_DTYPE = np.dtype([("result", "<i8"), ("t_pick_min", "<u8"), ("t_pick_max", "<u8"),
                              ("t_done_min", "<u8"), ("t_done_max", "<u8")])
-TILE_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("n", "<u4"), ("op", "<u4"), ("a", "<i4"), ("b", "<u4")])
+TILE_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("in2", "<u8"), ("n", "<u4"), ("op", "<u4"), ("a", "<i4"),
+                       ("b", "<u4"), ("reserved", "<u8")])
 LOG_DTYPE = np.dtype([("seq", "<u4"), ("code", "<u2"), ("worker", "<u2"), ("xcc", "<u4"),
                       ("hwid", "<u4"), ("t_pick", "<u8"), ("t_done", "<u8")])
 
@@ -132,6 +148,7 @@ def lib():
         "lkb_batch": (ctypes.c_int, [P, U32, P, U32, P, U32, I64, P, P]),
         "lkb_launch_burst": (ctypes.c_int, [I32, P, U32, U64, U32, U32, U32, P]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
+        "lks_run": (ctypes.c_int, [P, ctypes.POINTER(ServeConfig), P, U64, P, ctypes.POINTER(ServeStats)]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
         "lkb_copy": (ctypes.c_int, [I32, P, P, U64, U32, U32, PD, PD]),
@@ -187,7 +204,7 @@ def _np_ptr(a):
 
 
 _OP_DTYPES = {OP_AFFINE_SUM_I32: "int32", OP_SUM_I32_I64: "int32", OP_SAXPY_F32: "float32",
-              OP_COPY_F32: "float32"}
+              OP_COPY_F32: "float32", OP_AXPY_F32: "float32"}
 
 
 def _check_tensor(t, op, what):
@@ -347,6 +364,21 @@ class Context:
     def handle(self):
         return self._h
 
+    # -- serving (lk_serve.h) ---------------------------------------------------------------
+    def serve(self, requests, arena, arena_bytes, tile_elems=65536, threads=8, retain=False, timeout=10.0):
+        """Run a request trace (REQUEST_DTYPE, sorted by arrival) with continuous batching;
+        arena = device buffer (tensor or address) of arena_bytes for request outputs.
+        Returns (OUTCOME_DTYPE array, stats dict)."""
+        requests = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE).ravel()
+        cfg = ServeConfig(_ptr(arena), int(arena_bytes), int(tile_elems), int(threads), 1 if retain else 0,
+                          int(timeout * 1e9))
+        outc = np.zeros(max(requests.size, 1), OUTCOME_DTYPE)
+        st = ServeStats()
+        rc = lib().lks_run(self._h, ctypes.byref(cfg), _np_ptr(requests), requests.size, _np_ptr(outc),
+                           ctypes.byref(st))
+        _check(rc, "lks_run")
+        return outc[:requests.size], {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
     # -- native runners (lk_bench.h) -------------------------------------------------------
     def run_serial(self, cluster, items, timeout=10.0):
         """Submit-then-wait every item (ITEM_DTYPE array) on one cluster, natively timed.
@@ -421,8 +453,9 @@ def batch_plan(items, tile_elems):
     count = items.size
     descs = (Desc * max(count, 1))()
     for i in range(count):
-        descs[i] = Desc(int(items["op"][i]), 0, int(items["n"][i]), int(items["a"][i]), int(items["b"][i]),
-                        float(items["alpha"][i]), 0, 0, 0)
+        op = int(items["op"][i])
+        descs[i] = Desc(op, 0, int(items["n"][i]), int(items["a"][i]), int(items["b"][i]),
+                        float(items["alpha"][i]), 0, int(items["in2"][i]) if op == OP_AXPY_F32 else 0, 0)
     ins = np.ascontiguousarray(items["inp"], dtype=np.uint64)
     outs = np.ascontiguousarray(items["out"], dtype=np.uint64)
     need = ctypes.c_uint32()
@@ -485,14 +518,15 @@ def copy_bandwidth(src, dst, nbytes, grid, reps=10, device=0):
     return ms.value, gbps.value
 
 
-def make_items(op, n, inp, out, a=0, b=0, alpha=0.0):
-    """Build an ITEM_DTYPE array from per-item columns (scalars broadcast)."""
+def make_items(op, n, inp, out, a=0, b=0, alpha=0.0, in2=0):
+    """Build an ITEM_DTYPE array from per-item columns (scalars broadcast).  in2 is the y
+    address of AXPY_F32 items."""
     cols = np.broadcast_arrays(np.asarray(op), np.asarray(n), np.asarray(inp, dtype=np.uint64),
                                np.asarray(out, dtype=np.uint64), np.asarray(a), np.asarray(b),
-                               np.asarray(alpha, dtype=np.float32))
+                               np.asarray(alpha, dtype=np.float32), np.asarray(in2, dtype=np.uint64))
     shape = cols[0].shape
     it = np.zeros(shape, ITEM_DTYPE)
-    it["op"], it["n"], it["inp"], it["out"] = cols[0], cols[1], cols[2], cols[3]
+    it["op"], it["n"], it["inp"], it["out"], it["in2"] = cols[0], cols[1], cols[2], cols[3], cols[7]
     it["a"] = (np.asarray(cols[4]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
     it["b"] = (np.asarray(cols[5]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
     it["alpha"] = cols[6]

@@ -15,6 +15,10 @@ ALLCU_ITEMS, ALLCU_N = 10000, 16384
 # batching: bursts of uneven items, log-uniform 256 .. 2^20 elements, affine / SAXPY 50/50
 BATCH_SIZES = (1, 4, 16, 64, 256, 1024, 4096)
 BATCH_LOG2_RANGE = (8, 20)
+# serving: Poisson arrivals, op mix 40% affine / 30% sum / 30% SAXPY, log-uniform
+# 256 .. 2^22 elements
+SERVE_RATES = (10_000, 100_000, 1_000_000)
+SERVE_LOG2_RANGE = (8, 22)
 # cluster isolation: critical int32 affine+sum over 262,144 elements, 1 ms period;
 # interference: 256 MiB fp32 copies on the other clusters
 ISO_N, ISO_PERIOD_S, ISO_COPY_ELEMS = 262144, 1e-3, (256 << 20) // 4
@@ -84,3 +88,23 @@ def device_arena(elems, seed, device="cuda"):
     x = torch.randint(-2 ** 31, 2 ** 31 - 1, (elems,), generator=g, device=device, dtype=torch.int32)
     y = torch.randn(elems, generator=g, device=device, dtype=torch.float32)
     return x, y
+
+
+def serving(rate, seconds, pool_elems, seed=7, log2_range=SERVE_LOG2_RANGE, max_requests=None):
+    """Poisson request trace: arrival times (us) with exponential inter-arrival 1/rate,
+    op choice [affine + sum, sum, SAXPY] with p = [.4, .3, .3], n = round(2**U(lo, hi)),
+    input windows at uniform 256-aligned offsets inside a resident pool of pool_elems
+    elements (x and, for SAXPY, y), per-request a, b (int32) and alpha ~ U(-2, 2)."""
+    rng = np.random.default_rng(seed)
+    count = int(rate * seconds) if max_requests is None else int(max_requests)
+    gaps = rng.exponential(1.0 / rate, count)
+    arrival_us = np.cumsum(gaps) * 1e6
+    kind = rng.choice(3, size=count, p=[0.4, 0.3, 0.3])
+    n = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], count)).astype(np.uint64)
+    n = np.minimum(n, pool_elems)
+    slots = (pool_elems - n) // 256
+    off_x = (rng.random(count) * (slots + 1)).astype(np.uint64) * 256
+    off_y = (rng.random(count) * (slots + 1)).astype(np.uint64) * 256
+    ab = uniform_i32(rng, (count, 2))
+    alpha = rng.uniform(-2, 2, count).astype(np.float32)
+    return dict(arrival_us=arrival_us, kind=kind, n=n, off_x=off_x, off_y=off_y, ab=ab, alpha=alpha)

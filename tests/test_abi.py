@@ -23,7 +23,7 @@ def _declared():
     for h in sorted(os.listdir(INCLUDE)):
         if h.endswith(".h"):
             text = open(os.path.join(INCLUDE, h)).read()
-            names += re.findall(r"^LK_API\s+[\w\s\*]+?\b(lkb?_\w+)\s*\(", text, re.M)
+            names += re.findall(r"^LK_API\s+[\w\s\*]+?\b(lk[bs]?_\w+)\s*\(", text, re.M)
     return names
 
 
@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", lk.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r" T (lkb?_\w+)", out))
+    exported = set(re.findall(r" T (lk[bs]?_\w+)", out))
     assert set(declared) == exported
     assert set(lk.EXPORTED) == exported
 
@@ -42,15 +42,15 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_c_headers(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text('#include "lk.h"\n#include "lk_bench.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc), sizeof(lk_config),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc), sizeof(lk_config),'
                    ' sizeof(lk_completion), sizeof(lk_info), sizeof(lk_log_entry), sizeof(lkb_item),'
-                   ' offsetof(lk_config, init_timeout_ns), offsetof(lk_desc, aux)); return 0;}\n')
+                   ' offsetof(lk_config, init_timeout_ns), offsetof(lk_desc, aux), sizeof(lk_tile)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(lk.Desc), ctypes.sizeof(lk.Config), ctypes.sizeof(lk.Completion),
             ctypes.sizeof(lk.Info), ctypes.sizeof(lk.LogEntry), lk.ITEM_DTYPE.itemsize,
-            lk.Config.init_timeout_ns.offset, lk.Desc.aux.offset]
+            lk.Config.init_timeout_ns.offset, lk.Desc.aux.offset, lk.TILE_DTYPE.itemsize]
     assert got == want
     assert lk.LOG_DTYPE.itemsize == ctypes.sizeof(lk.LogEntry)
     assert lk.COMPLETION_DTYPE.itemsize == ctypes.sizeof(lk.Completion)
@@ -197,7 +197,11 @@ def test_batch_plan_cuts_items_into_tiles():
         assert tiles["n"][owner == i].sum() == it["n"]
     with pytest.raises(lk.LKError):
         lk.batch_plan(items, 100)   # not a multiple of 256
-    assert lk.TILE_DTYPE.itemsize == 32
+    assert lk.TILE_DTYPE.itemsize == 48
+    ax = lk.make_items(lk.OP_AXPY_F32, 600, 0x1000, 0x2000, alpha=np.float32(2.0), in2=0x3000)[None]
+    t2, o2 = lk.batch_plan(ax, 256)
+    assert t2["in2"].tolist() == [0x3000, 0x3000 + 1024, 0x3000 + 2048] and t2["n"].tolist() == [256, 256, 88]
+    assert t2["b"][0] == np.float32(2.0).view(np.uint32)
 
 
 def test_autotuner_picks_the_fastest_median_with_stable_ties():

@@ -557,3 +557,141 @@ def test_launch_burst_baseline_matches_oracle():
                 for _ in range(2):
                     oracle.saxpy_f32(alpha[i], xf[lo:hi].copy(), want)
                 assert np.array_equal(YF[lo:hi].view(np.uint32), want.view(np.uint32)), (graph, i)
+
+
+def test_out_of_place_axpy_single_cluster_and_batch():
+    rng = np.random.default_rng(17)
+    n = 70001
+    x = rng.standard_normal(n + 8).astype(np.float32)
+    yv = rng.standard_normal(n + 8).astype(np.float32)
+    x[:5] = [np.inf, -0.0, 1e-40, np.nan, 3e38]
+    say("axpy: out-of-place fma on one worker, on an XCD cluster and inside a batch")
+    d_x, d_y = to_dev(x), to_dev(yv)
+    outs = [sentinel_f32((n + 8,)) for _ in range(3)]
+    torch.cuda.synchronize()
+    alpha = np.float32(-1.75)
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=20000) as ctx:
+        t = ctx.submit(0, lk.OP_AXPY_F32, x=addr(d_x, 1), y=addr(outs[0], 1), alpha=alpha, n=n, aux=addr(d_y, 1))
+        ctx.wait(0, t)
+        it = lk.make_items(lk.OP_AXPY_F32, n, addr(d_x, 1), addr(outs[2], 1), alpha=alpha, in2=addr(d_y, 1))[None]
+        tiles, owner = lk.batch_plan(it, 4096)
+        d_t = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
+        part = torch.zeros(tiles.size, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        ctx.run_batch(1, d_t, tiles.size, part, reps=1)
+    with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
+        t = ctx.submit(0, lk.OP_AXPY_F32, x=addr(d_x, 1), y=addr(outs[1], 1), alpha=alpha, n=n, aux=addr(d_y, 1))
+        ctx.wait(0, t)
+    want = oracle.axpy_f32(alpha, x[1:n + 1].copy(), yv[1:n + 1].copy())
+    for o in outs:
+        got = o.cpu().numpy()
+        assert same_f32(got[1:n + 1], want)
+        assert got[0].view(np.uint32) == SENT_F32_BITS and np.all(got[n + 1:].view(np.uint32) == SENT_F32_BITS)
+    assert np.array_equal(d_y.cpu().numpy().view(np.uint32), yv.view(np.uint32))  # y only read
+
+
+# ------------------------------------------------------------------ serving (continuous batching)
+def _serve_setup(count, seed, pool_elems=1 << 20, log2=(8, 16)):
+    tr = workloads.serving(1e5, None, pool_elems, seed=seed, log2_range=log2, max_requests=count)
+    rng = np.random.default_rng(seed + 1)
+    xi = rng.integers(-2 ** 31, 2 ** 31, pool_elems, dtype=np.int64).astype(np.int32)
+    xf = rng.standard_normal(pool_elems).astype(np.float32)
+    yf = rng.standard_normal(pool_elems).astype(np.float32)
+    return tr, xi, xf, yf
+
+
+def _requests(tr, d_xi, d_xf, d_yf, arrival_us):
+    req = np.zeros(tr["n"].size, lk.REQUEST_DTYPE)
+    kind = tr["kind"]
+    req["arrival_us"] = arrival_us
+    req["op"] = np.choose(kind, [lk.OP_AFFINE_SUM_I32, lk.OP_SUM_I32_I64, lk.OP_AXPY_F32])
+    req["a"], req["b"], req["alpha"], req["n"] = tr["ab"][:, 0], tr["ab"][:, 1], tr["alpha"], tr["n"]
+    req["inp"] = np.where(kind == 2, addr(d_xf), addr(d_xi)).astype(np.uint64) + tr["off_x"] * 4
+    req["in2"] = np.where(kind == 2, addr(d_yf) + tr["off_y"].astype(np.int64) * 4, 0).astype(np.uint64)
+    return req
+
+
+def _oracle_request(tr, i, xi, xf, yf):
+    n, ox, oy = int(tr["n"][i]), int(tr["off_x"][i]), int(tr["off_y"][i])
+    k = int(tr["kind"][i])
+    if k == 0:
+        return oracle.affine_sum_i32(xi[ox:ox + n].copy(), int(tr["ab"][i, 0]), int(tr["ab"][i, 1]))
+    if k == 1:
+        return None, oracle.sum_i32_i64(xi[ox:ox + n].copy())
+    return oracle.axpy_f32(tr["alpha"][i], xf[ox:ox + n].copy(), yf[oy:oy + n].copy()), 0
+
+
+def _read_output(arena, outc, i, n, kind):
+    base = arena.data_ptr()
+    off = (int(outc["out"][i]) - base) // 4
+    v = arena[off:off + n].cpu().numpy()
+    return v.view(np.float32) if kind == 2 else v
+
+
+def test_serving_results_identical_alone_and_in_the_mix():
+    count = 240
+    tr, xi, xf, yf = _serve_setup(count, 21)
+    say(f"serving: {count} requests all at once (mix) vs one at a time (alone), retained outputs")
+    d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf)
+    # retained outputs: every shard's slice (arena / threads) must hold all of its requests
+    per_req = (tr["n"].astype(np.int64) * 4 + 255) // 256 * 256
+    per_shard = max(int(per_req[s::8].sum()) for s in range(8))
+    need = 8 * (per_shard + (1 << 16))
+    arenas = [torch.zeros(need // 4, dtype=torch.int32, device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=0, depth=4, idle_timeout_ms=30000) as ctx:
+        mix, st_mix = ctx.serve(_requests(tr, d_xi, d_xf, d_yf, np.zeros(count)), arenas[0], need,
+                                tile_elems=4096, threads=8, retain=True)
+        alone, st_alone = ctx.serve(_requests(tr, d_xi, d_xf, d_yf, np.arange(count) * 400.0), arenas[1], need,
+                                    tile_elems=4096, threads=1, retain=True)
+    assert np.all(mix["status"] == 0) and np.all(alone["status"] == 0)
+    # alone really was alone: every request finished before the next arrived
+    assert np.all(alone["done_us"][:-1] < np.arange(1, count) * 400.0)
+    assert np.array_equal(mix["result"], alone["result"])
+    for i in range(count):
+        k, n = int(tr["kind"][i]), int(tr["n"][i])
+        yr, sr = _oracle_request(tr, i, xi, xf, yf)
+        if k in (0, 1):
+            assert mix["result"][i] == sr, i
+        if k != 1:
+            a = _read_output(arenas[0], mix, i, n, k)
+            b = _read_output(arenas[1], alone, i, n, k)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), i
+            if k == 0:
+                assert np.array_equal(a, yr), i
+            else:
+                assert same_f32(a, yr), i
+    assert st_mix["tiles"] == st_alone["tiles"] == int(mix["tiles"].sum())
+
+
+def test_serving_admission_waits_for_memory_budget():
+    count = 400
+    tr, xi, xf, yf = _serve_setup(count, 22)
+    say(f"serving: {count} requests through a 2 MiB output budget (admission waits for memory)")
+    d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf)
+    budget = 2 << 20
+    arena = torch.zeros(budget // 4, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=0, depth=2, idle_timeout_ms=30000) as ctx:
+        outc, st = ctx.serve(_requests(tr, d_xi, d_xf, d_yf, np.zeros(count)), arena, budget,
+                             tile_elems=8192, threads=2, retain=False)
+    assert np.all(outc["status"] == 0)
+    assert st["deferred"] > 0 and st["peak_bytes"] <= budget
+    assert np.all(outc["admit_us"] <= outc["done_us"])
+    for i in range(count):
+        if int(tr["kind"][i]) in (0, 1):
+            assert outc["result"][i] == _oracle_request(tr, i, xi, xf, yf)[1], i
+
+
+def test_second_context_that_cannot_fit_is_refused_at_once():
+    say("two contexts: the second one asking for every CU is refused without booting")
+    with lk.Context(n_workers=0, idle_timeout_ms=10000) as ctx:
+        t0 = time.time()
+        with pytest.raises(lk.LKError) as e:
+            lk.Context(n_workers=0)
+        assert e.value.code == lk.ENODEV and time.time() - t0 < 1.0
+        t = ctx.submit(0, lk.OP_NOP)
+        ctx.wait(0, t)
+    with lk.Context(n_workers=8) as a, lk.Context(n_workers=8) as b:   # room for both
+        for c in (a, b):
+            c.wait(0, c.submit(0, lk.OP_NOP))

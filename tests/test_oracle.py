@@ -228,3 +228,18 @@ def test_fifo_results_and_unknown_op():
     assert res.tolist() == [-5, sum(2 * v + 1 for v in range(-5, 5)), 0]
     with pytest.raises(ValueError):
         oracle.run_fifo([dict(op=99, n=0)])
+
+
+def test_out_of_place_axpy_matches_brute_force_and_leaves_y():
+    rng = np.random.default_rng(31)
+    x = _f32_pool(rng, 300)
+    y = _f32_pool(rng, 300)
+    y_before = y.copy()
+    for alpha in (np.float32(-1.25), np.float32(3e-39), np.float32(7.0)):
+        out = oracle.axpy_f32(alpha, x, y)
+        want = np.array(brute.saxpy(alpha, x, y), dtype=np.float32)
+        assert np.array_equal(_bits(out), _bits(want))
+        assert np.array_equal(_bits(y), _bits(y_before))
+    got = np.empty_like(y)
+    oracle.exec_item(oracle.AXPY_F32, inp=x, out=got, in2=y, alpha=np.float32(0.5))
+    assert np.array_equal(_bits(got), _bits(np.array(brute.saxpy(np.float32(0.5), x, y), np.float32)))
