@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=4, help="HIP streams of the per-launch baseline")
     ap.add_argument("--skip-baselines", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-items", type=int, default=1000, help="items per mailbox in the CPU sample")
+    ap.add_argument("--cpu-items", type=int, default=10000,
+                    help="items per mailbox in the CPU sample (capped at the workload's own)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024)
     ap.add_argument("--workload", choices=["allcu", "isolation", "replay", "batching", "serving"], default="allcu",
                     help="allcu: the headline all-CU workload; isolation: cluster 0 critical "
@@ -559,12 +560,24 @@ def bench_allcu(args):
             serial[name + "_launch_call"] = lat_summary(lau_b)
         rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
         serial["pingpong_rtt"] = lat_summary(rtt)
+        # one-CU streaming copy: the bandwidth one worker can reach on its own
+        cb = 32 << 20
+        csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
+        cdst = torch.empty_like(csrc)
+        torch.cuda.synchronize()
+        _, bw1 = lk.copy_bandwidth(csrc, cdst, cb, grid=1, reps=3)
+        del csrc, cdst
+        item_bytes = 8 * Xs.shape[1] + 8
+        serial["copy_1cu_gbps"] = round(bw1, 2)
         result["serial_1cu"] = {"workload": "1 worker on 1 CU, 1000 submit-then-wait items: int32 affine "
                                             "+ int64 sum over 4096 elements", **serial}
         result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
                                       "floor_us": serial["pingpong_rtt"]["p50"],
                                       "dispatch_p50_us": serial["persistent"]["p50"],
-                                      "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3)}
+                                      "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
+                                      "item_bytes": item_bytes,
+                                      "bytes_frac_of_1cu_copy": round(
+                                          item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
         log(f"serial: persistent p50 {serial['persistent']['p50']} us, launch p50 {serial['launch_sync']['p50']} us")
 
     # ---------------- streaming-copy probe (HBM roofline reference, known-size kernel)
@@ -582,14 +595,14 @@ def bench_allcu(args):
         import oracle
         oracle.build(force=False)
         cores = min(16, os.cpu_count() or 1)
-        per_cpu = args.cpu_items
-
+        per_cpu = min(args.cpu_items, A.shape[1])
+        # The item lists are marshalled before the clock starts; the timed region is the
+        # oracle's own FIFO executor, one mailbox after another on each thread.
         ys = [Y0[w].copy() for w in range(lanes)]
-        jobs = [[dict(op=oracle.SAXPY_F32, inp=X[w], out=ys[w], alpha=a) for a in A[w, :per_cpu]]
-                for w in range(lanes)]
+        packed = [oracle.pack_chain(oracle.SAXPY_F32, X[w], ys[w], A[w, :per_cpu]) for w in range(lanes)]
 
         def lane_job(w):
-            oracle.run_fifo(jobs[w])
+            oracle.run_packed(packed[w])
 
         t0 = time.perf_counter()
         with cf.ThreadPoolExecutor(max_workers=cores) as ex:

@@ -179,6 +179,39 @@ def run_fifo(items):
     return res
 
 
+# numpy view of the orc_item layout, so that long item lists are marshalled without a
+# Python loop (the executor itself is orc_run_fifo either way).
+_ITEM_NP = np.dtype({"names": [f[0] for f in _Item._fields_],
+                     "formats": [np.uint32, np.uint64, np.int32, np.int32, np.float32,
+                                 np.uint64, np.uint64, np.uint64],
+                     "offsets": [getattr(_Item, f[0]).offset for f in _Item._fields_],
+                     "itemsize": ctypes.sizeof(_Item)})
+
+
+def pack_chain(op, inp, out, alphas, a=0, b=0, n=None, in2=None):
+    """A FIFO list of len(alphas) items that share op, operands and (a, b) and differ in
+    alpha, as an array run_packed accepts. The arrays must outlive the packed list."""
+    if n is None:
+        n = (inp if inp is not None else out).size
+    alphas = np.ascontiguousarray(alphas, dtype=np.float32)
+    arr = np.zeros(alphas.size, dtype=_ITEM_NP)
+    arr["op"], arr["n"], arr["a"], arr["b"] = op, n, a, b
+    arr["alpha"] = alphas
+    arr["inp"], arr["out"], arr["in2"] = (_ptr(inp) or 0), (_ptr(out) or 0), (_ptr(in2) or 0)
+    return arr
+
+
+def run_packed(arr):
+    """orc_run_fifo over an array made by pack_chain; returns the int64 results."""
+    if arr.dtype != _ITEM_NP or not arr.flags.c_contiguous:
+        raise ValueError("not a packed item list")
+    res = np.zeros(arr.size, dtype=np.int64)
+    rc = lib().orc_run_fifo(ctypes.cast(arr.ctypes.data, ctypes.POINTER(_Item)), arr.size, _ptr(res))
+    if rc != 0:
+        raise ValueError("unknown op in item list")
+    return res
+
+
 def saxpy_chain_elem(x, y, alphas):
     alphas = _check(np.ascontiguousarray(alphas, dtype=np.float32), np.float32)
     return np.float32(lib().orc_saxpy_chain_elem(float(x), float(y), _ptr(alphas), alphas.size))

@@ -41,6 +41,15 @@ __device__ __forceinline__ void backoff(uint32_t units) {
   for (uint32_t i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(1);
 }
 
+// Values every lane holds identically (descriptor fields broadcast through LDS): tell the
+// compiler so that loop bounds and base addresses live in scalar registers.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 }  // namespace lkdev
 
 #endif

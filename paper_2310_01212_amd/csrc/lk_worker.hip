@@ -44,20 +44,21 @@ __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_
     *s_next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) - base;
   __syncthreads();
   for (;;) {
-    const uint64_t t = *s_next;
+    const uint64_t t = uniform_u64(*s_next);
     if (t >= n_tiles) break;
     const lkd::Tile tile = tiles[t];
     uint64_t next = 0;
     if (threadIdx.x == 0) next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     lkops::Slice sl;
-    sl.op = (tile.op == lkd::kOpBatch || tile.op >= lkd::kOpCount) ? 0u : tile.op;  // no nested batches
-    sl.n = tile.n;
-    sl.in = reinterpret_cast<const void *>(tile.in);
-    sl.out = reinterpret_cast<void *>(tile.out);
-    sl.in2 = reinterpret_cast<const void *>(tile.in2);
-    sl.a = static_cast<uint32_t>(tile.a);
-    sl.b = tile.b;
-    sl.alpha = __uint_as_float(tile.b);
+    const uint32_t top = uniform_u32(tile.op);
+    sl.op = (top == lkd::kOpBatch || top >= lkd::kOpCount) ? 0u : top;  // no nested batches
+    sl.n = uniform_u32(tile.n);
+    sl.in = reinterpret_cast<const void *>(uniform_u64(tile.in));
+    sl.out = reinterpret_cast<void *>(uniform_u64(tile.out));
+    sl.in2 = reinterpret_cast<const void *>(uniform_u64(tile.in2));
+    sl.a = uniform_u32(static_cast<uint32_t>(tile.a));
+    sl.b = uniform_u32(tile.b);
+    sl.alpha = __uint_as_float(sl.b);
     const int64_t part = lkops::run_slice<lkops::SystemStore>(sl, s_red, nt);  // ends with a barrier
     if (threadIdx.x == 0) {
       st_sys_i64(partials + t, part);
@@ -189,13 +190,13 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     uint32_t reply = LKW_FROM_FINISHED;
     lkops::Slice s;
     s.op = 0;
-    s.n = s_w[LKW_W_N] & LKW_PAYLOAD_MASK;
-    s.in = reinterpret_cast<const void *>(s_w[LKW_W_IN] & LKW_PAYLOAD_MASK);
-    s.out = reinterpret_cast<void *>(s_w[LKW_W_OUT] & LKW_PAYLOAD_MASK);
-    s.in2 = reinterpret_cast<const void *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
-    s.a = static_cast<uint32_t>(s_w[LKW_W_A]);
-    s.b = static_cast<uint32_t>(s_w[LKW_W_B]);
-    s.alpha = __uint_as_float(static_cast<uint32_t>(s_w[LKW_W_ALPHA]));
+    s.n = uniform_u64(s_w[LKW_W_N] & LKW_PAYLOAD_MASK);
+    s.in = reinterpret_cast<const void *>(uniform_u64(s_w[LKW_W_IN] & LKW_PAYLOAD_MASK));
+    s.out = reinterpret_cast<void *>(uniform_u64(s_w[LKW_W_OUT] & LKW_PAYLOAD_MASK));
+    s.in2 = reinterpret_cast<const void *>(uniform_u64(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK));
+    s.a = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_A]));
+    s.b = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_B]));
+    s.alpha = __uint_as_float(uniform_u32(static_cast<uint32_t>(s_w[LKW_W_ALPHA])));
     if (code == LKW_TO_NOP) {
       reply = LKW_FROM_NOP;
     } else if (code >= LKW_TO_WORK && code < LKW_TO_WORK + lkd::kOpCount) {

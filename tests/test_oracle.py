@@ -219,6 +219,23 @@ def test_fifo_runs_in_submission_order():
     assert not np.array_equal(_bits(yr), _bits(y))
 
 
+def test_packed_chain_runs_the_same_fifo():
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal(300).astype(np.float32)
+    y0 = rng.standard_normal(300).astype(np.float32)
+    alphas = rng.uniform(-2, 2, 40).astype(np.float32)
+    y1, y2 = y0.copy(), y0.copy()
+    oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=x, out=y1, alpha=a) for a in alphas])
+    res = oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, x, y2, alphas))
+    assert np.array_equal(_bits(y1), _bits(y2)) and not res.any()
+    xi = np.arange(-7, 9, dtype=np.int32)
+    yi = np.empty_like(xi)
+    res = oracle.run_packed(oracle.pack_chain(oracle.AFFINE_SUM_I32, xi, yi, np.zeros(3), a=3, b=-2))
+    assert res.tolist() == [sum(3 * v - 2 for v in range(-7, 9))] * 3
+    with pytest.raises(ValueError):
+        oracle.run_packed(oracle.pack_chain(99, None, None, np.zeros(1), n=0))
+
+
 def test_fifo_results_and_unknown_op():
     x = np.arange(-5, 5, dtype=np.int32)
     y = np.empty_like(x)
