@@ -64,7 +64,7 @@ def worker_source_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_per_item(n):
+def traffic_per_item(n, threads_per_worker):
     """HBM bytes per item of the worker kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration);
     None when the summary is missing, was taken for another item size, or the worker's
@@ -77,7 +77,8 @@ def traffic_per_item(n):
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("worker_source_digest") != worker_source_digest() or d.get("n") != n:
+    if (d.get("worker_source_digest") != worker_source_digest() or d.get("n") != n or
+            d.get("threads_per_worker", 256) != threads_per_worker):
         return None
     return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
 
@@ -90,8 +91,11 @@ def parse():
     ap.add_argument("--items-per-step", type=int, default=1000, help="items per mailbox per step")
     ap.add_argument("--n", type=int, default=16384, help="elements per item")
     ap.add_argument("--depth", type=int, default=1, help="ring slots per mailbox (in flight)")
-    ap.add_argument("--threads-per-worker", type=int, default=256,
-                    help="workgroup size of each persistent worker (256 = one wave64 per SIMD)")
+    ap.add_argument("--threads-per-worker", type=int, default=1024,
+                    help="workgroup size of each persistent worker and of the per-launch baselines "
+                         "(1024 = four wave64 per SIMD; the 1-CU serial comparison keeps 256)")
+    ap.add_argument("--pipelined-depth", type=int, default=4,
+                    help="ring depth of the pipelined variant reported beside the depth-1 headline (0 = skip)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
                     help="host feeder threads (one producer per mailbox)")
     ap.add_argument("--poll-sleep", type=int, default=0)
@@ -313,6 +317,15 @@ def bench_serving(args):
                    "offered_gbps": round(nbytes / (tr["arrival_us"][-1] * 1e-6) / 1e9, 1),
                    "tiles": int(st["tiles"]), "deferred": int(st["deferred"]),
                    "peak_output_bytes": int(st["peak_bytes"])}
+            # where the tail sits in time: p99 per 100 ms window of arrivals
+            win = (tr["arrival_us"] // 1e5).astype(np.int64)
+            order = np.argsort(win, kind="stable")
+            bounds = np.flatnonzero(np.diff(win[order])) + 1
+            w99 = [(int(win[order][g[0]]), pct(lat[g], 0.99), g.size) for g in np.split(order, bounds)]
+            worst = max(w99, key=lambda t: t[1])
+            row["windows_100ms"] = {"count": len(w99), "p99_over_1ms": int(sum(t[1] > 1000 for t in w99)),
+                                    "worst": {"start_s": worst[0] / 10, "p99_us": round(worst[1], 3),
+                                              "requests": int(worst[2])}}
             # spot parity of int64 results against the oracle
             sample = np.flatnonzero(kind != 2)[:: max(1, int(np.sum(kind != 2)) // 40)][:40]
             bad = 0
@@ -516,7 +529,7 @@ def bench_allcu(args):
                           "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
                           "items_per_launch": session_items, "algorithmic_bytes_per_item": bytes_per_item,
                           "algorithmic_bytes": session_items * bytes_per_item}
-    tr = traffic_per_item(n)
+    tr = traffic_per_item(n, args.threads_per_worker)
     if tr is not None:
         result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
         result["roofline"]["traffic_source"] = tr["source"]
@@ -529,15 +542,33 @@ def bench_allcu(args):
             t0 = time.perf_counter()
             for s in range(args.baseline_steps):
                 _, lat, el = lk.launch_lanes(step_items(s), streams=args.streams, threads_host=args.threads,
-                                             mode=mode)
+                                             threads=args.threads_per_worker, mode=mode)
                 bl.append(lat)
             el = time.perf_counter() - t0
             bl = np.concatenate([b.ravel() for b in bl])
             base[name] = {"items_per_s": round(bl.size / el, 1), "latency_us": lat_summary(bl),
-                          "streams": args.streams, "items": int(bl.size)}
+                          "streams": args.streams, "threads_per_wg": args.threads_per_worker,
+                          "items": int(bl.size)}
             log(f"{name}: {bl.size / el:,.0f} items/s, p50 {pct(bl, .5):.2f} us")
         result["baselines"] = base
         result["speedup_items_per_s"] = {k: round(items_per_s / v["items_per_s"], 2) for k, v in base.items()}
+
+        # pipelined variant: the same mailboxes kept `depth` items ahead (latency then
+        # includes the time an item waits behind the ones before it in its ring)
+        if args.pipelined_depth > 1:
+            d = args.pipelined_depth
+            with lk.Context(n_workers=lanes, depth=d, threads=args.threads_per_worker,
+                            poll_sleep=args.poll_sleep, idle_timeout_ms=60000) as cp:
+                cp.run_lanes(np.arange(lanes), step_items(0), in_flight=d, threads=args.threads)
+                pl, pt = [], 0.0
+                for s in range(1, min(4, args.warmup + args.steps)):
+                    _, lat, el = cp.run_lanes(np.arange(lanes), step_items(s), in_flight=d, threads=args.threads)
+                    pl.append(lat)
+                    pt += el
+            pl = np.concatenate([l.ravel() for l in pl])
+            result["pipelined"] = {"queue_depth": d, "items_per_s": round(pl.size / pt, 1),
+                                   "latency_us": lat_summary(pl), "items": int(pl.size)}
+            log(f"pipelined depth {d}: {pl.size / pt:,.0f} items/s")
 
         # serial single-worker comparison (1 CU, 1000 affine+sum items of 4096 int32)
         Xs, ABs = workloads.plain()

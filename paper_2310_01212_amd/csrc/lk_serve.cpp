@@ -10,66 +10,18 @@
 #include <atomic>
 #include <chrono>
 #include <deque>
-#include <map>
 #include <thread>
 #include <vector>
 
 #include "lk.h"
+#include "lk_arena.hpp"
 
 namespace {
 
 using clk = std::chrono::steady_clock;
+using lksrv::Arena;
 
-constexpr uint64_t kGranule = 256;  // bytes; output buffers start 256-byte aligned
-
-// First-fit allocator over one shard's slice of the arena (offsets in bytes).
-class Arena {
- public:
-  Arena(uint64_t base, uint64_t size) : base_(base), size_(size) {
-    if (size) free_[0] = size;
-  }
-  // Returns false if no free block is large enough.
-  bool alloc(uint64_t bytes, uint64_t *addr) {
-    bytes = round(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const uint64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[off + bytes] = len - bytes;
-        used_ += bytes;
-        peak_ = std::max(peak_, used_);
-        *addr = base_ + off;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(uint64_t addr, uint64_t bytes) {
-    bytes = round(bytes);
-    uint64_t off = addr - base_;
-    used_ -= bytes;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + bytes == next->first) {
-      bytes += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += bytes;
-        return;
-      }
-    }
-    free_[off] = bytes;
-  }
-  uint64_t size() const { return size_; }
-  uint64_t peak() const { return peak_; }
-  static uint64_t round(uint64_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
-
- private:
-  uint64_t base_, size_, used_ = 0, peak_ = 0;
-  std::map<uint64_t, uint64_t> free_;  // offset -> length
-};
+constexpr uint64_t kGranule = Arena::kGranule;  // bytes; output buffers start 256-byte aligned
 
 bool op_allowed(uint32_t op) {
   return op == LK_OP_AFFINE_SUM_I32 || op == LK_OP_SUM_I32_I64 || op == LK_OP_AXPY_F32 || op == LK_OP_COPY_F32;
@@ -129,7 +81,9 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
     size_t next_arrival = 0;
     std::deque<uint64_t> waiting;   // arrived, not admitted
     std::deque<Tile> queue;         // tiles of admitted requests, admission order
-    std::map<uint64_t, Active> active;
+    // State of this shard's requests, indexed by i / T (request i belongs to shard i % T).
+    std::vector<Active> act(mine.size());
+    uint64_t n_active = 0;
     uint64_t finished = 0;
     uint64_t last_deferred = ~0ull;  // the waiting head already counted as deferred
     uint32_t rr = 0;
@@ -153,7 +107,7 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           if (!arena.alloc(need, &addr)) {
             // Nothing in flight in this shard means nothing will ever be freed: the
             // budget is exhausted for good (possible only with `retain`).
-            if (active.empty()) return fail(LK_EINVAL);
+            if (n_active == 0) return fail(LK_EINVAL);
             if (i != last_deferred) {
               ++deferred[s];
               last_deferred = i;
@@ -166,7 +120,8 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
         Active a;
         a.remaining = nt;
         a.out = addr;
-        active[i] = a;
+        act[i / T] = a;
+        ++n_active;
         out[i].admit_us = now_us;
         out[i].out = addr;
         out[i].tiles = static_cast<uint32_t>(nt);
@@ -193,13 +148,13 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           const uint64_t i = pq.front().req;
           pq.pop_front();
           ++tiles_done[s];
-          Active &a = active[i];
+          Active &a = act[i / T];
           a.sum += part;
           if (--a.remaining == 0) {
             out[i].result = a.sum;
             out[i].done_us = us_since(clk::now());
             if (!cfg->retain && a.out) arena.release(a.out, out_bytes(reqs[i]));
-            active.erase(i);
+            --n_active;
             ++finished;
           }
         }
@@ -218,7 +173,8 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           d.alpha = r.alpha;
           d.aux = r.op == LK_OP_AXPY_F32 ? r.in2 + tl.lo * 4 : 0;
           const uint64_t in = r.in + tl.lo * 4;
-          const uint64_t o = active[tl.req].out ? active[tl.req].out + tl.lo * 4 : 0;
+          const uint64_t ob = act[tl.req / T].out;
+          const uint64_t o = ob ? ob + tl.lo * 4 : 0;
           uint64_t t;
           const int rc = lk_submit(c, workers[w], &d, reinterpret_cast<const void *>(in), reinterpret_cast<void *>(o), &t);
           if (rc == LK_EAGAIN) break;

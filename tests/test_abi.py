@@ -218,3 +218,16 @@ def test_autotuner_picks_the_fastest_median_with_stable_ties():
     table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), sleeps=(0, 8), reps=2)
     assert table[1]["tile"] == 16384 and table[1]["poll_sleep"] == 0
     assert table[4]["tile"] == 65536 and len(calls) == 12
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_serving_arena_best_fit_allocator(tmp_path, seed):
+    """The serving loop's output allocator (csrc/lk_arena.hpp), driven by a randomised
+    C++ check: no overlap, 256-byte alignment, exact accounting, full coalescing, best
+    fit, and failure only when no free block is large enough."""
+    exe = tmp_path / "arena_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-Werror",
+                    "-I", os.path.join(ROOT, "paper_2310_01212_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "cpp", "arena_check.cpp"), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe), str(seed)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "OK", r.stderr

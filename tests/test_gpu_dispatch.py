@@ -101,10 +101,13 @@ def test_plain_1000_items_bit_exact_with_log_invariants():
 
 
 # ------------------------------------------------------------------ edge cases on one worker
-def _edge_items(rng):
-    """(op, n, x_off, y_off, a, b, alpha) with ragged sizes and misalignments."""
+EDGE_N = [0, 1, 3, 4, 5, 255, 256, 257, 1023, 4097, 65537, 1000003]
+
+
+def _edge_items(rng, sizes=EDGE_N):
+    """(op, n, x_off, y_off) with ragged sizes and misalignments."""
     cases = []
-    for n in [0, 1, 3, 4, 5, 255, 256, 257, 1023, 4097, 65537, 1000003]:
+    for n in sizes:
         for xo, yo in [(0, 0), (1, 1), (3, 3), (1, 2)]:
             cases.append((lk.OP_AFFINE_SUM_I32, n, xo, yo))
             cases.append((lk.OP_SAXPY_F32, n, xo, yo))
@@ -114,10 +117,20 @@ def _edge_items(rng):
 
 
 def test_edge_cases_ragged_misaligned_and_special_values():
-    rng = np.random.default_rng(42)
-    cases = _edge_items(rng)
-    say(f"edge: {len(cases)} items, ragged n up to 1000003, misaligned in/out")
-    span = 1000003 + 8
+    _run_edge_cases(256, EDGE_N, seed=42)
+
+
+@pytest.mark.parametrize("threads", [64, 512, 1024])
+def test_other_worker_sizes_match_oracle(threads):
+    """Workgroups of 1, 8 and 16 waves run the same bodies (strides, wave reduction)."""
+    _run_edge_cases(threads, [0, 1, 255, 257, 4097, 65537, 300001], seed=43 + threads)
+
+
+def _run_edge_cases(threads, sizes, seed):
+    rng = np.random.default_rng(seed)
+    cases = _edge_items(rng, sizes)
+    say(f"edge: {len(cases)} items, ragged n up to {max(sizes)}, misaligned in/out, {threads} threads/worker")
+    span = max(sizes) + 8
     xs_i = rng.integers(-2 ** 31, 2 ** 31, (len(cases), span), dtype=np.int64).astype(np.int32)
     # float inputs with specials: subnormals, +-0, inf, nan payloads, near-overflow
     xs_f = rng.standard_normal((len(cases), span)).astype(np.float32)
@@ -150,7 +163,8 @@ def test_edge_cases_ragged_misaligned_and_special_values():
     # NOP and SPIN ride along (no memory effect, result 0)
     extra = lk.make_items(np.array([lk.OP_NOP, lk.OP_SPIN]), 0, 0, 0, a=np.array([0, 2000]), b=0)
     items = np.concatenate([items, extra])
-    with lk.Context(n_workers=1, log_capacity=4096) as ctx:
+    with lk.Context(n_workers=1, threads=threads, log_capacity=4096) as ctx:
+        assert ctx.info()["threads_per_worker"] == threads
         res, _, _, _ = ctx.run_serial(0, items)
     YI = y_i.cpu().numpy()
     YF = y_f.cpu().numpy()
