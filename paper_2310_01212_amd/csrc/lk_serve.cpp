@@ -68,7 +68,12 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
   const uint32_t depth = info.queue_depth;
   std::atomic<int> error{LK_OK};
   std::vector<uint64_t> tiles_done(T, 0), deferred(T, 0), peak(T, 0);
-  const auto t0 = clk::now() + std::chrono::milliseconds(2);
+  // The arrival clock starts only once every shard has built its tables (they are sized
+  // by the trace and page-faulted in while being filled), so that set-up is not charged
+  // to the first requests as queueing.
+  std::atomic<uint32_t> ready{0};
+  std::atomic<int64_t> t0_ns{0};
+  clk::time_point t0;
   auto us_since = [&](clk::time_point t) { return std::chrono::duration<double, std::micro>(t - t0).count(); };
 
   auto shard = [&](uint32_t s) {
@@ -91,6 +96,8 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
       int expected = LK_OK;
       error.compare_exchange_strong(expected, rc);
     };
+    ready.fetch_add(1, std::memory_order_acq_rel);
+    while (t0_ns.load(std::memory_order_acquire) == 0) _mm_pause();
     while (finished < mine.size() && error.load(std::memory_order_relaxed) == LK_OK) {
       const auto now = clk::now();
       const double now_us = us_since(now);
@@ -193,6 +200,9 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
   };
   std::vector<std::thread> th;
   for (uint32_t s = 0; s < T; ++s) th.emplace_back(shard, s);
+  while (ready.load(std::memory_order_acquire) < T) std::this_thread::yield();
+  t0 = clk::now() + std::chrono::milliseconds(2);
+  t0_ns.store(std::max<int64_t>(1, t0.time_since_epoch().count()), std::memory_order_release);
   for (auto &t : th) t.join();
   const int rc = error.load();
   if (stats) {
