@@ -96,6 +96,8 @@ def parse():
                          "(1024 = four wave64 per SIMD; the 1-CU serial comparison keeps 256)")
     ap.add_argument("--pipelined-depth", type=int, default=4,
                     help="ring depth of the pipelined variant reported beside the depth-1 headline (0 = skip)")
+    ap.add_argument("--variant-per-cu", type=int, default=2,
+                    help="workers per CU of the variant reported beside the one-per-CU headline (0/1 = skip)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
                     help="host feeder threads (one producer per mailbox)")
     ap.add_argument("--poll-sleep", type=int, default=0)
@@ -569,6 +571,38 @@ def bench_allcu(args):
             result["pipelined"] = {"queue_depth": d, "items_per_s": round(pl.size / pt, 1),
                                    "latency_us": lat_summary(pl), "items": int(pl.size)}
             log(f"pipelined depth {d}: {pl.size / pt:,.0f} items/s")
+
+        # several workers per CU: k mailboxes per CU, each fed back-to-back at depth 1, so
+        # one worker's round trip to the host overlaps another's execution on the same CU
+        if args.variant_per_cu > 1:
+            k = args.variant_per_cu
+            tv = min(args.threads_per_worker, 1024 // k)
+            vl = lanes * k
+            vsteps = min(4, args.warmup + args.steps)
+            VX = np.empty((vl, n), np.float32)
+            VY = np.empty((vl, n), np.float32)
+            VA = np.empty((vl, vsteps * per), np.float32)
+            for w in range(vl):
+                VX[w], VY[w], VA[w] = workloads.allcu_lane(w, items=vsteps * per, n=n)
+            vx, vy = torch.from_numpy(VX).to(dev), torch.from_numpy(VY).to(dev)
+            torch.cuda.synchronize()
+            vli = np.arange(vl, dtype=np.uint64)[:, None]
+            vitems = [lk.make_items(lk.OP_SAXPY_F32, n, vx.data_ptr() + vli * n * 4, vy.data_ptr() + vli * n * 4,
+                                    alpha=VA[:, s * per:(s + 1) * per]) for s in range(vsteps)]
+            with lk.Context(n_workers=0, workers_per_cu=k, threads=tv, poll_sleep=args.poll_sleep,
+                            idle_timeout_ms=60000) as cv:
+                cv.run_lanes(np.arange(vl), vitems[0], in_flight=1, threads=args.threads)
+                vlat, vt = [], 0.0
+                for s in range(1, vsteps):
+                    _, lat, el = cv.run_lanes(np.arange(vl), vitems[s], in_flight=1, threads=args.threads)
+                    vlat.append(lat)
+                    vt += el
+            del vx, vy
+            vlat = np.concatenate([l.ravel() for l in vlat])
+            result["workers_per_cu_variant"] = {"workers_per_cu": k, "threads_per_worker": tv, "mailboxes": vl,
+                                                "queue_depth": 1, "items_per_s": round(vlat.size / vt, 1),
+                                                "latency_us": lat_summary(vlat), "items": int(vlat.size)}
+            log(f"{k} workers per CU: {vlat.size / vt:,.0f} items/s")
 
         # serial single-worker comparison (1 CU, 1000 affine+sum items of 4096 int32)
         Xs, ABs = workloads.plain()

@@ -40,6 +40,7 @@ extern "C" {
 /* ------------------------------------------------------------------ limits */
 #define LK_MAX_WORKERS 1024u   /* workers per context (MI355X has 256 CUs) */
 #define LK_MAX_DEPTH 64u       /* ring slots per mailbox; 1 is the paper's single slot */
+#define LK_MAX_WORKERS_PER_CU 4u /* persistent workgroups resident on one CU */
 #define LK_MAX_N (1ull << 40)  /* elements per work item */
 
 /* ------------------------------------------------------------------ error codes */
@@ -131,7 +132,8 @@ enum { LK_CLUSTERS_PER_WORKER = 0, LK_CLUSTERS_PER_XCD = 1, LK_CLUSTERS_ONE = 2,
 
 typedef struct lk_config {
   int32_t device;              /* HIP device ordinal */
-  uint32_t n_workers;          /* 1..LK_MAX_WORKERS, at most the CU count; 0 = one per CU */
+  uint32_t n_workers;          /* 1..LK_MAX_WORKERS, at most the CU count times
+                                  workers_per_cu; 0 = workers_per_cu on every CU */
   uint32_t threads_per_worker; /* 64..1024, multiple of 64; 0 = 256 (4 wave64 per CU) */
   uint32_t queue_depth;        /* 1..LK_MAX_DEPTH ring slots per mailbox; 0 = 1 */
   uint32_t cluster_policy;     /* LK_CLUSTERS_* */
@@ -143,22 +145,28 @@ typedef struct lk_config {
   uint32_t log_capacity;       /* device log entries per worker (ring); 0 = no log */
   uint32_t idle_timeout_ms;    /* watchdog: a worker idle this long leaves the loop;
                                   0 = 10000 ms; at most 3600000 */
-  uint32_t reserved;
+  uint32_t workers_per_cu;     /* persistent workgroups resident on one CU, 1..4 (0 = 1),
+                                  each with its own mailbox; they share the CU's LDS
+                                  evenly (sized so that one more never fits) and
+                                  threads_per_worker x workers_per_cu must be <= 1024 so
+                                  that the register file holds all of them */
   int64_t init_timeout_ns;     /* lk_init: deadline for every worker to report INIT;
                                   0 = 5 s */
 } lk_config;
 
 typedef struct lk_ctx lk_ctx;  /* opaque, owned by the library */
 
-/* Fill *cfg with the defaults (all CUs, 256 threads, depth 1, one cluster per worker). */
+/* Fill *cfg with the defaults (one worker on every CU, 256 threads, depth 1, one cluster
+ * per worker). */
 LK_API void lk_config_default(lk_config *cfg);
 
 /* Init phase (Sec. 3; pinning at boot, Sec. 2.3).  Checks the device, allocates the
  * mailboxes in fine-grained host-coherent memory, dispatches the persistent kernel with
- * one workgroup per CU on its own HSA queue and waits until every worker has reported
- * INIT (Table 1) with its physical placement.  On success *out holds a running context.
- * Errors: LK_EINVAL (bad config), LK_ENODEV (no device, too few CUs, workers not all
- * resident or not on distinct CUs within init_timeout_ns), LK_EHIP. */
+ * workers_per_cu workgroups per CU on its own HSA queue and waits until every worker has
+ * reported INIT (Table 1) with its physical placement.  On success *out holds a running
+ * context.  Errors: LK_EINVAL (bad config), LK_ENODEV (no device, too few CUs, workers not
+ * all resident within init_timeout_ns, or more than workers_per_cu of them on one CU),
+ * LK_EHIP. */
 LK_API int lk_init(const lk_config *cfg, lk_ctx **out);
 
 /* Trigger phase (Sec. 3): post one work item to every member of `cluster`.
@@ -256,6 +264,8 @@ typedef struct lk_info {
                                   when a tool intercepting the queue hides them) */
   double device_span_ms;       /* first worker boot to last worker exit on the device
                                   wall clock (after lk_dispose) */
+  uint32_t workers_per_cu;     /* as configured */
+  uint32_t max_workers_on_a_cu; /* most workers found on one physical CU at boot */
 } lk_info;
 
 LK_API int lk_get_info(lk_ctx *ctx, lk_info *info);

@@ -104,6 +104,8 @@ struct lk_ctx {
   lk_config cfg{};
   int device = 0;
   uint32_t n_workers = 0, depth = 1, threads = 256, n_clusters = 0, cu_count = 0, xcd_count = 0;
+  uint32_t per_cu = 1, max_on_a_cu = 0;
+  uint32_t cus_held = 0;  // CUs counted for this context in the process registry
   uint32_t log_cap = 0;
   uint64_t wall_hz = 100000000ull;
   State state = RUNNING;
@@ -190,6 +192,11 @@ int validate_config(const lk_config *cfg) {
   const uint32_t t = cfg->threads_per_worker;
   if (t != 0 && (t < 64 || t > 1024 || t % 64 != 0))
     return fail(LK_EINVAL, "threads_per_worker %u: need a multiple of 64 in 64..1024", t);
+  const uint32_t wpc = cfg->workers_per_cu ? cfg->workers_per_cu : 1;
+  if (wpc > LK_MAX_WORKERS_PER_CU) return fail(LK_EINVAL, "workers_per_cu %u > %u", wpc, LK_MAX_WORKERS_PER_CU);
+  if (wpc * (t ? t : 256) > 1024)
+    return fail(LK_EINVAL, "threads_per_worker %u x workers_per_cu %u > 1024: not every worker could stay resident",
+                t ? t : 256, wpc);
   if (cfg->queue_depth > LK_MAX_DEPTH) return fail(LK_EINVAL, "queue_depth %u > %u", cfg->queue_depth, LK_MAX_DEPTH);
   if (cfg->cluster_policy > LK_CLUSTERS_EXPLICIT) return fail(LK_EINVAL, "unknown cluster_policy %u", cfg->cluster_policy);
   if (cfg->cluster_policy == LK_CLUSTERS_EXPLICIT) {
@@ -216,7 +223,7 @@ int validate_config(const lk_config *cfg) {
 
 // Only called once the persistent dispatch has ended (or was never made).
 void release_gpu(lk_ctx *c) {
-  if (c->cus_reserved) release_cus(c->device, c->n_workers);
+  if (c->cus_reserved) release_cus(c->device, c->cus_held);
   c->cus_reserved = false;
   c->wq.close();
   if (c->d_batch_counters) (void)hipFree(c->d_batch_counters);
@@ -254,6 +261,7 @@ void lk_config_default(lk_config *cfg) {
   cfg->cluster_policy = LK_CLUSTERS_PER_WORKER;
   cfg->log_capacity = 0;
   cfg->idle_timeout_ms = 10000;
+  cfg->workers_per_cu = 1;
 }
 
 int lk_slice(uint64_t n, uint32_t k, uint32_t j, uint64_t *lo, uint64_t *hi) {
@@ -296,7 +304,9 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   if ((e = hipGetDeviceProperties(&prop, cfg.device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(LK_ENODEV, "device %d is %s; this library is built for gfx950", cfg.device, prop.gcnArchName);
-  if (prop.maxSharedMemoryPerMultiProcessor < 2 * LKW_LDS_PAD_BYTES - 64 * 1024)
+  // The one-worker-per-CU layout relies on LKW_LDS_PAD_BYTES fitting a CU once, not twice.
+  if (prop.maxSharedMemoryPerMultiProcessor < LKW_LDS_PAD_BYTES + 4096 ||
+      prop.maxSharedMemoryPerMultiProcessor >= 2 * LKW_LDS_PAD_BYTES)
     return fail(LK_ENODEV, "unexpected LDS size %zu per CU", prop.maxSharedMemoryPerMultiProcessor);
 
   auto *c = new lk_ctx();
@@ -304,20 +314,31 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   c->cfg.cluster_of_worker = nullptr;
   c->device = cfg.device;
   c->cu_count = static_cast<uint32_t>(prop.multiProcessorCount);
-  c->n_workers = cfg.n_workers ? cfg.n_workers : c->cu_count;
+  c->per_cu = cfg.workers_per_cu ? cfg.workers_per_cu : 1;
+  c->n_workers = cfg.n_workers ? cfg.n_workers : c->cu_count * c->per_cu;
   c->depth = cfg.queue_depth ? cfg.queue_depth : 1;
   c->threads = cfg.threads_per_worker ? cfg.threads_per_worker : 256;
   c->log_cap = cfg.log_capacity;
-  if (c->n_workers > c->cu_count || c->n_workers > LK_MAX_WORKERS) {
+  if (c->n_workers > c->cu_count * c->per_cu || c->n_workers > LK_MAX_WORKERS) {
+    const uint32_t cap = std::min(c->cu_count * c->per_cu, LK_MAX_WORKERS);
     delete c;
-    return fail(LK_EINVAL, "n_workers %u exceeds the %u CUs", cfg.n_workers, c->cu_count);
+    return fail(LK_EINVAL, "n_workers %u exceeds %u (%u per CU)", cfg.n_workers, cap,
+                cfg.workers_per_cu ? cfg.workers_per_cu : 1);
   }
+  // Dynamic LDS per worker: one worker per CU takes 96 KiB, so a second never fits;
+  // k workers per CU take an even share of the CU's LDS less 2 KiB (room for the static
+  // LDS and the allocation granule), so k fit and k + 1 do not.
+  const uint32_t lds_cu = static_cast<uint32_t>(prop.maxSharedMemoryPerMultiProcessor);
+  const uint32_t lds_pad = c->per_cu == 1 ? LKW_LDS_PAD_BYTES : (lds_cu / c->per_cu - 2048u) / 256u * 256u;
   {
+    // Until the hardware ids are known every worker may sit on a CU of its own.
     uint32_t in_use = 0;
-    if (!reserve_cus(cfg.device, c->n_workers, c->cu_count, &in_use)) {
+    c->cus_held = std::min(c->n_workers, c->cu_count);
+    if (!reserve_cus(cfg.device, c->cus_held, c->cu_count, &in_use)) {
+      const uint32_t want = c->cus_held;
       delete c;
-      return fail(LK_ENODEV, "%u workers requested but this process's running contexts already hold %u of the %u CUs",
-                  cfg.n_workers ? cfg.n_workers : c->cu_count, in_use, c->cu_count);
+      return fail(LK_ENODEV, "%u CUs needed but this process's running contexts already hold %u of the %u CUs", want,
+                  in_use, c->cu_count);
     }
     c->cus_reserved = true;
   }
@@ -388,7 +409,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
 
   {
     std::string err;
-    if (!c->wq.dispatch(p, c->n_workers, c->threads, LKW_LDS_PAD_BYTES, err))
+    if (!c->wq.dispatch(p, c->n_workers, c->threads, lds_pad, err))
       return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
   }
   c->kernel_launched = true;
@@ -433,19 +454,22 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   std::sort(ws.begin(), ws.end(), [](const WorkerInfo &x, const WorkerInfo &y) {
     return std::make_tuple(x.xcc, x.se, x.sh, x.cu, x.mailbox) < std::make_tuple(y.xcc, y.se, y.sh, y.cu, y.mailbox);
   });
-  if (!(cfg.flags & LK_F_ANY_PLACEMENT)) {
-    for (uint32_t i = 1; i < c->n_workers; ++i) {
-      const auto &x = ws[i - 1], &y = ws[i];
-      if (x.xcc == y.xcc && x.se == y.se && x.sh == y.sh && x.cu == y.cu) {
-        for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
-        if (!join_kernel(c, 2.0 + idle_ms / 1000.0)) {
-          c->state = POISONED;
-          *out = c;
-          return fail(LK_ENODEV, "two workers share CU (xcc %u se %u cu %u); kernel did not end", x.xcc, x.se, x.cu);
-        }
-        return bail(fail(LK_ENODEV, "two workers share CU (xcc %u se %u sh %u cu %u)", x.xcc, x.se, x.sh, x.cu));
-      }
+  // Workers per physical CU (sorted, so co-resident workers are adjacent).
+  for (uint32_t i = 0, run = 0; i < c->n_workers; ++i) {
+    const bool same = i > 0 && ws[i - 1].xcc == ws[i].xcc && ws[i - 1].se == ws[i].se && ws[i - 1].sh == ws[i].sh &&
+                      ws[i - 1].cu == ws[i].cu;
+    run = same ? run + 1 : 1;
+    c->max_on_a_cu = std::max(c->max_on_a_cu, run);
+  }
+  if (!(cfg.flags & LK_F_ANY_PLACEMENT) && c->max_on_a_cu > c->per_cu) {
+    for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
+    if (!join_kernel(c, 2.0 + idle_ms / 1000.0)) {
+      c->state = POISONED;
+      *out = c;
+      return fail(LK_ENODEV, "%u workers share one CU (at most %u asked); kernel did not end", c->max_on_a_cu,
+                  c->per_cu);
     }
+    return bail(fail(LK_ENODEV, "%u workers share one CU (at most %u asked)", c->max_on_a_cu, c->per_cu));
   }
   c->workers = ws;
   {
@@ -772,6 +796,8 @@ int lk_get_info(lk_ctx *c, lk_info *info) {
   info->dispose_ms = c->dispose_ms;
   info->kernel_ms = c->kernel_ms;
   info->device_span_ms = c->device_span_ms;
+  info->workers_per_cu = c->per_cu;
+  info->max_workers_on_a_cu = c->max_on_a_cu;
   return LK_OK;
 }
 

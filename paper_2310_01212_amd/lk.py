@@ -45,7 +45,7 @@ class Config(ctypes.Structure):
                 ("cluster_of_worker", ctypes.POINTER(ctypes.c_uint32)),
                 ("poll_sleep", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("log_capacity", ctypes.c_uint32), ("idle_timeout_ms", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64)]
+                ("workers_per_cu", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64)]
 
 
 class Desc(ctypes.Structure):
@@ -68,7 +68,8 @@ class Info(ctypes.Structure):
                 ("state", ctypes.c_uint32), ("workers_exited", ctypes.c_uint32),
                 ("wall_clock_hz", ctypes.c_uint64), ("init_ms", ctypes.c_double),
                 ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("device_span_ms", ctypes.c_double)]
+                ("device_span_ms", ctypes.c_double), ("workers_per_cu", ctypes.c_uint32),
+                ("max_workers_on_a_cu", ctypes.c_uint32)]
 
 
 class LogEntry(ctypes.Structure):
@@ -222,11 +223,12 @@ def _check_tensor(t, op, what):
 
 
 class Context:
-    """A running LightKernel context: persistent workers, one per CU (lk_init)."""
+    """A running LightKernel context: persistent workers, workers_per_cu on each CU
+    (lk_init)."""
 
     def __init__(self, n_workers=0, threads=256, depth=1, clusters=CLUSTERS_PER_WORKER,
                  cluster_of_worker=None, poll_sleep=0, flags=0, log_capacity=0,
-                 idle_timeout_ms=10000, init_timeout_s=5.0, device=0):
+                 idle_timeout_ms=10000, init_timeout_s=5.0, device=0, workers_per_cu=1):
         L = lib()
         cfg = Config()
         L.lk_config_default(ctypes.byref(cfg))
@@ -239,6 +241,7 @@ class Context:
         cfg.log_capacity = log_capacity
         cfg.idle_timeout_ms = idle_timeout_ms
         cfg.init_timeout_ns = int(init_timeout_s * 1e9)
+        cfg.workers_per_cu = workers_per_cu
         self._cow = None
         if cluster_of_worker is not None:
             cow = np.ascontiguousarray(cluster_of_worker, dtype=np.uint32)

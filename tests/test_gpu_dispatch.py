@@ -228,6 +228,35 @@ def test_all_cus_small_fifo_chains_bit_exact():
     assert topo == sorted(topo) and len(set(topo)) == lanes
 
 
+@pytest.mark.parametrize("per_cu,threads", [(2, 256), (4, 256), (2, 512)])
+def test_several_workers_per_cu_fifo_chains_bit_exact(per_cu, threads):
+    """k persistent workgroups on every CU, each with its own mailbox: FIFO chains exact,
+    exactly k workers on each physical CU, log invariants per worker."""
+    with lk.Context(n_workers=0, workers_per_cu=per_cu, threads=threads, log_capacity=64) as ctx:
+        info = ctx.info()
+        lanes = info["n_workers"]
+        say(f"{per_cu} workers per CU x {threads} threads: {lanes} lanes x 20 SAXPY items, ragged n")
+        assert lanes == info["cu_count"] * per_cu and info["max_workers_on_a_cu"] == per_cu
+        nl = lambda w: 600 + 37 * (w % 11)
+        X, Y0, A, span = _allcu_setup(ctx, 20, nl)
+        x, y = to_dev(X), to_dev(Y0)
+        torch.cuda.current_stream().synchronize()
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        n = np.array([nl(w) for w in range(lanes)], np.uint64)[:, None]
+        items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * span * 4, addr(y) + li * span * 4, alpha=A)
+        ctx.run_lanes(np.arange(lanes), items, in_flight=1, threads=8)
+        topo = [ctx.topology(w) for w in range(lanes)]
+    Y = y.cpu().numpy()
+    for w in range(lanes):
+        yr = Y0[w, :nl(w)].copy()
+        oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=X[w, :nl(w)].copy(), out=yr, alpha=a) for a in A[w]])
+        assert np.array_equal(Y[w, :nl(w)].view(np.uint32), yr.view(np.uint32)), w
+        check_log(ctx.log(w), 20, lk.CODE_WORK + lk.OP_SAXPY_F32)
+    assert topo == sorted(topo)
+    _, counts = np.unique(np.array(topo), axis=0, return_counts=True)
+    assert counts.size == lanes // per_cu and np.all(counts == per_cu)
+
+
 def test_all_cus_full_size_sampled_elements():
     """256 mailboxes x 10,000 back-to-back SAXPY items of 16,384 fp32; final y of 64
     sampled elements per lane against the oracle's 10,000-step fma chain."""
