@@ -497,6 +497,32 @@ def test_isolation_runner_critical_items_and_copies_exact():
     assert np.all(r["lat_us"] > 0) and np.all(r["late_us"] < r["lat_us"])
 
 
+def test_isolation_full_size_critical_items_and_256mib_copies_exact():
+    """The isolation workload at its full sizes: a 262,144-element critical item every
+    1 ms on XCD 0 (32 slices) while XCDs 1-7 copy private 256 MiB buffers."""
+    periods = 100
+    say(f"isolation full size: {periods} periods of 1 ms, 7 x 256 MiB copies")
+    xh, AB = workloads.isolation(periods=periods)
+    x = to_dev(xh)
+    y = sentinel_i32(xh.shape)
+    elems = workloads.ISO_COPY_ELEMS
+    srcs = [workloads.isolation_copy_source_device(c, elems, "cuda") for c in range(1, 8)]
+    dsts = [torch.zeros_like(t) for t in srcs]
+    torch.cuda.synchronize()
+    crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, addr(x), addr(y), AB[:, 0], AB[:, 1])
+    bg = lk.make_items(lk.OP_COPY_F32, elems, [addr(t) for t in srcs], [addr(d) for d in dsts])
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=30000) as ctx:
+        assert ctx.info()["n_clusters"] == 8
+        r = ctx.run_isolation(0, crit, 1e-3, list(range(1, 8)), bg)
+    for k in range(periods):
+        assert r["results"][k] == oracle.affine_sum_i32(xh, int(AB[k, 0]), int(AB[k, 1]))[1], k
+    yr, _ = oracle.affine_sum_i32(xh, int(AB[-1, 0]), int(AB[-1, 1]))
+    assert np.array_equal(y.cpu().numpy(), yr)
+    for t, d in zip(srcs, dsts):
+        assert torch.equal(t.view(torch.int32), d.view(torch.int32))
+    assert np.all(r["bg_done"] > 0)
+
+
 # ------------------------------------------------------------------ paper replay protocol
 def test_replay_protocol_runs_on_one_cu_and_all_cus():
     say("replay: 3 runs of Init/Trigger/Wait/Dispose vs Alloc/Spawn/Wait/Dispose, SPIN 20000")
@@ -577,6 +603,47 @@ def test_batches_in_flight_two_deep_keep_their_own_counters():
             lo, hi = int(off[i]), int(off[i]) + int(n[i])
             yr, sr = oracle.affine_sum_i32(xi[lo:hi].copy(), lk._i32(int(ab[i, 0]) + shift), int(ab[i, 1]))
             assert int(P[owner == i].sum()) == sr and np.array_equal(Z[lo:hi], yr)
+
+
+def test_batch_full_size_burst_of_4096_exact():
+    """The batching workload's largest evaluation burst at its full sizes (4096 items,
+    log-uniform 256 .. 2^20 elements, seed 5), one persistent batch over all CUs with
+    16,384-element tiles; every item checked."""
+    ops, n, ab, alpha = workloads.batching(4096, seed=5)
+    off = np.concatenate([[0], np.cumsum((n + 255) // 256 * 256)]).astype(np.uint64)
+    total = int(off[-1])
+    say(f"batch full size: 4096 items, {int(n.sum())} elements, tiles of 16384")
+    rng = np.random.default_rng(1005)
+    xi = rng.integers(0, 2 ** 32, total, dtype=np.uint32).view(np.int32)
+    xf = rng.standard_normal(total, dtype=np.float32)
+    yf = rng.standard_normal(total, dtype=np.float32)
+    d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf)
+    d_z = sentinel_i32((total,))
+    ins = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_xi), addr(d_xf)).astype(np.uint64) + off[:-1] * 4
+    outs = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_z), addr(d_yf)).astype(np.uint64) + off[:-1] * 4
+    items = lk.make_items(ops, n, ins, outs, ab[:, 0], ab[:, 1], alpha)
+    tiles, owner = lk.batch_plan(items, 16384)
+    d_tiles = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
+    partials = torch.zeros(tiles.size, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=8, idle_timeout_ms=30000) as ctx:
+        ctx.run_batch(0, d_tiles, tiles.size, partials, reps=1)
+    P = partials.cpu().numpy()
+    sums = np.bincount(owner, weights=None, minlength=4096)  # tiles per item
+    assert int(sums.sum()) == tiles.size
+    part_sum = np.zeros(4096, np.int64)
+    np.add.at(part_sum, owner, P)
+    Z, YF = d_z.cpu().numpy(), d_yf.cpu().numpy()
+    for i in range(4096):
+        lo, hi = int(off[i]), int(off[i]) + int(n[i])
+        if ops[i] == lk.OP_AFFINE_SUM_I32:
+            yr, sr = oracle.affine_sum_i32(xi[lo:hi].copy(), int(ab[i, 0]), int(ab[i, 1]))
+            assert int(part_sum[i]) == sr, i
+            assert np.array_equal(Z[lo:hi], yr), i
+        else:
+            want = yf[lo:hi].copy()
+            oracle.saxpy_f32(alpha[i], xf[lo:hi].copy(), want)
+            assert same_f32(YF[lo:hi], want), i
 
 
 def test_launch_burst_baseline_matches_oracle():
@@ -724,6 +791,34 @@ def test_serving_admission_waits_for_memory_budget():
     for i in range(count):
         if int(tr["kind"][i]) in (0, 1):
             assert outc["result"][i] == _oracle_request(tr, i, xi, xf, yf)[1], i
+
+
+def test_serving_full_size_requests_exact():
+    """Serving with the workload's full request sizes (log-uniform 256 .. 2^22 elements,
+    windows in resident pools of 2^26 elements), Poisson arrivals, tiles of 65,536, the
+    bench's context (depth 4); every result and every retained output checked."""
+    count = 300
+    tr, xi, xf, yf = _serve_setup(count, 23, pool_elems=1 << 26, log2=(8, 22))
+    say(f"serving full size: {count} requests, n up to 2^22, {int(tr['n'].sum())} elements")
+    d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf)
+    per_req = (tr["n"].astype(np.int64) * 4 + 255) // 256 * 256
+    per_shard = max(int(per_req[s::8].sum()) for s in range(8))
+    need = 8 * (per_shard + (1 << 16))
+    arena = torch.zeros(need // 4, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=0, depth=4, idle_timeout_ms=30000) as ctx:
+        outc, st = ctx.serve(_requests(tr, d_xi, d_xf, d_yf, tr["arrival_us"]), arena, need,
+                             tile_elems=65536, threads=8, retain=True)
+    assert np.all(outc["status"] == 0) and st["tiles"] == int(outc["tiles"].sum())
+    for i in range(count):
+        k, n = int(tr["kind"][i]), int(tr["n"][i])
+        yr, sr = _oracle_request(tr, i, xi, xf, yf)
+        if k in (0, 1):
+            assert outc["result"][i] == sr, i
+        if k == 0:
+            assert np.array_equal(_read_output(arena, outc, i, n, k), yr), i
+        elif k == 2:
+            assert same_f32(_read_output(arena, outc, i, n, k), yr), i
 
 
 def test_second_context_that_cannot_fit_is_refused_at_once():
