@@ -131,7 +131,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "the dispatch path has no multi-GPU component; see DESIGN.md for how it would shard.",
+              "the dispatch path has no multi-GPU component (each GPU would run a context of its own).",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "isolation":

@@ -31,7 +31,7 @@ def test_model_codes_are_table1():
     assert g[("to_GPU", "THREAD_WORK")] == pm.TO_WORK
 
 
-CONFIGS = [
+SYSTEMS = [
     pm.Config(((0,),), (0, 0, 0), 1),
     pm.Config(((0,),), (0, 0, 0), 2),
     pm.Config(((0,), (1,)), (0, 1, 0, 1), 1),
@@ -42,7 +42,7 @@ CONFIGS = [
 ]
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"{c.clusters}-{c.items}-d{c.depth}")
+@pytest.mark.parametrize("cfg", SYSTEMS, ids=lambda c: f"{c.clusters}-{c.items}-d{c.depth}")
 def test_protocol_holds_on_every_interleaving(cfg):
     n = pm.check(cfg)
     assert n > 10
@@ -56,7 +56,7 @@ def test_protocol_holds_on_every_interleaving(cfg):
 ])
 def test_checker_catches_planted_protocol_bugs(bug, expect):
     caught = 0
-    for cfg in CONFIGS[2:]:
+    for cfg in SYSTEMS[2:]:
         bad = pm.Config(cfg.clusters, cfg.items, cfg.depth, bug)
         try:
             pm.check(bad)
