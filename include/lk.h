@@ -152,7 +152,18 @@ typedef struct lk_config {
                                   that the register file holds all of them */
   int64_t init_timeout_ns;     /* lk_init: deadline for every worker to report INIT;
                                   0 = 5 s */
+  int32_t first_poll_delay;    /* pause, in s_sleep(1) units, between a worker's status
+                                  record and its first read of the next command slot:
+                                  LK_POLL_DELAY_ADAPTIVE (the default) learns it per worker,
+                                  0 = none, 1..127 = fixed.  A read issued right after the
+                                  status record usually reaches host memory before the host
+                                  has posted the next command and then costs a whole PCIe
+                                  round trip; the pause never delays a command that arrives
+                                  later than it */
+  uint32_t reserved;
 } lk_config;
+
+#define LK_POLL_DELAY_ADAPTIVE (-1)
 
 typedef struct lk_ctx lk_ctx;  /* opaque, owned by the library */
 

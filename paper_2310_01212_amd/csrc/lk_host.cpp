@@ -218,6 +218,8 @@ int validate_config(const lk_config *cfg) {
     return fail(LK_EINVAL, "unknown flags 0x%x", cfg->flags);
   if (cfg->init_timeout_ns < 0) return fail(LK_EINVAL, "init_timeout_ns < 0");
   if (cfg->log_capacity > (1u << 24)) return fail(LK_EINVAL, "log_capacity %u > 2^24", cfg->log_capacity);
+  if (cfg->first_poll_delay < LK_POLL_DELAY_ADAPTIVE || cfg->first_poll_delay > 127)
+    return fail(LK_EINVAL, "first_poll_delay %d: need -1 (adaptive) or 0..127", cfg->first_poll_delay);
   return LK_OK;
 }
 
@@ -262,6 +264,7 @@ void lk_config_default(lk_config *cfg) {
   cfg->log_capacity = 0;
   cfg->idle_timeout_ms = 10000;
   cfg->workers_per_cu = 1;
+  cfg->first_poll_delay = LK_POLL_DELAY_ADAPTIVE;
 }
 
 int lk_slice(uint64_t n, uint32_t k, uint32_t j, uint64_t *lo, uint64_t *hi) {
@@ -406,6 +409,8 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
             ((cfg.flags & LK_F_NO_ACQUIRE) ? LKW_K_NO_ACQUIRE : 0u);
   const uint32_t idle_ms = cfg.idle_timeout_ms ? cfg.idle_timeout_ms : 10000u;
   p.idle_ticks = c->wall_hz / 1000ull * idle_ms;
+  p.first_delay = cfg.first_poll_delay;
+  p.b2b_ticks = static_cast<uint32_t>(c->wall_hz / 100000ull);  // 10 us
 
   {
     std::string err;

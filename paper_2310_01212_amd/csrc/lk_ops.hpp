@@ -304,7 +304,8 @@ __device__ __forceinline__ void spin(uint32_t iters) {
 // Execute one slice with the calling workgroup of nt threads (the thread count is passed
 // explicitly: the persistent worker is dispatched without the runtime's implicit kernel
 // arguments); returns the slice's int64 result in thread 0 (0 elsewhere and for ops
-// without a result).  Ends with a barrier.
+// without a result).  Ops with a result end with the workgroup reduction; the others end
+// without a barrier, so a caller synchronises before it reuses LDS or publishes.
 template <class St>
 __device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uint32_t nt) {
   int64_t acc = 0;
@@ -337,7 +338,6 @@ __device__ __forceinline__ int64_t run_slice(const Slice &s, int64_t *s_red, uin
     }
   }
   if (s.op == 1 || s.op == 2) return block_sum_i64(acc, s_red, nt);
-  __syncthreads();
   return 0;
 }
 

@@ -118,6 +118,8 @@ typedef struct lkw_params {
   uint32_t flags;        /* LKW_K_* */
   uint32_t threads;      /* workgroup size (the worker reads no implicit kernel argument) */
   uint64_t idle_ticks;   /* watchdog, device wall-clock ticks */
+  int32_t first_delay;   /* s_sleep(1) units before the first poll after a completion; -1 = adaptive */
+  uint32_t b2b_ticks;    /* a command found this soon after a completion counts as back-to-back */
 } lkw_params;
 
 #define LKW_K_REPORT_WORKING 0x1u

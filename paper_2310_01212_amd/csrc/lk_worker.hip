@@ -59,7 +59,7 @@ __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_
     sl.a = uniform_u32(static_cast<uint32_t>(tile.a));
     sl.b = uniform_u32(tile.b);
     sl.alpha = __uint_as_float(sl.b);
-    const int64_t part = lkops::run_slice<lkops::SystemStore>(sl, s_red, nt);  // ends with a barrier
+    const int64_t part = lkops::run_slice<lkops::SystemStore>(sl, s_red, nt);
     if (threadIdx.x == 0) {
       st_sys_i64(partials + t, part);
       *s_next = next - base;
@@ -71,31 +71,28 @@ __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_
 }
 
 // Lanes 0..7 of wave 0 write the eight tagged words of a status record in one store.
+// Each lane picks its word with selects, so the wave does not branch per lane.
 __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uint32_t code, int64_t partial,
                                                uint64_t t_pick, uint64_t t_done, uint32_t hw, uint32_t xcc) {
   const uint32_t lane = threadIdx.x;
   const uint64_t tag = LKW_TAG(seq);
   const uint64_t up = static_cast<uint64_t>(partial);
   uint64_t v = tag;
-  switch (lane) {
-    case LKW_S_WORD: v = LKW_WORD(seq, code); break;
-    case LKW_S_PART_LO: v = tag | (up & 0xffffffffull); break;
-    case LKW_S_PART_HI: v = tag | (up >> 32); break;
-    case LKW_S_T_PICK: v = tag | (t_pick & LKW_PAYLOAD_MASK); break;
-    case LKW_S_T_DONE: v = tag | (t_done & LKW_PAYLOAD_MASK); break;
-    case LKW_S_HWID: v = tag | hw | (static_cast<uint64_t>(xcc & 0xffffu) << 32); break;
-    default: break;
-  }
+  v = lane == LKW_S_WORD ? LKW_WORD(seq, code) : v;
+  v = lane == LKW_S_PART_LO ? (tag | (up & 0xffffffffull)) : v;
+  v = lane == LKW_S_PART_HI ? (tag | (up >> 32)) : v;
+  v = lane == LKW_S_T_PICK ? (tag | (t_pick & LKW_PAYLOAD_MASK)) : v;
+  v = lane == LKW_S_T_DONE ? (tag | (t_done & LKW_PAYLOAD_MASK)) : v;
+  v = lane == LKW_S_HWID ? (tag | hw | (static_cast<uint64_t>(xcc & 0xffffu) << 32)) : v;
   st_sys(&st->w[lane], v);
 }
 
 // ----------------------------------------------------------------------------- worker
 extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
-  extern __shared__ uint64_t lds_reserve[];  // only holds the CU: one worker per CU
+  extern __shared__ uint64_t lds_reserve[];  // only holds the CU's LDS share
   __shared__ uint64_t s_w[LKW_CMD_WORDS];
-  __shared__ uint64_t s_t_pick, s_t_done, s_batch_next;
-  __shared__ int64_t s_partial;
-  __shared__ uint32_t s_mb, s_go, s_hw, s_xcc;
+  __shared__ uint64_t s_batch_next;
+  __shared__ uint32_t s_mb, s_go;
   __shared__ int64_t s_red[lkops::kMaxWaves];
   (void)lds_reserve;
   const uint32_t tid = threadIdx.x;
@@ -122,19 +119,30 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   lkw_cmd *ring = p.cmd + m * stride;
   lkw_status *sring = p.status + m * stride;
   lkw_worker *wr = p.workers + m;
-  uint64_t seq = 0;  // last sequence number executed by this worker
+  lkw_log *wlog = p.log ? p.log + static_cast<uint64_t>(m) * p.log_cap : nullptr;
+  uint64_t seq = 0;                                 // last sequence number executed by this worker
+  uint32_t slot = p.depth > 1 ? 1u : 0u;            // ring slot of seq + 1, kept without a division
+  uint32_t log_i = 0;                               // log entry of seq + 1
+  // Pause before the first poll after a completion (wave 0).  Adaptive: a back-to-back
+  // command missed by that first read lengthens it by 2 units, one it finds shortens it
+  // by 1, so the first read tends to arrive just after the host has posted.
+  uint32_t pre = 8;
 
   for (;;) {
     const uint64_t want = seq + 1;
-    const uint32_t slot = static_cast<uint32_t>(want % p.depth);
 
     // ---- poll: wave 0 reads the whole 64-byte slot, one 8-byte word per lane 0..7.
+    // Pickup time and placement are scalars of wave 0, kept in registers until the
+    // status record is written.
+    uint64_t t_pick = 0;
+    uint32_t hw = 0, xcc = 0;
     if (tid < 64) {
       const uint64_t *src = ring[slot].w;
       const uint64_t tag = want & 0xffffu;
       const uint64_t t0 = wall_clock64();
       uint32_t polls = 0, outcome = 0;
       uint64_t v = 0;
+      if (seq > 0) backoff(p.first_delay < 0 ? pre : static_cast<uint32_t>(p.first_delay));
       for (;;) {
         if (tid < LKW_CMD_WORDS) v = ld_sys(src + tid);
         bool ok = true;
@@ -152,16 +160,14 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
         }
         backoff(p.poll_sleep);
       }
-      if (outcome == 0) {
-        if (!(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        if (tid < LKW_CMD_WORDS) s_w[tid] = v;
-      }
-      if (tid == 0) {
-        s_go = outcome;
-        s_t_pick = wall_clock64();
-        s_hw = read_hw_id();
-        s_xcc = read_xcc_id();
-      }
+      if (p.first_delay < 0 && seq > 0 && outcome == 0 && wall_clock64() - t0 < p.b2b_ticks)
+        pre = polls == 0 ? (pre > 0 ? pre - 1 : 0u) : (pre + 2 > 96 ? 96u : pre + 2);
+      if (outcome == 0 && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      if (tid < LKW_CMD_WORDS) s_w[tid] = v;
+      if (tid == 0) s_go = outcome;
+      t_pick = wall_clock64();
+      hw = read_hw_id();
+      xcc = read_xcc_id();
     }
     __syncthreads();
 
@@ -172,10 +178,10 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       }
       return;
     }
-    const uint64_t w0 = s_w[LKW_W_DOORBELL];
+    const uint64_t w0 = uniform_u64(s_w[LKW_W_DOORBELL]);
     const uint32_t code = LKW_CODE(w0);
     if (code == LKW_TO_EXIT) {  // THREAD_EXIT (Table 1)
-      if (tid < LKW_S_WORDS) publish_status(sring + slot, want, LKW_FROM_EXITED, 0, s_t_pick, s_t_pick, s_hw, s_xcc);
+      if (tid < LKW_S_WORDS) publish_status(sring + slot, want, LKW_FROM_EXITED, 0, t_pick, t_pick, hw, xcc);
       if (tid == 0) {
         drain_wave_memory();
         st_sys(&wr->t_exit, wall_clock64());
@@ -204,37 +210,39 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     } else {
       reply = LKW_FROM_ERROR;
     }
-    const bool batch = s.op == lkd::kOpBatch;
-    const int64_t partial =
-        batch ? run_batch(static_cast<const lkd::Tile *>(s.in), s.n, static_cast<int64_t *>(s.out),
-                          reinterpret_cast<uint64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK),
+    int64_t partial = 0;
+    if (s.op == lkd::kOpBatch) {
+      partial = run_batch(static_cast<const lkd::Tile *>(s.in), s.n, static_cast<int64_t *>(s.out),
+                          reinterpret_cast<uint64_t *>(const_cast<void *>(s.in2)),
                           static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, &s_batch_next,
-                          p.threads)
-              : lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
+                          p.threads);
+    } else if (s.op != 0) {
+      partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
+    }
 
-    // ---- complete.  Thread 0 writes the optional per-member partial and the log record
-    // with system-coherent stores; every wave then waits until all of its stores have
-    // been acknowledged, and the barrier orders all of that before the status record.
-    if (tid == 0) {
+    // ---- complete.  Thread 0 writes the optional per-member partial with a
+    // system-coherent store; every wave then waits until all of its stores have been
+    // acknowledged, and the barrier orders all of that before the status record.
+    if (tid == 0 && s.in2 && (s.op == 1 || s.op == 2))  // ops with an int64 result
+      st_sys_i64(reinterpret_cast<int64_t *>(const_cast<void *>(s.in2)), partial);
+    drain_wave_memory();
+    __syncthreads();
+    if (tid < 64) {
       const uint64_t t_done = wall_clock64();
-      s_t_done = t_done;
-      s_partial = partial;
-      int64_t *aux = reinterpret_cast<int64_t *>(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK);
-      if (aux && (s.op == 1 || s.op == 2)) st_sys_i64(aux, partial);  // ops with an int64 result
-      if (p.log) {
-        lkw_log *e = p.log + static_cast<uint64_t>(m) * p.log_cap + (seq % p.log_cap);
+      const int64_t part0 = static_cast<int64_t>(uniform_u64(static_cast<uint64_t>(partial)));  // thread 0's
+      if (tid < LKW_S_WORDS) publish_status(sring + slot, want, reply, part0, t_pick, t_done, hw, xcc);
+      if (tid == 0 && wlog) {
+        lkw_log *e = wlog + log_i;
         const uint64_t head = static_cast<uint64_t>(static_cast<uint32_t>(want)) |
                               (static_cast<uint64_t>(code & 0xffffu) << 32) | (static_cast<uint64_t>(m & 0xffffu) << 48);
         st_sys(reinterpret_cast<uint64_t *>(e) + 0, head);
-        st_sys(reinterpret_cast<uint64_t *>(e) + 1, static_cast<uint64_t>(s_xcc) | (static_cast<uint64_t>(s_hw) << 32));
-        st_sys(&e->t_pick, s_t_pick);
+        st_sys(reinterpret_cast<uint64_t *>(e) + 1, static_cast<uint64_t>(xcc) | (static_cast<uint64_t>(hw) << 32));
+        st_sys(&e->t_pick, t_pick);
         st_sys(&e->t_done, t_done);
       }
     }
-    drain_wave_memory();
-    __syncthreads();
-    if (tid < LKW_S_WORDS) publish_status(sring + slot, want, reply, s_partial, s_t_pick, s_t_done, s_hw, s_xcc);
     seq = want;
+    slot = slot + 1 == p.depth ? 0u : slot + 1;
+    log_i = log_i + 1 == p.log_cap ? 0u : log_i + 1;
   }
 }
-

@@ -17,6 +17,7 @@ OK, EINVAL, EAGAIN, ETIMEDOUT, ESTATE, ENODEV, EHIP, EFAULT = 0, -1, -2, -3, -4,
 OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, OP_BATCH, OP_AXPY_F32 = range(8)
 CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
 F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
+POLL_DELAY_ADAPTIVE = -1
 COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
 
 # Table 1 values of the command codes recorded in the device log.
@@ -45,7 +46,8 @@ class Config(ctypes.Structure):
                 ("cluster_of_worker", ctypes.POINTER(ctypes.c_uint32)),
                 ("poll_sleep", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("log_capacity", ctypes.c_uint32), ("idle_timeout_ms", ctypes.c_uint32),
-                ("workers_per_cu", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64)]
+                ("workers_per_cu", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64),
+                ("first_poll_delay", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class Desc(ctypes.Structure):
@@ -228,7 +230,8 @@ class Context:
 
     def __init__(self, n_workers=0, threads=256, depth=1, clusters=CLUSTERS_PER_WORKER,
                  cluster_of_worker=None, poll_sleep=0, flags=0, log_capacity=0,
-                 idle_timeout_ms=10000, init_timeout_s=5.0, device=0, workers_per_cu=1):
+                 idle_timeout_ms=10000, init_timeout_s=5.0, device=0, workers_per_cu=1,
+                 first_poll_delay=POLL_DELAY_ADAPTIVE):
         L = lib()
         cfg = Config()
         L.lk_config_default(ctypes.byref(cfg))
@@ -242,6 +245,7 @@ class Context:
         cfg.idle_timeout_ms = idle_timeout_ms
         cfg.init_timeout_ns = int(init_timeout_s * 1e9)
         cfg.workers_per_cu = workers_per_cu
+        cfg.first_poll_delay = first_poll_delay
         self._cow = None
         if cluster_of_worker is not None:
             cow = np.ascontiguousarray(cluster_of_worker, dtype=np.uint32)

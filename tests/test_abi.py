@@ -42,17 +42,18 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_c_headers(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text('#include "lk.h"\n#include "lk_bench.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc),'
                    ' sizeof(lk_config), sizeof(lk_completion), sizeof(lk_info), sizeof(lk_log_entry), sizeof(lkb_item),'
                    ' offsetof(lk_config, init_timeout_ns), offsetof(lk_desc, aux), sizeof(lk_tile),'
-                   ' offsetof(lk_config, workers_per_cu), offsetof(lk_info, workers_per_cu)); return 0;}\n')
+                   ' offsetof(lk_config, workers_per_cu), offsetof(lk_info, workers_per_cu),'
+                   ' offsetof(lk_config, first_poll_delay)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(lk.Desc), ctypes.sizeof(lk.Config), ctypes.sizeof(lk.Completion),
             ctypes.sizeof(lk.Info), ctypes.sizeof(lk.LogEntry), lk.ITEM_DTYPE.itemsize,
             lk.Config.init_timeout_ns.offset, lk.Desc.aux.offset, lk.TILE_DTYPE.itemsize,
-            lk.Config.workers_per_cu.offset, lk.Info.workers_per_cu.offset]
+            lk.Config.workers_per_cu.offset, lk.Info.workers_per_cu.offset, lk.Config.first_poll_delay.offset]
     assert got == want
     assert lk.LOG_DTYPE.itemsize == ctypes.sizeof(lk.LogEntry)
     assert lk.COMPLETION_DTYPE.itemsize == ctypes.sizeof(lk.Completion)
@@ -113,6 +114,7 @@ def _cfg(**kw):
     ("threads_per_worker", 100), ("threads_per_worker", 2048), ("queue_depth", 65),
     ("cluster_policy", 9), ("poll_sleep", 200), ("idle_timeout_ms", 3600001),
     ("flags", 0x80), ("n_workers", 5000), ("init_timeout_ns", -1), ("workers_per_cu", 5),
+    ("first_poll_delay", -2), ("first_poll_delay", 128),
 ])
 def test_init_rejects_bad_config_before_touching_a_device(field, value):
     L = lk.lib()
@@ -130,7 +132,7 @@ def test_workers_per_cu_must_leave_every_worker_resident():
         assert "resident" in lk.last_error() and not h
     cfg = lk.Config()
     L.lk_config_default(ctypes.byref(cfg))
-    assert cfg.workers_per_cu == 1
+    assert cfg.workers_per_cu == 1 and cfg.first_poll_delay == lk.POLL_DELAY_ADAPTIVE
 
 
 def test_explicit_clusters_are_validated():

@@ -100,6 +100,24 @@ def test_plain_1000_items_bit_exact_with_log_invariants():
     assert info["state"] == 1 and info["kernel_ms"] > 0
 
 
+@pytest.mark.parametrize("delay", [0, 40, lk.POLL_DELAY_ADAPTIVE])
+def test_first_poll_delay_settings_keep_results_and_order(delay):
+    say(f"first poll delay {delay}: 1 worker x 300 affine+sum items of 4096 int32")
+    X, AB = workloads.plain(items=300)
+    x = to_dev(X)
+    y = sentinel_i32(X.shape)
+    rows = np.arange(X.shape[0], dtype=np.uint64)
+    items = lk.make_items(lk.OP_AFFINE_SUM_I32, X.shape[1], addr(x) + rows * X.shape[1] * 4,
+                          addr(y) + rows * X.shape[1] * 4, AB[:, 0], AB[:, 1])
+    with lk.Context(n_workers=1, first_poll_delay=delay, log_capacity=512) as ctx:
+        res, _, _, _ = ctx.run_serial(0, items)
+    Y = y.cpu().numpy()
+    for i in range(X.shape[0]):
+        yr, sr = oracle.affine_sum_i32(X[i], int(AB[i, 0]), int(AB[i, 1]))
+        assert res[i] == sr and np.array_equal(Y[i], yr), i
+    check_log(ctx.log(0), X.shape[0], lk.CODE_WORK + lk.OP_AFFINE_SUM_I32)
+
+
 # ------------------------------------------------------------------ edge cases on one worker
 EDGE_N = [0, 1, 3, 4, 5, 255, 256, 257, 1023, 4097, 65537, 1000003]
 
