@@ -251,6 +251,13 @@ LK_API int lk_wait_info(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int64_t 
 /* Non-blocking completion test: *done = 1 if every member finished `ticket`. */
 LK_API int lk_poll(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int *done);
 
+/* Hint for a host thread that drives many clusters: start fetching the cache lines it will
+ * touch next for `cluster` -- the status records of `ticket` (if it is posted and not yet
+ * released; 0 = none) and the command slots of the cluster's next ticket -- so that the
+ * misses on lines the GPU has just written or read overlap with work on other clusters.
+ * No effect on results.  Errors: LK_EINVAL, LK_ESTATE. */
+LK_API int lk_prefetch(lk_ctx *ctx, uint32_t cluster, uint64_t ticket);
+
 /* Dispose phase (Sec. 3; THREAD_EXIT, Table 1): post EXIT to every worker, wait for the
  * persistent kernel to end, copy the device log to the host and free every GPU
  * resource.  Idempotent.  The context object itself stays readable (lk_info,

@@ -200,8 +200,15 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
       stop.store(true);
     };
     uint64_t remaining = lanes.size() * items_per_lane;
+    const size_t nl = lanes.size();
+    constexpr size_t kAhead = 3;  // lanes between a prefetch and its use
     while (remaining && !stop.load(std::memory_order_relaxed)) {
-      for (Lane &L : lanes) {
+      for (size_t li = 0; li < nl; ++li) {
+        Lane &L = lanes[li];
+        if (nl > kAhead) {
+          const Lane &A = lanes[(li + kAhead) % nl];
+          (void)lk_prefetch(c, A.cluster, A.done < A.next ? A.first_ticket + A.done : 0);
+        }
         while (L.done < L.next) {
           const uint64_t t = L.first_ticket + L.done;
           int fin = 0;

@@ -716,6 +716,20 @@ int lk_poll(lk_ctx *c, uint32_t cluster, uint64_t t, int *done) {
   return LK_OK;
 }
 
+__attribute__((target("prfchw"))) int lk_prefetch(lk_ctx *c, uint32_t cluster, uint64_t t) {
+  if (!c) return fail(LK_EINVAL, "NULL context");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  const ClusterSeq &cs = c->seqs[cluster];
+  const bool pending = t > cs.consumed && t <= cs.posted;
+  const uint64_t next = cs.posted + 1;
+  for (uint32_t mb : c->cluster_mbox[cluster]) {
+    if (pending) __builtin_prefetch(slot_status(c, mb, t), 0, 3);
+    __builtin_prefetch(slot_cmd(c, mb, next), 1, 3);  // will be written
+  }
+  return LK_OK;
+}
+
 int lk_dispose(lk_ctx *c) {
   if (!c) return fail(LK_EINVAL, "NULL context");
   if (c->state == DISPOSED) return LK_OK;

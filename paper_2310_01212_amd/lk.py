@@ -25,7 +25,7 @@ CODE_NOP, CODE_EXIT, CODE_WORK = 4, 8, 16
 
 EXPORTED = [
     "lk_config_default", "lk_init", "lk_submit", "lk_submit_batch", "lk_batch_plan", "lk_wait", "lk_wait_info", "lk_poll",
-    "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
+    "lk_prefetch", "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
     "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_replay", "lkb_batch", "lkb_launch_burst",
     "lkb_launch_serial", "lks_run", "lkb_launch_lanes", "lkb_pingpong",
@@ -135,6 +135,7 @@ def lib():
         "lk_wait": (ctypes.c_int, [P, U32, U64, I64, PI64]),
         "lk_wait_info": (ctypes.c_int, [P, U32, U64, I64, ctypes.POINTER(Completion)]),
         "lk_poll": (ctypes.c_int, [P, U32, U64, ctypes.POINTER(ctypes.c_int)]),
+        "lk_prefetch": (ctypes.c_int, [P, U32, U64]),
         "lk_dispose": (ctypes.c_int, [P]),
         "lk_free": (ctypes.c_int, [P]),
         "lk_get_info": (ctypes.c_int, [P, ctypes.POINTER(Info)]),
@@ -321,6 +322,10 @@ class Context:
         d = ctypes.c_int()
         _check(lib().lk_poll(self._h, cluster, ticket, ctypes.byref(d)), "lk_poll")
         return bool(d.value)
+
+    def prefetch(self, cluster, ticket=0):
+        """Hint: fetch the cluster's status lines of `ticket` and its next command slots."""
+        _check(lib().lk_prefetch(self._h, cluster, ticket), "lk_prefetch")
 
     def close(self):
         """Dispose: THREAD_EXIT to every worker, join the kernel, free GPU resources."""

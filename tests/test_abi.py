@@ -157,6 +157,7 @@ def test_calls_on_a_null_context_fail_cleanly():
     assert L.lk_submit(None, 0, ctypes.byref(d), None, None, ctypes.byref(t)) == lk.EINVAL
     assert L.lk_wait(None, 0, 1, 0, ctypes.byref(r)) == lk.EINVAL
     assert L.lk_dispose(None) == lk.EINVAL
+    assert L.lk_prefetch(None, 0, 0) == lk.EINVAL
     assert L.lk_free(None) == lk.OK
     assert L.lk_init(None, None) == lk.EINVAL
 

@@ -394,9 +394,17 @@ def test_ring_full_timeout_and_disposed_state():
             ctx.wait(0, t1)
         assert e.value.code == lk.EINVAL   # already released
         t2 = ctx.submit(0, lk.OP_NOP)
+        ctx.prefetch(0, t2)  # a hint: no effect on the result
         assert ctx.wait(0, t2) == 0
+        ctx.prefetch(0, t2)  # released ticket: only the next command slot
+        with pytest.raises(lk.LKError) as e:
+            ctx.prefetch(1, 0)
+        assert e.value.code == lk.EINVAL
     with pytest.raises(lk.LKError) as e:
         ctx.submit(0, lk.OP_NOP)
+    assert e.value.code == lk.ESTATE
+    with pytest.raises(lk.LKError) as e:
+        ctx.prefetch(0, 0)
     assert e.value.code == lk.ESTATE
     ctx.close()  # idempotent
 
