@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblk.so")
 WORKER_CO = os.path.join(HERE, "lk_worker.hsaco")
 
-SOURCES = ["lk_device.hip", "lk_host.cpp", "lk_queue.cpp", "lk_bench.cpp", "lk_serve.cpp"]
+SOURCES = ["lk_backend_hip.cpp", "lk_device.hip", "lk_host.cpp", "lk_queue.cpp", "lk_bench.cpp", "lk_serve.cpp"]
 WORKER_SOURCE = "lk_worker.hip"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -9,7 +9,6 @@
  * fine-grained host-coherent memory that the workers read and write directly over PCIe,
  * so the host side of a dispatch is a handful of ordinary stores and loads.
  */
-#include <hip/hip_runtime_api.h>
 #include <immintrin.h>
 
 #include <algorithm>
@@ -25,8 +24,8 @@
 #include <vector>
 
 #include "lk.h"
-#include "lk_device.h"
-#include "lk_queue.h"
+#include "lk_backend.h"
+#include "lk_common.h"
 #include "lk_wire.h"
 
 namespace {
@@ -44,9 +43,6 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-int hip_fail(hipError_t e, const char *what) {
-  return fail(LK_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
 
 using clk = std::chrono::steady_clock;
 
@@ -109,7 +105,7 @@ struct lk_ctx {
   uint32_t log_cap = 0;
   uint64_t wall_hz = 100000000ull;
   State state = RUNNING;
-  lkq::Queue wq;  // the persistent worker's own HSA queue
+  lkbe::Dispatch *wq = nullptr;  // the persistent dispatch (its own hardware queue)
   void *host_region = nullptr;
   lkw_cmd *cmd = nullptr;
   lkw_status *status = nullptr;
@@ -227,12 +223,13 @@ int validate_config(const lk_config *cfg) {
 void release_gpu(lk_ctx *c) {
   if (c->cus_reserved) release_cus(c->device, c->cus_held);
   c->cus_reserved = false;
-  c->wq.close();
-  if (c->d_batch_counters) (void)hipFree(c->d_batch_counters);
+  delete c->wq;
+  c->wq = nullptr;
+  lkbe::device_free(c->d_batch_counters);
   c->d_batch_counters = nullptr;
-  if (c->d_log) (void)hipFree(c->d_log);
-  if (c->d_claim) (void)hipFree(c->d_claim);
-  if (c->host_region) (void)hipHostFree(c->host_region);
+  lkbe::device_free(c->d_log);
+  lkbe::device_free(c->d_claim);
+  lkbe::host_free(c->host_region);
   c->d_log = nullptr;
   c->d_claim = nullptr;
   c->host_region = nullptr;
@@ -245,7 +242,7 @@ void release_gpu(lk_ctx *c) {
 bool join_kernel(lk_ctx *c, double seconds) {
   const auto deadline = clk::now() + std::chrono::duration<double>(seconds);
   for (;;) {
-    if (c->wq.finished()) return true;
+    if (!c->wq || c->wq->finished()) return true;
     if (clk::now() > deadline) return false;
     std::this_thread::sleep_for(std::chrono::microseconds(200));
   }
@@ -298,25 +295,17 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   if (rc) return rc;
   lk_config cfg = *cfg_in;
 
-  int ndev = 0;
-  hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess || ndev == 0) return fail(LK_ENODEV, "no HIP device (%s)", hipGetErrorString(e));
-  if (cfg.device < 0 || cfg.device >= ndev) return fail(LK_EINVAL, "device %d of %d", cfg.device, ndev);
-  if ((e = hipSetDevice(cfg.device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipDeviceProp_t prop;
-  if ((e = hipGetDeviceProperties(&prop, cfg.device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(LK_ENODEV, "device %d is %s; this library is built for gfx950", cfg.device, prop.gcnArchName);
-  // The one-worker-per-CU layout relies on LKW_LDS_PAD_BYTES fitting a CU once, not twice.
-  if (prop.maxSharedMemoryPerMultiProcessor < LKW_LDS_PAD_BYTES + 4096 ||
-      prop.maxSharedMemoryPerMultiProcessor >= 2 * LKW_LDS_PAD_BYTES)
-    return fail(LK_ENODEV, "unexpected LDS size %zu per CU", prop.maxSharedMemoryPerMultiProcessor);
+  lkbe::DeviceInfo dev;
+  {
+    std::string err;
+    if ((rc = lkbe::device_info(cfg.device, &dev, &err)) != LK_OK) return fail(rc, "%s", err.c_str());
+  }
 
   auto *c = new lk_ctx();
   c->cfg = cfg;
   c->cfg.cluster_of_worker = nullptr;
   c->device = cfg.device;
-  c->cu_count = static_cast<uint32_t>(prop.multiProcessorCount);
+  c->cu_count = dev.cu_count;
   c->per_cu = cfg.workers_per_cu ? cfg.workers_per_cu : 1;
   c->n_workers = cfg.n_workers ? cfg.n_workers : c->cu_count * c->per_cu;
   c->depth = cfg.queue_depth ? cfg.queue_depth : 1;
@@ -331,23 +320,21 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   // Dynamic LDS per worker: one worker per CU takes 96 KiB, so a second never fits;
   // k workers per CU take an even share of the CU's LDS less 2 KiB (room for the static
   // LDS and the allocation granule), so k fit and k + 1 do not.
-  const uint32_t lds_cu = static_cast<uint32_t>(prop.maxSharedMemoryPerMultiProcessor);
+  const uint32_t lds_cu = dev.lds_per_cu;
   const uint32_t lds_pad = c->per_cu == 1 ? LKW_LDS_PAD_BYTES : (lds_cu / c->per_cu - 2048u) / 256u * 256u;
   {
     // Until the hardware ids are known every worker may sit on a CU of its own.
     uint32_t in_use = 0;
     c->cus_held = std::min(c->n_workers, c->cu_count);
     if (!reserve_cus(cfg.device, c->cus_held, c->cu_count, &in_use)) {
-      const uint32_t want = c->cus_held;
+      const uint32_t want = c->cus_held, cus = c->cu_count;
       delete c;
       return fail(LK_ENODEV, "%u CUs needed but this process's running contexts already hold %u of the %u CUs", want,
-                  in_use, c->cu_count);
+                  in_use, cus);
     }
     c->cus_reserved = true;
   }
-  int wc_khz = 0;
-  if (hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, cfg.device) == hipSuccess && wc_khz > 0)
-    c->wall_hz = static_cast<uint64_t>(wc_khz) * 1000ull;
+  c->wall_hz = dev.wall_hz;
 
   auto bail = [&](int code) {
     release_gpu(c);
@@ -361,9 +348,9 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   const size_t wr_bytes = sizeof(lkw_worker) * c->n_workers;
   auto up = [](size_t v) { return (v + 4095) & ~static_cast<size_t>(4095); };
   const size_t region = up(cmd_bytes) + up(st_bytes) + up(wr_bytes);
-  e = hipHostMalloc(&c->host_region, region, hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable);
-  if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc(coherent mailboxes)"));
-  memset(c->host_region, 0, region);
+  std::string err;
+  if ((rc = lkbe::host_alloc(cfg.device, region, &c->host_region, &err)) != LK_OK)
+    return bail(fail(rc, "mailboxes: %s", err.c_str()));
   char *base = static_cast<char *>(c->host_region);
   c->cmd = reinterpret_cast<lkw_cmd *>(base);
   c->status = reinterpret_cast<lkw_status *>(base + up(cmd_bytes));
@@ -371,28 +358,25 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   // Mark every worker record as not yet booted (INIT is 0, so use an impossible word).
   for (uint32_t m = 0; m < c->n_workers; ++m) store_release(&c->wrec[m].word, LKW_WORD(~0ull >> 8, 0xffu));
 
-  if ((e = hipMalloc(&c->d_claim, 256)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(claim)"));
-  if ((e = hipMemset(c->d_claim, 0, 256)) != hipSuccess) return bail(hip_fail(e, "hipMemset(claim)"));
+  if ((rc = lkbe::device_alloc(cfg.device, 256, reinterpret_cast<void **>(&c->d_claim), &err)) != LK_OK)
+    return bail(fail(rc, "claim counter: %s", err.c_str()));
   // Tile counters of batches: one per (cluster, ring slot) -- there are at most n_workers
   // clusters -- 128 bytes apart and never reset: each batch advances its counter by
   // n_tiles + members (every member's last claim overshoots once), which the host adds to
   // that slot's base.
   {
     const size_t cb = static_cast<size_t>(c->n_workers) * c->depth * 128;
-    if ((e = hipMalloc(&c->d_batch_counters, cb)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(batch counters)"));
-    if ((e = hipMemset(c->d_batch_counters, 0, cb)) != hipSuccess) return bail(hip_fail(e, "hipMemset(batch counters)"));
+    if ((rc = lkbe::device_alloc(cfg.device, cb, reinterpret_cast<void **>(&c->d_batch_counters), &err)) != LK_OK)
+      return bail(fail(rc, "batch counters: %s", err.c_str()));
   }
   if (c->log_cap) {
     const size_t lb = sizeof(lkw_log) * c->n_workers * static_cast<size_t>(c->log_cap);
-    if ((e = hipMalloc(&c->d_log, lb)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(log)"));
-    if ((e = hipMemset(c->d_log, 0, lb)) != hipSuccess) return bail(hip_fail(e, "hipMemset(log)"));
+    if ((rc = lkbe::device_alloc(cfg.device, lb, reinterpret_cast<void **>(&c->d_log), &err)) != LK_OK)
+      return bail(fail(rc, "log: %s", err.c_str()));
   }
 
-  // The persistent worker runs on a hardware queue of its own (lk_queue.cpp).
-  {
-    std::string err;
-    if (!c->wq.open(cfg.device, err)) return bail(fail(LK_EHIP, "worker queue: %s", err.c_str()));
-  }
+  // The persistent worker runs on a hardware queue of its own.
+  if (!(c->wq = lkbe::open_dispatch(cfg.device, &err))) return bail(fail(LK_EHIP, "worker queue: %s", err.c_str()));
 
   lkw_params p{};
   p.cmd = c->cmd;
@@ -412,11 +396,8 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   p.first_delay = cfg.first_poll_delay;
   p.b2b_ticks = static_cast<uint32_t>(c->wall_hz / 100000ull);  // 10 us
 
-  {
-    std::string err;
-    if (!c->wq.dispatch(p, c->n_workers, c->threads, lds_pad, err))
-      return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
-  }
+  if (!c->wq->start(p, c->n_workers, c->threads, lds_pad, &err))
+    return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
   c->kernel_launched = true;
 
   // Boot handshake: every worker reports INIT with its placement.
@@ -428,7 +409,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
     booted = 0;
     for (uint32_t m = 0; m < c->n_workers; ++m) booted += load_acquire(&c->wrec[m].word) == LKW_WORD(0, LKW_FROM_INIT);
     if (booted == c->n_workers) break;
-    if (c->wq.finished()) {
+    if (c->wq->finished()) {
       early_end = true;
       break;
     }
@@ -763,11 +744,12 @@ int lk_dispose(lk_ctx *c) {
     c->state = POISONED;
     return fail(LK_ETIMEDOUT, "persistent kernel did not end after EXIT (context poisoned)");
   }
-  c->kernel_ms = c->wq.kernel_ms();
+  c->kernel_ms = c->wq ? c->wq->kernel_ms() : 0.0;
   if (c->d_log && c->log_cap) {
     c->host_log.resize(static_cast<size_t>(c->n_workers) * c->log_cap);
-    const hipError_t e = hipMemcpy(c->host_log.data(), c->d_log, sizeof(lkw_log) * c->host_log.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) c->host_log.clear();
+    std::string err;
+    if (lkbe::device_to_host(c->host_log.data(), c->d_log, sizeof(lkw_log) * c->host_log.size(), &err) != LK_OK)
+      c->host_log.clear();
   }
   // Worker records survive for lk_get_info: keep a copy of the exit codes and the span
   // from the first boot to the last exit on the device wall clock.
