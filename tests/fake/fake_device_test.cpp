@@ -353,6 +353,25 @@ static void dispose_in_flight() {
   printf("OK %s\n", g_case);
 }
 
+// Dispose while a worker is hung: LK_ETIMEDOUT and a poisoned context whose resources stay
+// allocated; once the worker runs again a second dispose completes.
+static void dispose_hung_worker() {
+  g_case = "dispose_hung_worker";
+  lk_ctx *c = open_ctx(2, 1, LK_CLUSTERS_PER_WORKER, 100);  // dispose gives up after 5 s + 0.1 s
+  lkfake_freeze(1);
+  CHECK(lk_dispose(c) == LK_ETIMEDOUT);
+  lk_info info;
+  CHECK(lk_get_info(c, &info) == LK_OK && info.state == 2);
+  lk_desc nop = desc(LK_OP_NOP, 0);
+  uint64_t t;
+  CHECK(lk_submit(c, 0, &nop, nullptr, nullptr, &t) == LK_ESTATE);
+  lkfake_freeze(-1);
+  CHECK(lk_dispose(c) == LK_OK);
+  CHECK(lk_get_info(c, &info) == LK_OK && info.state == 1);
+  lk_free(c);
+  printf("OK %s\n", g_case);
+}
+
 // A second context that would need more CUs than are left is refused at once.
 static void cu_reservation() {
   g_case = "cu_reservation";
@@ -379,6 +398,7 @@ int main() {
   serving();
   idle_watchdog();
   dispose_in_flight();
+  dispose_hung_worker();
   cu_reservation();
   printf("ALL OK\n");
   return 0;

@@ -124,15 +124,17 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
     uint32_t spins = 0;
     bool timed_out = false;
     for (;;) {
-      if (g_frozen.load(std::memory_order_relaxed) != static_cast<int>(m)) {
-        w[0] = ld_acq(src);
-        bool ok = LKW_SEQ(w[0]) == want;
-        for (int i = 1; ok && i < LKW_CMD_WORDS; ++i) {
-          w[i] = ld_acq(src + i);
-          ok = (w[i] >> LKW_TAG_SHIFT) == (want & 0xffffu);
-        }
-        if (ok) break;
+      if (g_frozen.load(std::memory_order_relaxed) == static_cast<int>(m)) {  // hung: no poll, no watchdog
+        relax(spins);
+        continue;
       }
+      w[0] = ld_acq(src);
+      bool ok = LKW_SEQ(w[0]) == want;
+      for (int i = 1; ok && i < LKW_CMD_WORDS; ++i) {
+        w[i] = ld_acq(src + i);
+        ok = (w[i] >> LKW_TAG_SHIFT) == (want & 0xffffu);
+      }
+      if (ok) break;
       if (wall_ticks() - t0 > p.idle_ticks) {
         timed_out = true;
         break;
