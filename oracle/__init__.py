@@ -188,9 +188,17 @@ _ITEM_NP = np.dtype({"names": [f[0] for f in _Item._fields_],
                      "itemsize": ctypes.sizeof(_Item)})
 
 
+class PackedChain:
+    """Item records for orc_run_fifo plus references to the arrays they point into."""
+
+    def __init__(self, items, keep):
+        self.items = items
+        self._keep = keep
+
+
 def pack_chain(op, inp, out, alphas, a=0, b=0, n=None, in2=None):
     """A FIFO list of len(alphas) items that share op, operands and (a, b) and differ in
-    alpha, as an array run_packed accepts. The arrays must outlive the packed list."""
+    alpha, for run_packed (the list keeps its operand arrays alive)."""
     if n is None:
         n = (inp if inp is not None else out).size
     alphas = np.ascontiguousarray(alphas, dtype=np.float32)
@@ -198,12 +206,13 @@ def pack_chain(op, inp, out, alphas, a=0, b=0, n=None, in2=None):
     arr["op"], arr["n"], arr["a"], arr["b"] = op, n, a, b
     arr["alpha"] = alphas
     arr["inp"], arr["out"], arr["in2"] = (_ptr(inp) or 0), (_ptr(out) or 0), (_ptr(in2) or 0)
-    return arr
+    return PackedChain(arr, (inp, out, in2))
 
 
-def run_packed(arr):
-    """orc_run_fifo over an array made by pack_chain; returns the int64 results."""
-    if arr.dtype != _ITEM_NP or not arr.flags.c_contiguous:
+def run_packed(chain):
+    """orc_run_fifo over a list made by pack_chain; returns the int64 results."""
+    arr = chain.items if isinstance(chain, PackedChain) else None
+    if arr is None or arr.dtype != _ITEM_NP or not arr.flags.c_contiguous:
         raise ValueError("not a packed item list")
     res = np.zeros(arr.size, dtype=np.int64)
     rc = lib().orc_run_fifo(ctypes.cast(arr.ctypes.data, ctypes.POINTER(_Item)), arr.size, _ptr(res))

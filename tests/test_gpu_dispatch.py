@@ -246,6 +246,32 @@ def test_all_cus_small_fifo_chains_bit_exact():
     assert topo == sorted(topo) and len(set(topo)) == lanes
 
 
+def test_rotating_buffer_pairs_chains_bit_exact():
+    """The cold pattern: each mailbox's items rotate through P (x, y) pairs (item k uses
+    pair k mod P); every pair's final y is the oracle's chain of its own alphas."""
+    P, items, n = 4, 40, 2048
+    with lk.Context(n_workers=0, threads=1024, idle_timeout_ms=20000) as ctx:
+        lanes = ctx.info()["n_workers"]
+        say(f"rotating pairs: {lanes} lanes x {P} pairs x {items} SAXPY items of {n}")
+        rng = np.random.default_rng(61)
+        X = rng.standard_normal((lanes, P, n)).astype(np.float32)
+        Y0 = rng.standard_normal((lanes, P, n)).astype(np.float32)
+        A = rng.uniform(-2, 2, (lanes, items)).astype(np.float32)
+        x, y = to_dev(X), to_dev(Y0)
+        torch.cuda.current_stream().synchronize()
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        pair = (np.arange(items) % P).astype(np.uint64)[None, :]
+        off = (li * P + pair) * n * 4
+        ctx.run_lanes(np.arange(lanes), lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + off, addr(y) + off, alpha=A),
+                      in_flight=1, threads=8)
+    Y = y.cpu().numpy()
+    for w in range(lanes):
+        for p in range(P):
+            xr, yr = X[w, p].copy(), Y0[w, p].copy()  # the packed list points into both
+            oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, xr, yr, A[w, p::P]))
+            assert np.array_equal(Y[w, p].view(np.uint32), yr.view(np.uint32)), (w, p)
+
+
 @pytest.mark.parametrize("per_cu,threads", [(2, 256), (4, 256), (2, 512)])
 def test_several_workers_per_cu_fifo_chains_bit_exact(per_cu, threads):
     """k persistent workgroups on every CU, each with its own mailbox: FIFO chains exact,
