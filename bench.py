@@ -427,7 +427,8 @@ def bench_isolation(args):
             wall = 1e8
             span = (r["info"]["t_done_max"] - r["info"]["t_pick_min"]) / wall * 1e6
             v = {"latency_us": lat_summary(r["lat_us"]), "device_span_us": lat_summary(span),
-                 "release_lateness_us": lat_summary(r["late_us"]), "elapsed_s": round(r["elapsed_s"], 3)}
+                 "release_lateness_us": lat_summary(r["late_us"]),
+                 "submit_to_done_us": lat_summary(r["lat_us"] - r["late_us"]), "elapsed_s": round(r["elapsed_s"], 3)}
             if bgc:
                 copied = float(r["bg_done"].sum()) * 2 * (elems * 4)
                 v["interference_copy_gbps"] = round(copied / r["elapsed_s"] / 1e9, 1)
