@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--cold-pairs", type=int, default=16,
                     help="(x, y) pairs each mailbox rotates through in the cold variant, 512 MiB in "
                          "aggregate at 16 (0/1 = skip)")
+    ap.add_argument("--no-pinned", dest="pinned", action="store_false",
+                    help="skip the pinned-input (x kept in LDS) variants")
     ap.add_argument("--variant-per-cu", type=int, default=2,
                     help="workers per CU of the variant reported beside the one-per-CU headline (0/1 = skip)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
@@ -648,6 +650,62 @@ def bench_allcu(args):
                                       "kernel_ms": round(cinfo["device_span_ms"], 3), "items_per_launch": c_items,
                                       "achieved_gbps": round(c_gbps, 1), "frac_of_peak": round(c_gbps / HBM_PEAK_GBPS, 4)}
             log(f"cold ({P} pairs per mailbox): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
+
+        # pinned-input variants: x kept in each worker's LDS across items (descriptor flag
+        # DF_PIN_INPUT).  "hot" is the headline workload with the flag; "y_cold" keeps x per
+        # mailbox and rotates y through P buffers (512 MiB at P = 32, past the Infinity
+        # Cache), run without and with the flag, so HBM carries 12n or 8n bytes per item
+        if args.pinned:
+            def timed(ctx_kw, items_of_step, nsteps):
+                with lk.Context(n_workers=lanes, threads=args.threads_per_worker, poll_sleep=args.poll_sleep,
+                                idle_timeout_ms=60000, **ctx_kw) as cx:
+                    cx.run_lanes(np.arange(lanes), items_of_step(0), in_flight=1, threads=args.threads)
+                    ll, tt = [], 0.0
+                    for s in range(1, nsteps):
+                        _, lat, el = cx.run_lanes(np.arange(lanes), items_of_step(s), in_flight=1,
+                                                  threads=args.threads)
+                        ll.append(lat)
+                        tt += el
+                inf = cx.info()
+                ll = np.concatenate([l.ravel() for l in ll])
+                return ll, tt, inf
+
+            psteps = min(4, args.warmup + args.steps)
+            pin_items = []
+            for s in range(psteps):
+                it = step_items(s).copy()
+                it["flags"] = lk.DF_PIN_INPUT
+                pin_items.append(it)
+            pl, pt, pinf = timed({}, lambda s: pin_items[s], psteps)
+            pv = {"workload": "the headline workload with x pinned", "items_per_s": round(pl.size / pt, 1),
+                  "latency_us": lat_summary(pl), "items": int(pl.size),
+                  "pin_capacity_bytes": pinf["pin_capacity"]}
+            log(f"pinned (hot): {pl.size / pt:,.0f} items/s")
+            P = 32
+            g = torch.Generator(device=dev)
+            g.manual_seed(3)
+            ycold = torch.randn((lanes, P, n), generator=g, device=dev, dtype=torch.float32)
+            torch.cuda.synchronize()
+            ycit = {0: [], lk.DF_PIN_INPUT: []}
+            for s in range(psteps):
+                pair = ((s * per + np.arange(per)) % P).astype(np.uint64)[None, :]
+                yo = ycold.data_ptr() + (li * P + pair) * n * 4
+                for fl in ycit:
+                    ycit[fl].append(lk.make_items(lk.OP_SAXPY_F32, n, x_addr, yo, alpha=A[:, s * per:(s + 1) * per],
+                                                  flags=fl))
+            for fl, key in ((0, "y_cold_unpinned"), (lk.DF_PIN_INPUT, "y_cold_pinned")):
+                yl, yt, yinf = timed({}, lambda s, fl=fl: ycit[fl][s], psteps)
+                y_items = lanes * per * psteps
+                hbm = (8 if fl else 12) * n
+                gbps = y_items * hbm / (yinf["device_span_ms"] * 1e-3) / 1e9
+                pv[key] = {"y_buffers_per_mailbox": P, "y_footprint_bytes": lanes * P * n * 4,
+                           "items_per_s": round(yl.size / yt, 1), "latency_us": lat_summary(yl),
+                           "kernel_ms": round(yinf["device_span_ms"], 3), "items_per_launch": y_items,
+                           "hbm_bytes_per_item": hbm, "achieved_gbps": round(gbps, 1),
+                           "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+                log(f"{key}: {yl.size / yt:,.0f} items/s, {gbps:,.0f} GB/s")
+            del ycold
+            result["pinned_variant"] = pv
 
         # serial single-worker comparison (1 CU, 1000 affine+sum items of 4096 int32)
         Xs, ABs = workloads.plain()

@@ -93,7 +93,7 @@ enum {
  * the work").  The in/out references are passed beside it to lk_submit. */
 typedef struct lk_desc {
   uint32_t op;        /* LK_OP_* */
-  uint32_t flags;     /* reserved, must be 0 */
+  uint32_t flags;     /* LK_DF_*; 0 for plain items */
   uint64_t n;         /* element count, 0 .. LK_MAX_N; 0 is a valid no-op with result 0 */
   int32_t a, b;       /* AFFINE_SUM_I32 coefficients; SPIN: a = iterations */
   float alpha;        /* SAXPY_F32 coefficient */
@@ -103,6 +103,26 @@ typedef struct lk_desc {
                          0 = none; AXPY_F32: the device address of y (required) */
   uint64_t user_tag;  /* opaque to the library; not interpreted */
 } lk_desc;
+
+/* Descriptor flags: keep x of a SAXPY_F32 / AXPY_F32 item in each member worker's local
+ * data share (LDS) across items, mapping that operand onto the cluster that computes with
+ * it (Sec. 2.1: clusters are exposed so that data, as well as work, can be placed on
+ * them, and their local memories keep data next to the computation).
+ *
+ *  LK_DF_PIN_INPUT   a member whose pinned copy has the same slice address and length
+ *                    reads x from LDS instead of memory; otherwise it reads x from memory
+ *                    and keeps it.  By setting the flag the caller promises that those
+ *                    bytes are unchanged since the member pinned them.
+ *  LK_DF_PIN_RELOAD  as LK_DF_PIN_INPUT, but always reads x from memory and replaces the
+ *                    pinned copy: use it on the first item after x has changed.
+ *
+ * Each worker holds one pinned slice.  Items without these flags leave it in place.
+ * lk_submit rejects a flagged item (LK_EINVAL) unless: the op is SAXPY_F32 or AXPY_F32;
+ * in, out and (AXPY_F32) y are 16-byte aligned; and every member's slice is a multiple
+ * of 4 elements of at most lk_info.pin_capacity bytes.  n = 0 is accepted and pins
+ * nothing.  Batches take no flags. */
+#define LK_DF_PIN_INPUT  0x1u
+#define LK_DF_PIN_RELOAD 0x2u
 
 /* ------------------------------------------------------------------ clusters
  * Workers are numbered 0..n_workers-1 in physical order (XCD, shader engine, shader
@@ -284,6 +304,8 @@ typedef struct lk_info {
                                   wall clock (after lk_dispose) */
   uint32_t workers_per_cu;     /* as configured */
   uint32_t max_workers_on_a_cu; /* most workers found on one physical CU at boot */
+  uint32_t pin_capacity;       /* bytes of x one worker can keep pinned (LK_DF_PIN_INPUT) */
+  uint32_t reserved;
 } lk_info;
 
 LK_API int lk_get_info(lk_ctx *ctx, lk_info *info);

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-/* One work item with its in/out references (48 bytes). */
+/* One work item with its in/out references (56 bytes). */
 typedef struct lkb_item {
   uint32_t op;      /* LK_OP_* */
   int32_t a, b;     /* AFFINE_SUM_I32 coefficients; SPIN: a = iterations */
@@ -42,6 +42,9 @@ typedef struct lkb_item {
   uint64_t n;       /* elements */
   uint64_t in, out; /* device addresses */
   uint64_t in2;     /* AXPY_F32: device address of y; 0 otherwise */
+  uint32_t flags;   /* LK_DF_* descriptor flags: honoured by the persistent paths, ignored
+                       by the per-launch ones (a launched kernel keeps nothing across items) */
+  uint32_t reserved;
 } lkb_item;
 
 /* Submit-then-wait each item on `cluster` in order (the paper's Trigger then Wait).

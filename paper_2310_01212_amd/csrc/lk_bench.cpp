@@ -53,6 +53,7 @@ lk_desc to_desc(const lkb_item &it) {
   d.b = it.b;
   d.alpha = it.alpha;
   d.aux = it.op == LK_OP_AXPY_F32 ? it.in2 : 0;
+  d.flags = it.flags;
   return d;
 }
 

@@ -102,6 +102,7 @@ struct lk_ctx {
   uint32_t n_workers = 0, depth = 1, threads = 256, n_clusters = 0, cu_count = 0, xcd_count = 0;
   uint32_t per_cu = 1, max_on_a_cu = 0;
   uint32_t cus_held = 0;  // CUs counted for this context in the process registry
+  uint32_t pin_bytes = 0; // dynamic LDS of each worker: the largest x slice it can pin
   uint32_t log_cap = 0;
   uint64_t wall_hz = 100000000ull;
   State state = RUNNING;
@@ -158,7 +159,7 @@ uint32_t worker_code(lk_ctx *c, uint32_t mb) { return LKW_CODE(load_acquire(&c->
 
 // Write one command slot: tagged payload words first, then the doorbell word (release).
 void post_cmd(lk_ctx *c, uint32_t mb, uint64_t seq, uint32_t code, uint64_t n, uint64_t in, uint64_t out,
-              uint64_t aux, uint32_t a, uint32_t b, float alpha, uint32_t member) {
+              uint64_t aux, uint32_t a, uint32_t b, float alpha, uint32_t member, uint32_t dflags = 0) {
   lkw_cmd *s = slot_cmd(c, mb, seq);
   const uint64_t tag = LKW_TAG(seq);
   uint32_t alpha_bits;
@@ -168,7 +169,7 @@ void post_cmd(lk_ctx *c, uint32_t mb, uint64_t seq, uint32_t code, uint64_t n, u
   store_relaxed(&s->w[LKW_W_OUT], tag | (out & LKW_PAYLOAD_MASK));
   store_relaxed(&s->w[LKW_W_AUX], tag | (aux & LKW_PAYLOAD_MASK));
   store_relaxed(&s->w[LKW_W_A], tag | (static_cast<uint64_t>(member & 0xffffu) << 32) | a);
-  store_relaxed(&s->w[LKW_W_B], tag | b);
+  store_relaxed(&s->w[LKW_W_B], tag | (static_cast<uint64_t>(dflags & 0xffffu) << 32) | b);
   store_relaxed(&s->w[LKW_W_ALPHA], tag | alpha_bits);
   store_release(&s->w[LKW_W_DOORBELL], LKW_WORD(seq, code));
 }
@@ -322,6 +323,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   // LDS and the allocation granule), so k fit and k + 1 do not.
   const uint32_t lds_cu = dev.lds_per_cu;
   const uint32_t lds_pad = c->per_cu == 1 ? LKW_LDS_PAD_BYTES : (lds_cu / c->per_cu - 2048u) / 256u * 256u;
+  c->pin_bytes = lds_pad;
   {
     // Until the hardware ids are known every worker may sit on a CU of its own.
     uint32_t in_use = 0;
@@ -395,6 +397,7 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   p.idle_ticks = c->wall_hz / 1000ull * idle_ms;
   p.first_delay = cfg.first_poll_delay;
   p.b2b_ticks = static_cast<uint32_t>(c->wall_hz / 100000ull);  // 10 us
+  p.lds_bytes = lds_pad;
 
   if (!c->wq->start(p, c->n_workers, c->threads, lds_pad, &err))
     return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
@@ -512,7 +515,8 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
   if (d->op >= LK_OP_COUNT) return fail(LK_EINVAL, "unknown op %u", d->op);
   if (d->op == LK_OP_BATCH) return fail(LK_EINVAL, "batches go through lk_submit_batch");
-  if (d->flags || d->reserved) return fail(LK_EINVAL, "flags/reserved must be 0");
+  if (d->reserved) return fail(LK_EINVAL, "reserved must be 0");
+  if (d->flags & ~(LK_DF_PIN_INPUT | LK_DF_PIN_RELOAD)) return fail(LK_EINVAL, "unknown descriptor flags 0x%x", d->flags);
   if (d->n > LK_MAX_N) return fail(LK_EINVAL, "n %llu > LK_MAX_N", static_cast<unsigned long long>(d->n));
   const uint64_t ia = reinterpret_cast<uint64_t>(in), oa = reinterpret_cast<uint64_t>(out);
   if (d->n && op_reads(d->op) && (!in || (ia & 3u))) return fail(LK_EINVAL, "input pointer NULL or not 4-byte aligned");
@@ -534,6 +538,22 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
 
   const uint32_t k = static_cast<uint32_t>(mbs.size());
   const uint32_t esz = 4;
+  if (d->flags && d->n) {
+    if (d->op != LK_OP_SAXPY_F32 && d->op != LK_OP_AXPY_F32)
+      return fail(LK_EINVAL, "pinned input needs SAXPY_F32 or AXPY_F32, not op %u", d->op);
+    if ((ia | oa | (d->op == LK_OP_AXPY_F32 ? d->aux : 0)) & 15u)
+      return fail(LK_EINVAL, "pinned input needs 16-byte aligned in, out and y");
+    for (uint32_t j = 0; j < k; ++j) {
+      uint64_t lo, hi;
+      lkd::slice_bounds(d->n, k, j, &lo, &hi);
+      if ((hi - lo) & 3u)
+        return fail(LK_EINVAL, "pinned input: member %u slice of %llu elements is not a multiple of 4", j,
+                    static_cast<unsigned long long>(hi - lo));
+      if ((hi - lo) * esz > c->pin_bytes)
+        return fail(LK_EINVAL, "pinned input: member %u slice of %llu bytes exceeds the %u-byte LDS buffer", j,
+                    static_cast<unsigned long long>((hi - lo) * esz), c->pin_bytes);
+    }
+  }
   for (uint32_t j = 0; j < k; ++j) {
     uint64_t lo, hi;
     lkd::slice_bounds(d->n, k, j, &lo, &hi);
@@ -543,7 +563,7 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
     if (d->aux && op_has_result(d->op)) saux = d->aux + 8ull * j;
     if (d->aux && d->op == LK_OP_AXPY_F32) saux = d->aux + lo * esz;
     post_cmd(c, mbs[j], t, LKW_TO_WORK + d->op, hi - lo, sin, sout, saux, static_cast<uint32_t>(d->a),
-             static_cast<uint32_t>(d->b), d->alpha, j);
+             static_cast<uint32_t>(d->b), d->alpha, j, d->flags);
   }
   cs.posted = t;
   *ticket = t;
@@ -585,6 +605,7 @@ int lk_batch_plan(const lk_desc *items, const uint64_t *in_addr, const uint64_t 
   for (uint32_t i = 0; i < count; ++i) {
     const lk_desc &d = items[i];
     if (d.op >= LK_OP_COUNT || d.op == LK_OP_BATCH) return fail(LK_EINVAL, "item %u: op %u cannot be tiled", i, d.op);
+    if (d.flags || d.reserved) return fail(LK_EINVAL, "item %u: tiles take no descriptor flags", i);
     if ((in_addr[i] | out_addr[i]) & 3u) return fail(LK_EINVAL, "item %u: pointers must be 4-byte aligned", i);
     need += d.n == 0 ? 1 : (d.n + tile_elems - 1) / tile_elems;
   }
@@ -799,6 +820,7 @@ int lk_get_info(lk_ctx *c, lk_info *info) {
   info->device_span_ms = c->device_span_ms;
   info->workers_per_cu = c->per_cu;
   info->max_workers_on_a_cu = c->max_on_a_cu;
+  info->pin_capacity = c->pin_bytes;
   return LK_OK;
 }
 

@@ -229,6 +229,45 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
   for (uint64_t i = done + tid; i < n; i += nt) st.put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
 }
 
+// out[i] = fma(alpha, x[i], y[i]) with x kept in the workgroup's LDS across items (SAXPY
+// passes y == out).  x, y and out are 16-byte aligned, n is a multiple of 4 and n * 4
+// bytes fit the LDS buffer.  FILL reads x from memory and also stores it to LDS; otherwise
+// x is read from LDS.  Element vector k is handled by the same thread in both forms, so a
+// thread only reads back LDS words it wrote itself and no barrier is needed between items.
+// y and out may be the same buffer: every vector is loaded before it is stored.
+template <class St, bool FILL>
+__device__ __forceinline__ void axpy_pinned(const float *__restrict__ x, float4 *__restrict__ lds, const float *y,
+                                            float *out, uint64_t n, float alpha, uint64_t nt) {
+  constexpr int U = 4;
+  const St st(out, n * 4);
+  const uint64_t tid = threadIdx.x;
+  const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x);
+  const float4 *yv = reinterpret_cast<const float4 *>(y);
+  float4 *ov = reinterpret_cast<float4 *>(out);
+  const uint64_t nv = n >> 2;
+  uint64_t k = tid;
+  for (; k + (U - 1) * nt < nv; k += U * nt) {
+    float4 rx[U], ry[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rx[u] = FILL ? xv[k + u * nt] : lds[k + u * nt];
+      ry[u] = yv[k + u * nt];
+    }
+    if (FILL) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) lds[k + u * nt] = rx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) st.put(ov + k + u * nt, fma4(alpha, rx[u], ry[u]));
+  }
+  for (; k < nv; k += nt) {
+    const float4 rx = FILL ? xv[k] : lds[k];
+    const float4 ry = yv[k];
+    if (FILL) lds[k] = rx;
+    st.put(ov + k, fma4(alpha, rx, ry));
+  }
+}
+
 // out[i] = fma(alpha, x[i], y[i]): SAXPY with y read from its own buffer.
 template <class St>
 __device__ __forceinline__ void axpy(const float *__restrict__ x, const float *__restrict__ y, float *__restrict__ out,

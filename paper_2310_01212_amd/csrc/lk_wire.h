@@ -56,7 +56,7 @@ enum {
   LKW_W_AUX = 4,      /* device address: this member's partial-result entry (AFFINE, SUM),
                          the slice's y (AXPY), the tile counter (BATCH), or 0 */
   LKW_W_A = 5,        /* uint32 a | (member index << 32) */
-  LKW_W_B = 6,        /* uint32 b */
+  LKW_W_B = 6,        /* uint32 b | (descriptor flags << 32) */
   LKW_W_ALPHA = 7,    /* float alpha bits */
   LKW_CMD_WORDS = 8
 };
@@ -120,7 +120,13 @@ typedef struct lkw_params {
   uint64_t idle_ticks;   /* watchdog, device wall-clock ticks */
   int32_t first_delay;   /* s_sleep(1) units before the first poll after a completion; -1 = adaptive */
   uint32_t b2b_ticks;    /* a command found this soon after a completion counts as back-to-back */
+  uint32_t lds_bytes;    /* dynamic LDS of each worker (the pinned-input buffer) */
+  uint32_t pad;
 } lkw_params;
+
+/* Descriptor flags, carried in bits 32..47 of LKW_W_B (same values as LK_DF_*). */
+#define LKW_DF_PIN_INPUT 0x1u
+#define LKW_DF_PIN_RELOAD 0x2u
 
 #define LKW_K_REPORT_WORKING 0x1u
 #define LKW_K_NO_ACQUIRE 0x2u

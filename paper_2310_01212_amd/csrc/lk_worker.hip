@@ -89,12 +89,12 @@ __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uin
 
 // ----------------------------------------------------------------------------- worker
 extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
-  extern __shared__ uint64_t lds_reserve[];  // only holds the CU's LDS share
+  // Dynamic LDS: holds the CU's LDS share and serves as the pinned-input buffer.
+  extern __shared__ float4 lds_pin[];
   __shared__ uint64_t s_w[LKW_CMD_WORDS];
   __shared__ uint64_t s_batch_next;
   __shared__ uint32_t s_mb, s_go;
   __shared__ int64_t s_red[lkops::kMaxWaves];
-  (void)lds_reserve;
   const uint32_t tid = threadIdx.x;
 
   // Boot: claim a mailbox, record the physical placement, announce INIT (Table 1).
@@ -127,6 +127,9 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   // command missed by that first read lengthens it by 2 units, one it finds shortens it
   // by 1, so the first read tends to arrive just after the host has posted.
   uint32_t pre = 8;
+  // Input held in lds_pin: device address and element count of the last pinned x
+  // (pin_n == 0: nothing pinned).
+  uint64_t pin_addr = 0, pin_n = 0;
 
   for (;;) {
     const uint64_t want = seq + 1;
@@ -202,6 +205,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     s.in2 = reinterpret_cast<const void *>(uniform_u64(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK));
     s.a = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_A]));
     s.b = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_B]));
+    const uint32_t dflags = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_B] >> 32) & 0xffffu);
     s.alpha = __uint_as_float(uniform_u32(static_cast<uint32_t>(s_w[LKW_W_ALPHA])));
     if (code == LKW_TO_NOP) {
       reply = LKW_FROM_NOP;
@@ -217,7 +221,25 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
                           static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, &s_batch_next,
                           p.threads);
     } else if (s.op != 0) {
-      partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
+      // Pinned input (AXPY forms only): x is served from LDS when this worker's last
+      // pinned copy has the same address and length, else loaded and kept.  The shape
+      // check repeats the host's so LDS is never addressed past the buffer.
+      const uint64_t ia = reinterpret_cast<uint64_t>(s.in);
+      const float *y = s.op == lkd::kOpAxpy ? static_cast<const float *>(s.in2) : static_cast<const float *>(s.out);
+      const bool pin = (dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == lkd::kOpSaxpy || s.op == lkd::kOpAxpy) &&
+                       s.n > 0 && (s.n & 3u) == 0 && s.n * 4 <= p.lds_bytes &&
+                       ((ia | reinterpret_cast<uint64_t>(s.out) | reinterpret_cast<uint64_t>(y)) & 15u) == 0;
+      if (!pin) {
+        partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
+      } else if (!(dflags & LKW_DF_PIN_RELOAD) && ia == pin_addr && s.n == pin_n) {
+        lkops::axpy_pinned<lkops::SystemStore, false>(static_cast<const float *>(s.in), lds_pin, y,
+                                                      static_cast<float *>(s.out), s.n, s.alpha, p.threads);
+      } else {
+        lkops::axpy_pinned<lkops::SystemStore, true>(static_cast<const float *>(s.in), lds_pin, y,
+                                                     static_cast<float *>(s.out), s.n, s.alpha, p.threads);
+        pin_addr = ia;
+        pin_n = s.n;
+      }
     }
 
     // ---- complete.  Thread 0 writes the optional per-member partial with a

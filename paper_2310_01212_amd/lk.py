@@ -18,6 +18,7 @@ OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, O
 CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
 F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
 POLL_DELAY_ADAPTIVE = -1
+DF_PIN_INPUT, DF_PIN_RELOAD = 1, 2
 COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
 
 # Table 1 values of the command codes recorded in the device log.
@@ -71,7 +72,8 @@ class Info(ctypes.Structure):
                 ("wall_clock_hz", ctypes.c_uint64), ("init_ms", ctypes.c_double),
                 ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("device_span_ms", ctypes.c_double), ("workers_per_cu", ctypes.c_uint32),
-                ("max_workers_on_a_cu", ctypes.c_uint32)]
+                ("max_workers_on_a_cu", ctypes.c_uint32), ("pin_capacity", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class LogEntry(ctypes.Structure):
@@ -95,9 +97,10 @@ REQUEST_DTYPE = np.dtype([("arrival_us", "<f8"), ("op", "<u4"), ("a", "<i4"), ("
 OUTCOME_DTYPE = np.dtype([("result", "<i8"), ("out", "<u8"), ("admit_us", "<f8"), ("done_us", "<f8"),
                           ("status", "<i4"), ("tiles", "<u4")])
 
-# numpy view of lkb_item (48 bytes)
+# numpy view of lkb_item (56 bytes)
 ITEM_DTYPE = np.dtype([("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4"),
-                       ("n", "<u8"), ("inp", "<u8"), ("out", "<u8"), ("in2", "<u8")])
+                       ("n", "<u8"), ("inp", "<u8"), ("out", "<u8"), ("in2", "<u8"),
+                       ("flags", "<u4"), ("reserved", "<u4")])
 COMPLETION_DTYPE = np.dtype([("result", "<i8"), ("t_pick_min", "<u8"), ("t_pick_max", "<u8"),
                              ("t_done_min", "<u8"), ("t_done_max", "<u8")])
 TILE_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("in2", "<u8"), ("n", "<u4"), ("op", "<u4"), ("a", "<i4"),
@@ -267,14 +270,15 @@ class Context:
         self._closed = False
 
     # -- phases ---------------------------------------------------------------------------
-    def submit(self, cluster, op, x=None, y=None, a=0, b=0, alpha=0.0, n=None, aux=None):
-        """Trigger: post one item; returns its ticket.  Raises LKError(EAGAIN) if full."""
+    def submit(self, cluster, op, x=None, y=None, a=0, b=0, alpha=0.0, n=None, aux=None, flags=0):
+        """Trigger: post one item; returns its ticket.  Raises LKError(EAGAIN) if full.
+        flags: DF_PIN_INPUT / DF_PIN_RELOAD (keep x in the members' LDS across items)."""
         _check_tensor(x, op, "x")
         _check_tensor(y, op, "y")
         if n is None:
             ref = x if x is not None else y
             n = 0 if ref is None else (ref.numel() if not isinstance(ref, int) else 0)
-        d = Desc(op, 0, n, _i32(a), _i32(b), float(np.float32(alpha)), 0, _ptr(aux) or 0, 0)
+        d = Desc(op, flags, n, _i32(a), _i32(b), float(np.float32(alpha)), 0, _ptr(aux) or 0, 0)
         t = ctypes.c_uint64()
         rc = lib().lk_submit(self._h, cluster, ctypes.byref(d), _ptr(x), _ptr(y), ctypes.byref(t))
         _check(rc, "lk_submit")
@@ -530,15 +534,17 @@ def copy_bandwidth(src, dst, nbytes, grid, reps=10, device=0):
     return ms.value, gbps.value
 
 
-def make_items(op, n, inp, out, a=0, b=0, alpha=0.0, in2=0):
+def make_items(op, n, inp, out, a=0, b=0, alpha=0.0, in2=0, flags=0):
     """Build an ITEM_DTYPE array from per-item columns (scalars broadcast).  in2 is the y
-    address of AXPY_F32 items."""
+    address of AXPY_F32 items; flags are DF_* descriptor flags."""
     cols = np.broadcast_arrays(np.asarray(op), np.asarray(n), np.asarray(inp, dtype=np.uint64),
                                np.asarray(out, dtype=np.uint64), np.asarray(a), np.asarray(b),
-                               np.asarray(alpha, dtype=np.float32), np.asarray(in2, dtype=np.uint64))
+                               np.asarray(alpha, dtype=np.float32), np.asarray(in2, dtype=np.uint64),
+                               np.asarray(flags, dtype=np.uint32))
     shape = cols[0].shape
     it = np.zeros(shape, ITEM_DTYPE)
     it["op"], it["n"], it["inp"], it["out"], it["in2"] = cols[0], cols[1], cols[2], cols[3], cols[7]
+    it["flags"] = cols[8]
     it["a"] = (np.asarray(cols[4]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
     it["b"] = (np.asarray(cols[5]).astype(np.int64) & 0xffffffff).astype(np.uint32).view(np.int32)
     it["alpha"] = cols[6]

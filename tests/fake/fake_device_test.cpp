@@ -173,6 +173,87 @@ static void error_paths() {
   printf("OK %s\n", g_case);
 }
 
+// Pinned input: a flagged item whose x matches the worker's pinned copy computes with that
+// copy (so a change to x in memory goes unseen until PIN_RELOAD), unflagged items read
+// memory and leave the copy in place, and lk_submit rejects shapes the buffer cannot take.
+static void pinned_input() {
+  g_case = "pinned_input";
+  lk_ctx *c = open_ctx(2, 1, LK_CLUSTERS_PER_WORKER);
+  lk_info info{};
+  CHECK(lk_get_info(c, &info) == LK_OK && info.pin_capacity >= 64 * 1024);
+  const uint64_t n = 4096;
+  alignas(64) static float x[8192], x2[8192], y[8192], yr[8192];
+  std::mt19937 rng(11);
+  std::uniform_real_distribution<float> u(-1.f, 1.f);
+  for (uint64_t i = 0; i < 8192; ++i) x[i] = u(rng), x2[i] = u(rng), y[i] = u(rng);
+  memcpy(yr, y, sizeof y);
+  auto run = [&](lk_desc d, const float *xp) {
+    uint64_t t;
+    CHECK(lk_submit(c, 0, &d, xp, y, &t) == LK_OK);
+    CHECK(lk_wait(c, 0, t, 5000000000ll, nullptr) == LK_OK);
+  };
+  auto ref = [&](float alpha, const float *xs) {
+    for (uint64_t i = 0; i < n; ++i) yr[i] = std::fmaf(alpha, xs[i], yr[i]);
+  };
+  lk_desc d = desc(LK_OP_SAXPY_F32, n, 0, 0, 0.5f);
+  d.flags = LK_DF_PIN_INPUT;
+  run(d, x);  // first flagged item: loads and pins x
+  ref(0.5f, x);
+  float old[4096];
+  memcpy(old, x, sizeof old);
+  for (uint64_t i = 0; i < n; ++i) x[i] += 1.f;  // broken promise: the pinned copy is used
+  run(d, x);
+  ref(0.5f, old);
+  CHECK(memcmp(y, yr, n * 4) == 0);
+  lk_desc plain = desc(LK_OP_SAXPY_F32, n, 0, 0, -1.25f);
+  run(plain, x);  // unflagged: memory
+  ref(-1.25f, x);
+  run(d, x);  // the copy is still the old x
+  ref(0.5f, old);
+  CHECK(memcmp(y, yr, n * 4) == 0);
+  lk_desc rl = d;
+  rl.flags = LK_DF_PIN_RELOAD;
+  run(rl, x);
+  ref(0.5f, x);
+  run(d, x);
+  ref(0.5f, x);
+  run(d, x2);  // another address: loads and replaces
+  ref(0.5f, x2);
+  CHECK(memcmp(y, yr, n * 4) == 0);
+  // AXPY with a pinned x
+  alignas(64) static float yy[4096], out[4096];
+  for (uint64_t i = 0; i < n; ++i) yy[i] = u(rng);
+  lk_desc ax = desc(LK_OP_AXPY_F32, n, 0, 0, 3.f, reinterpret_cast<uint64_t>(yy));
+  ax.flags = LK_DF_PIN_INPUT;
+  uint64_t t;
+  CHECK(lk_submit(c, 1, &ax, x2, out, &t) == LK_OK && lk_wait(c, 1, t, 5000000000ll, nullptr) == LK_OK);
+  for (uint64_t i = 0; i < n; ++i) CHECK(out[i] == std::fmaf(3.f, x2[i], yy[i]));
+  // shapes the pinned path refuses
+  lk_desc e = d;
+  e.flags = 0x4;
+  CHECK(lk_submit(c, 0, &e, x, y, &t) == LK_EINVAL);
+  e = desc(LK_OP_AFFINE_SUM_I32, 64);
+  e.flags = LK_DF_PIN_INPUT;
+  CHECK(lk_submit(c, 0, &e, x, y, &t) == LK_EINVAL);
+  e = d;
+  CHECK(lk_submit(c, 0, &e, x + 1, y + 1, &t) == LK_EINVAL);  // 4- but not 16-byte aligned
+  e.n = n - 2;
+  CHECK(lk_submit(c, 0, &e, x, y, &t) == LK_EINVAL);  // not a multiple of 4
+  e.n = info.pin_capacity / 4 + 4;
+  std::vector<float> big(e.n + 64);
+  float *bp = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(big.data()) + 15) & ~uintptr_t(15));
+  CHECK(lk_submit(c, 0, &e, bp, bp, &t) == LK_EINVAL);  // larger than the LDS buffer
+  e.n = 0;
+  CHECK(lk_submit(c, 0, &e, nullptr, nullptr, &t) == LK_OK && lk_wait(c, 0, t, 5000000000ll, nullptr) == LK_OK);
+  uint64_t in_a = reinterpret_cast<uint64_t>(x), out_a = reinterpret_cast<uint64_t>(y);
+  lk_tile tiles[4];
+  uint32_t item_of[4], nt = 0;
+  CHECK(lk_batch_plan(&d, &in_a, &out_a, 1, 4096, tiles, item_of, 4, &nt) == LK_EINVAL);
+  CHECK(lk_dispose(c) == LK_OK);
+  lk_free(c);
+  printf("OK %s\n", g_case);
+}
+
 // One item sliced over a cluster of every worker: exact sum, output and per-member partials.
 static void cluster_split() {
   g_case = "cluster_split";
@@ -393,6 +474,7 @@ int main() {
   single_worker_1000();
   concurrent_clusters();
   error_paths();
+  pinned_input();
   cluster_split();
   batch_tiles();
   serving();

@@ -115,6 +115,9 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
   lkw_cmd *ring = p.cmd + m * stride;
   lkw_status *sring = p.status + m * stride;
   uint64_t seq = 0;
+  // Model of the pinned input: one copy of x per worker, up to p.lds_bytes.
+  std::vector<float> pin;
+  uint64_t pin_addr = 0, pin_n = 0;
   for (;;) {
     const uint64_t want = seq + 1;
     const uint32_t slot = static_cast<uint32_t>(want % p.depth);
@@ -184,6 +187,17 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
         ++partial;
       }
     } else if (reply != LKW_FROM_EXITED) {
+      const uint32_t dflags = static_cast<uint32_t>(w[LKW_W_B] >> 32) & 0xffffu;
+      const uint64_t y = s.op == 7 ? s.in2 : s.out;
+      if ((dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == 3 || s.op == 7) && s.n > 0 &&
+          s.n % 4 == 0 && s.n * 4 <= p.lds_bytes && ((s.in | s.out | y) & 15u) == 0) {
+        if ((dflags & LKW_DF_PIN_RELOAD) || s.in != pin_addr || s.n != pin_n) {
+          pin.assign(reinterpret_cast<const float *>(s.in), reinterpret_cast<const float *>(s.in) + s.n);
+          pin_addr = s.in;
+          pin_n = s.n;
+        }
+        s.in = reinterpret_cast<uint64_t>(pin.data());
+      }
       partial = run_slice(s);
       if (s.in2 && (s.op == 1 || s.op == 2)) __atomic_store_n(reinterpret_cast<int64_t *>(s.in2), partial, __ATOMIC_RELAXED);
     }

@@ -326,6 +326,123 @@ def test_all_cus_full_size_sampled_elements():
             assert Y[w, i].view(np.uint32) == np.float32(want).view(np.uint32), (w, i)
 
 
+# ------------------------------------------------------------------ pinned input (x in LDS)
+def _pinned_sequence(ctx, cluster, n, seed):
+    """Flagged, changed-x, unflagged, reload and new-address items on one cluster; returns
+    (device y, expected y).  After x changes in memory, PIN_INPUT items must still see the
+    pinned copy (the LDS copy is really what they read) until PIN_RELOAD replaces it."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.standard_normal(n).astype(np.float32)
+    x0[:4] = [np.inf, -0.0, 1e-40, 3e38]
+    x2 = rng.standard_normal(n).astype(np.float32)
+    y0 = rng.standard_normal(n).astype(np.float32)
+    al = rng.uniform(-2, 2, 8).astype(np.float32)
+    dx, dx2, dy = to_dev(x0), to_dev(x2), to_dev(y0)
+    P, R = lk.DF_PIN_INPUT, lk.DF_PIN_RELOAD
+
+    def run(xd, alpha, flags):
+        t = ctx.submit(cluster, lk.OP_SAXPY_F32, x=addr(xd), y=addr(dy), alpha=alpha, n=n, flags=flags)
+        ctx.wait(cluster, t)
+
+    run(dx, al[0], P)                   # pins x0
+    dx.add_(1.0)                        # x changes in memory: x1
+    torch.cuda.synchronize()
+    x1 = x0 + np.float32(1.0)
+    run(dx, al[1], P)                   # pinned copy: x0
+    run(dx, al[2], 0)                   # memory: x1
+    run(dx, al[3], P)                   # still x0
+    run(dx, al[4], R)                   # reload: x1
+    run(dx, al[5], P)                   # x1
+    run(dx2, al[6], P)                  # another address: x2
+    run(dx, al[7], P)                   # back: x1 reloaded
+    want = y0.copy()
+    oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=xs, out=want, alpha=a)
+                     for xs, a in zip([x0, x0, x1, x0, x1, x1, x2, x1], al)])
+    torch.cuda.synchronize()
+    return dy.cpu().numpy(), want
+
+
+@pytest.mark.parametrize("n", [4, 260, 4096, 16384, 16388, 24576])
+def test_pinned_input_reads_the_lds_copy_until_reload(n):
+    with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
+        cap = ctx.info()["pin_capacity"]
+        assert cap == 96 * 1024 and n * 4 <= cap
+        say(f"pinned input: one worker, n={n}")
+        got, want = _pinned_sequence(ctx, 0, n, seed=n)
+    assert same_f32(got, want)
+
+
+def test_pinned_input_refuses_shapes_the_buffer_cannot_take():
+    with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
+        cap = ctx.info()["pin_capacity"]
+        big = torch.zeros(cap // 4 + 64, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        say("pinned input: refused shapes")
+        for kw in (dict(n=cap // 4 + 4), dict(n=1022), dict(n=64, x=addr(big, 1), y=addr(big, 1)),
+                   dict(n=64, flags=4)):
+            a = dict(x=addr(big), y=addr(big), flags=lk.DF_PIN_INPUT)
+            a.update(kw)
+            with pytest.raises(lk.LKError) as e:
+                ctx.submit(0, lk.OP_SAXPY_F32, alpha=1.0, **a)
+            assert e.value.code == lk.EINVAL
+        with pytest.raises(lk.LKError):
+            ctx.submit(0, lk.OP_COPY_F32, x=addr(big), y=addr(big), n=64, flags=lk.DF_PIN_INPUT)
+        t = ctx.submit(0, lk.OP_SAXPY_F32, x=addr(big), y=addr(big), alpha=1.0, n=cap // 4, flags=lk.DF_PIN_INPUT)
+        ctx.wait(0, t)  # the largest slice the buffer holds is accepted
+
+
+def test_pinned_input_on_xcd_clusters_pins_each_members_slice():
+    """An item sliced over the 32 members of an XCD: every member pins its own slice."""
+    n = 131084  # slices of 4352 elements, a ragged 524-element one, and an empty one
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=20000) as ctx:
+        say(f"pinned input: XCD clusters, n={n}")
+        res = [_pinned_sequence(ctx, c, n, seed=100 + c) for c in (0, ctx.info()["n_clusters"] - 1)]
+    for got, want in res:
+        assert same_f32(got, want)
+
+
+@pytest.mark.parametrize("per_cu", [1, 2])
+def test_pinned_input_all_cus_chains_bit_exact(per_cu):
+    """The all-CU SAXPY shape (n = 16,384) with x pinned on every worker, k workers per
+    CU each with its own copy: every lane's chain equals the oracle's."""
+    items, n = 200, workloads.ALLCU_N
+    with lk.Context(n_workers=0, workers_per_cu=per_cu, threads=1024 // per_cu, idle_timeout_ms=20000) as ctx:
+        lanes = ctx.info()["n_workers"]
+        say(f"pinned input all CUs: {per_cu} per CU, {lanes} lanes x {items} items of {n}")
+        X, Y0, A, span = _allcu_setup(ctx, items, lambda w: n)
+        assert span % 4 == 0
+        x, y = to_dev(X), to_dev(Y0)
+        torch.cuda.current_stream().synchronize()
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        it = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * span * 4, addr(y) + li * span * 4, alpha=A,
+                           flags=lk.DF_PIN_INPUT)
+        ctx.run_lanes(np.arange(lanes), it, in_flight=1, threads=8)
+    Y = y.cpu().numpy()
+    for w in range(lanes):
+        xr, yr = X[w, :n].copy(), Y0[w, :n].copy()
+        oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, xr, yr, A[w]))
+        assert np.array_equal(Y[w, :n].view(np.uint32), yr.view(np.uint32)), w
+
+
+def test_pinned_input_axpy_out_of_place():
+    rng = np.random.default_rng(23)
+    n = 8192
+    x = rng.standard_normal(n).astype(np.float32)
+    yv = rng.standard_normal(n).astype(np.float32)
+    dx, dy = to_dev(x), to_dev(yv)
+    outs = [sentinel_f32((n,)) for _ in range(3)]
+    torch.cuda.synchronize()
+    al = np.float32([0.75, -3.0, 1.5])
+    say("pinned input: out-of-place AXPY")
+    with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
+        for o, a in zip(outs, al):
+            t = ctx.submit(0, lk.OP_AXPY_F32, x=addr(dx), y=addr(o), alpha=a, n=n, aux=addr(dy),
+                           flags=lk.DF_PIN_INPUT)
+            ctx.wait(0, t)
+    for o, a in zip(outs, al):
+        assert same_f32(o.cpu().numpy(), oracle.axpy_f32(a, x.copy(), yv.copy()))
+
+
 # ------------------------------------------------------------------ clusters = XCDs
 def test_clusters_per_xcd_split_items_and_placement():
     rng = np.random.default_rng(3)
