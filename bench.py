@@ -60,7 +60,8 @@ def int_sum_check(x, a=None, b=None):
     return int(y.astype(np.int64).sum())
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lk_worker_allcu_saxpy_traffic.md")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md")]
 WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h"]
 
 
@@ -73,23 +74,24 @@ def worker_source_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_per_item(n, threads_per_worker):
-    """HBM bytes per item of the worker kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration);
-    None when the summary is missing, was taken for another item size, or the worker's
+def traffic_per_item(n, threads_per_worker, pin_input=False):
+    """HBM bytes per item of the worker kernel from a committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration); None when
+    no summary was taken for this item size, workgroup size and pinning, or the worker's
     sources changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    text = open(TRAFFIC_FILE).read()
     import re
-    m = re.search(r"```json\n(.*?)\n```", text, re.S)
-    if not m:
-        return None
-    d = json.loads(m.group(1))
-    if (d.get("worker_source_digest") != worker_source_digest() or d.get("n") != n or
-            d.get("threads_per_worker", 256) != threads_per_worker):
-        return None
-    return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        d = json.loads(m.group(1))
+        if (d.get("worker_source_digest") == worker_source_digest() and d.get("n") == n and
+                d.get("threads_per_worker", 256) == threads_per_worker and
+                bool(d.get("pin_input", False)) == bool(pin_input)):
+            return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(path, ROOT)}
+    return None
 
 
 def parse():
@@ -110,6 +112,9 @@ def parse():
                          "aggregate at 16 (0/1 = skip)")
     ap.add_argument("--no-pinned", dest="pinned", action="store_false",
                     help="skip the pinned-input (x kept in LDS) variants")
+    ap.add_argument("--pin-input", action="store_true",
+                    help="time the all-CU workload itself with x pinned in each worker's LDS "
+                         "(its roofline then counts the 8n HBM bytes per item of y alone)")
     ap.add_argument("--variant-per-cu", type=int, default=2,
                     help="workers per CU of the variant reported beside the one-per-CU headline (0/1 = skip)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
@@ -473,13 +478,16 @@ def bench_allcu(args):
     y_addr = y_d.data_ptr() + li * n * 4
 
     # every step's descriptors are built before any timed region
-    steps_items = [lk.make_items(lk.OP_SAXPY_F32, n, x_addr, y_addr, alpha=A[:, s * per:(s + 1) * per])
+    steps_items = [lk.make_items(lk.OP_SAXPY_F32, n, x_addr, y_addr, alpha=A[:, s * per:(s + 1) * per],
+                                 flags=lk.DF_PIN_INPUT if args.pin_input else 0)
                    for s in range(args.warmup + args.steps)]
 
     def step_items(s):
         return steps_items[s]
 
     bytes_per_item = 12 * n  # SAXPY: 8n read + 4n write
+    # with x pinned, memory carries y alone (4n read + 4n written); x is read once per worker
+    hbm_bytes_per_item = 8 * n if args.pin_input else bytes_per_item
 
     # ---------------- persistent path
     log("persistent path: boot")
@@ -509,7 +517,7 @@ def bench_allcu(args):
     if kernel_ms <= 0:
         kernel_ms, kernel_clock = info["kernel_ms"], "dispatch timestamps"
     session_items = lanes * per * (args.warmup + args.steps)
-    achieved_gbps = session_items * bytes_per_item / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
+    achieved_gbps = session_items * hbm_bytes_per_item / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
     log(f"persistent: {items_per_s:,.0f} items/s, p50 {pct(lat_all, .5):.2f} us, kernel {kernel_ms:.1f} ms")
 
     result = {
@@ -525,9 +533,10 @@ def bench_allcu(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded: x, y ~ N(0,1), alpha ~ U(-2,2) per mailbox)",
-        "config": {"workload": "all-CU SAXPY: one worker per CU, each mailbox fed items back-to-back",
+        "config": {"workload": "all-CU SAXPY: one worker per CU, each mailbox fed items back-to-back" +
+                               (", x pinned in each worker's LDS" if args.pin_input else ""),
                    "workers": lanes, "items_per_mailbox": per * args.steps, "n": n,
-                   "item_bytes": bytes_per_item, "queue_depth": args.depth,
+                   "item_bytes": bytes_per_item, "queue_depth": args.depth, "pin_input": args.pin_input,
                    "host_threads": args.threads, "threads_per_worker": args.threads_per_worker,
                    "poll_sleep": args.poll_sleep},
         "latency_us": lat_summary(lat_all),
@@ -540,9 +549,9 @@ def bench_allcu(args):
                           "unit": "GB/s", "frac": round(achieved_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
                           "kernel": "lk_worker", "kernel_ms": round(kernel_ms, 3), "kernel_clock": kernel_clock,
                           "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
-                          "items_per_launch": session_items, "algorithmic_bytes_per_item": bytes_per_item,
-                          "algorithmic_bytes": session_items * bytes_per_item}
-    tr = traffic_per_item(n, args.threads_per_worker)
+                          "items_per_launch": session_items, "algorithmic_bytes_per_item": hbm_bytes_per_item,
+                          "algorithmic_bytes": session_items * hbm_bytes_per_item}
+    tr = traffic_per_item(n, args.threads_per_worker, args.pin_input)
     if tr is not None:
         result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
         result["roofline"]["traffic_source"] = tr["source"]
@@ -653,9 +662,10 @@ def bench_allcu(args):
 
         # pinned-input variants: x kept in each worker's LDS across items (descriptor flag
         # DF_PIN_INPUT).  "hot" is the headline workload with the flag; "y_cold" keeps x per
-        # mailbox and rotates y through P buffers (512 MiB at P = 32, past the Infinity
-        # Cache), run without and with the flag, so HBM carries 12n or 8n bytes per item
-        if args.pinned:
+        # mailbox and rotates y through P buffers (512 MiB at P = 32, past the Infinity Cache),
+        # run without and with the flag.  Bandwidths are algorithmic (12n bytes per item),
+        # as for the headline
+        if args.pinned and not args.pin_input:
             def timed(ctx_kw, items_of_step, nsteps):
                 with lk.Context(n_workers=lanes, threads=args.threads_per_worker, poll_sleep=args.poll_sleep,
                                 idle_timeout_ms=60000, **ctx_kw) as cx:
@@ -696,12 +706,11 @@ def bench_allcu(args):
             for fl, key in ((0, "y_cold_unpinned"), (lk.DF_PIN_INPUT, "y_cold_pinned")):
                 yl, yt, yinf = timed({}, lambda s, fl=fl: ycit[fl][s], psteps)
                 y_items = lanes * per * psteps
-                hbm = (8 if fl else 12) * n
-                gbps = y_items * hbm / (yinf["device_span_ms"] * 1e-3) / 1e9
+                gbps = y_items * bytes_per_item / (yinf["device_span_ms"] * 1e-3) / 1e9
                 pv[key] = {"y_buffers_per_mailbox": P, "y_footprint_bytes": lanes * P * n * 4,
                            "items_per_s": round(yl.size / yt, 1), "latency_us": lat_summary(yl),
                            "kernel_ms": round(yinf["device_span_ms"], 3), "items_per_launch": y_items,
-                           "hbm_bytes_per_item": hbm, "achieved_gbps": round(gbps, 1),
+                           "algorithmic_bytes_per_item": bytes_per_item, "achieved_gbps": round(gbps, 1),
                            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
                 log(f"{key}: {yl.size / yt:,.0f} items/s, {gbps:,.0f} GB/s")
             del ycold

@@ -470,7 +470,7 @@ def batch_plan(items, tile_elems):
     descs = (Desc * max(count, 1))()
     for i in range(count):
         op = int(items["op"][i])
-        descs[i] = Desc(op, 0, int(items["n"][i]), int(items["a"][i]), int(items["b"][i]),
+        descs[i] = Desc(op, int(items["flags"][i]), int(items["n"][i]), int(items["a"][i]), int(items["b"][i]),
                         float(items["alpha"][i]), 0, int(items["in2"][i]) if op == OP_AXPY_F32 else 0, 0)
     ins = np.ascontiguousarray(items["inp"], dtype=np.uint64)
     outs = np.ascontiguousarray(items["out"], dtype=np.uint64)

@@ -197,6 +197,23 @@ def test_bench_quotes_the_paper_tables_as_printed():
     assert seen == len(golden) == 24
 
 
+def test_committed_traffic_profiles_match_the_worker_sources():
+    """The HBM-traffic summaries bench.py quotes were taken with the worker as it is now
+    (plain and pinned-input all-CU workloads, n = 16,384, 1024 threads per worker)."""
+    import bench
+    for pin in (False, True):
+        tr = bench.traffic_per_item(16384, 1024, pin)
+        assert tr is not None, f"traffic summary for pin_input={pin} is stale or missing"
+        assert 8 * 16384 <= tr["bytes_per_item"] <= 12 * 16384
+
+
+def test_make_items_carries_descriptor_flags():
+    it = lk.make_items(lk.OP_SAXPY_F32, 64, [0x1000, 0x2000], 0x3000, alpha=1.0, flags=[lk.DF_PIN_INPUT, 0])
+    assert it["flags"].tolist() == [lk.DF_PIN_INPUT, 0] and it["reserved"].tolist() == [0, 0]
+    with pytest.raises(lk.LKError):
+        lk.batch_plan(it, 4096)  # tiles take no descriptor flags
+
+
 def test_batch_plan_cuts_items_into_tiles():
     items = lk.make_items(np.array([lk.OP_AFFINE_SUM_I32, lk.OP_SAXPY_F32, lk.OP_COPY_F32, lk.OP_NOP]),
                           np.array([1000, 256, 513, 0], np.uint64), np.array([0x1000, 0x8000, 0x20000, 0]),
