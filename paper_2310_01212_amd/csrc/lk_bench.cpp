@@ -45,6 +45,30 @@ int bfail(int code, const char *fmt, ...) {
 
 inline uint64_t load_acquire(const uint64_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
 
+// CPUs the process may run on, in ascending order (its affinity mask at first use).
+const std::vector<int> &allowed_cpus() {
+  static const std::vector<int> cpus = [] {
+    std::vector<int> v;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof set, &set) == 0)
+      for (int i = 0; i < CPU_SETSIZE; ++i)
+        if (CPU_ISSET(i, &set)) v.push_back(i);
+    return v;
+  }();
+  return cpus;
+}
+
+// Pin the calling thread to the i-th allowed CPU.  Host threads that poll mailboxes then
+// keep their cache lines and are not migrated mid-run.
+void pin_to_allowed_cpu(size_t i) {
+  const std::vector<int> &cpus = allowed_cpus();
+  if (i >= cpus.size()) return;
+  cpu_set_t one;
+  CPU_ZERO(&one);
+  CPU_SET(cpus[i], &one);
+  (void)pthread_setaffinity_np(pthread_self(), sizeof one, &one);
+}
+
 lk_desc to_desc(const lkb_item &it) {
   lk_desc d{};
   d.op = it.op;
@@ -180,8 +204,11 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
   const auto start = clk::now();
   // Each host thread owns a fixed set of lanes (one producer per mailbox).  Per lane and
   // per sweep: first collect every finished ticket, then refill up to in_flight, so a
-  // lane is re-armed as soon as its completion is seen.
+  // lane is re-armed as soon as its completion is seen.  Threads are pinned to distinct
+  // allowed CPUs when there are enough of them (the caller's thread is left one).
+  const bool pin = n_threads < allowed_cpus().size();
   auto worker = [&](uint32_t tix) {
+    if (pin) pin_to_allowed_cpu(tix);
     struct Lane {
       uint32_t id, cluster;
       uint64_t next = 0, done = 0;
@@ -266,16 +293,11 @@ int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64
   std::atomic<bool> stop{false};
   std::atomic<int> bg_error{0};
   std::vector<uint64_t> counts(n_bg, 0);
-  const unsigned ncpu = std::thread::hardware_concurrency();
+  const size_t ncpu = allowed_cpus().size();
   // Background streams: one host thread per interfering cluster re-posts its item as soon
   // as the previous one completes.
   auto bg_worker = [&](uint32_t i) {
-    if (ncpu > n_bg + 1) {  // keep the critical thread's core (the last one) free
-      cpu_set_t set;
-      CPU_ZERO(&set);
-      CPU_SET(i % (ncpu - 1), &set);
-      pthread_setaffinity_np(pthread_self(), sizeof set, &set);
-    }
+    if (ncpu > n_bg + 1) pin_to_allowed_cpu(i);  // the last allowed CPU stays the critical thread's
     const lk_desc d = to_desc(bg[i]);
     while (!stop.load(std::memory_order_relaxed)) {
       uint64_t t;
@@ -292,16 +314,11 @@ int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64
   std::vector<std::thread> th;
   for (uint32_t i = 0; i < n_bg; ++i) th.emplace_back(bg_worker, i);
 
-  // Critical stream on the calling thread, pinned to the last core for the run: release
-  // k happens at t0 + k * period (busy-wait), then submit and wait.
+  // Critical stream on the calling thread, pinned to the last allowed CPU for the run:
+  // release k happens at t0 + k * period (busy-wait), then submit and wait.
   cpu_set_t old_set;
   const bool pinned = ncpu > n_bg + 1 && pthread_getaffinity_np(pthread_self(), sizeof old_set, &old_set) == 0;
-  if (pinned) {
-    cpu_set_t set;
-    CPU_ZERO(&set);
-    CPU_SET(ncpu - 1, &set);
-    pthread_setaffinity_np(pthread_self(), sizeof set, &set);
-  }
+  if (pinned) pin_to_allowed_cpu(ncpu - 1);
   int rc = LK_OK;
   const auto start = clk::now();
   const auto t0 = start + std::chrono::milliseconds(20);  // let the interference ramp up
@@ -595,7 +612,9 @@ int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64
   std::atomic<int> error{rc};
   std::atomic<bool> stop{rc != LK_OK};
   const auto start = clk::now();
+  const bool pin = n_threads < allowed_cpus().size();  // as in lkb_lanes
   auto worker = [&](uint32_t tix) {
+    if (pin) pin_to_allowed_cpu(tix);
     struct Lane {
       uint32_t id;
       uint64_t next = 0;

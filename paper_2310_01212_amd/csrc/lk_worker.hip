@@ -88,12 +88,18 @@ __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uin
 }
 
 // ----------------------------------------------------------------------------- worker
+// Marker wave 0 leaves in the doorbell word when the idle watchdog fires: its code field
+// (0xff) is no command code, so no posted doorbell can equal it.
+constexpr uint64_t kIdleExit = ~0ull;
+
 extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   // Dynamic LDS: holds the CU's LDS share and serves as the pinned-input buffer.
   extern __shared__ float4 lds_pin[];
-  __shared__ uint64_t s_w[LKW_CMD_WORDS];
+  // Command words broadcast by wave 0; word 0 holds kIdleExit instead of the doorbell
+  // when the idle watchdog fired, so one batch of LDS reads tells every wave what to do.
+  __shared__ __align__(16) uint64_t s_w[LKW_CMD_WORDS];
   __shared__ uint64_t s_batch_next;
-  __shared__ uint32_t s_mb, s_go;
+  __shared__ uint32_t s_mb;
   __shared__ int64_t s_red[lkops::kMaxWaves];
   const uint32_t tid = threadIdx.x;
 
@@ -166,22 +172,24 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       if (p.first_delay < 0 && seq > 0 && outcome == 0 && wall_clock64() - t0 < p.b2b_ticks)
         pre = polls == 0 ? (pre > 0 ? pre - 1 : 0u) : (pre + 2 > 96 ? 96u : pre + 2);
       if (outcome == 0 && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      if (tid < LKW_CMD_WORDS) s_w[tid] = v;
-      if (tid == 0) s_go = outcome;
+      if (tid < LKW_CMD_WORDS) s_w[tid] = (tid == 0 && outcome != 0) ? kIdleExit : v;
       t_pick = wall_clock64();
       hw = read_hw_id();
       xcc = read_xcc_id();
     }
     __syncthreads();
 
-    if (s_go != 0) {  // idle watchdog: leave the loop
+    // All eight command words in one batch of 16-byte LDS reads, then wave-uniform.
+    const ulonglong2 *sw2 = reinterpret_cast<const ulonglong2 *>(s_w);
+    const ulonglong2 q0 = sw2[0], q1 = sw2[1], q2 = sw2[2], q3 = sw2[3];
+    const uint64_t w0 = uniform_u64(q0.x);
+    if (w0 == kIdleExit) {  // idle watchdog: leave the loop
       if (tid == 0) {
         st_sys(&wr->t_exit, wall_clock64());
         st_sys_release(&wr->word, LKW_WORD(seq, LKW_FROM_TIMEDOUT));
       }
       return;
     }
-    const uint64_t w0 = uniform_u64(s_w[LKW_W_DOORBELL]);
     const uint32_t code = LKW_CODE(w0);
     if (code == LKW_TO_EXIT) {  // THREAD_EXIT (Table 1)
       if (tid < LKW_S_WORDS) publish_status(sring + slot, want, LKW_FROM_EXITED, 0, t_pick, t_pick, hw, xcc);
@@ -199,14 +207,17 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     uint32_t reply = LKW_FROM_FINISHED;
     lkops::Slice s;
     s.op = 0;
-    s.n = uniform_u64(s_w[LKW_W_N] & LKW_PAYLOAD_MASK);
-    s.in = reinterpret_cast<const void *>(uniform_u64(s_w[LKW_W_IN] & LKW_PAYLOAD_MASK));
-    s.out = reinterpret_cast<void *>(uniform_u64(s_w[LKW_W_OUT] & LKW_PAYLOAD_MASK));
-    s.in2 = reinterpret_cast<const void *>(uniform_u64(s_w[LKW_W_AUX] & LKW_PAYLOAD_MASK));
-    s.a = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_A]));
-    s.b = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_B]));
-    const uint32_t dflags = uniform_u32(static_cast<uint32_t>(s_w[LKW_W_B] >> 32) & 0xffffu);
-    s.alpha = __uint_as_float(uniform_u32(static_cast<uint32_t>(s_w[LKW_W_ALPHA])));
+    static_assert(LKW_W_DOORBELL == 0 && LKW_W_N == 1 && LKW_W_IN == 2 && LKW_W_OUT == 3 && LKW_W_AUX == 4 &&
+                      LKW_W_A == 5 && LKW_W_B == 6 && LKW_W_ALPHA == 7,
+                  "command word order");
+    s.n = uniform_u64(q0.y & LKW_PAYLOAD_MASK);
+    s.in = reinterpret_cast<const void *>(uniform_u64(q1.x & LKW_PAYLOAD_MASK));
+    s.out = reinterpret_cast<void *>(uniform_u64(q1.y & LKW_PAYLOAD_MASK));
+    s.in2 = reinterpret_cast<const void *>(uniform_u64(q2.x & LKW_PAYLOAD_MASK));
+    s.a = uniform_u32(static_cast<uint32_t>(q2.y));
+    s.b = uniform_u32(static_cast<uint32_t>(q3.x));
+    const uint32_t dflags = uniform_u32(static_cast<uint32_t>(q3.x >> 32) & 0xffffu);
+    s.alpha = __uint_as_float(uniform_u32(static_cast<uint32_t>(q3.y)));
     if (code == LKW_TO_NOP) {
       reply = LKW_FROM_NOP;
     } else if (code >= LKW_TO_WORK && code < LKW_TO_WORK + lkd::kOpCount) {
