@@ -149,6 +149,9 @@ enum { LK_CLUSTERS_PER_WORKER = 0, LK_CLUSTERS_PER_XCD = 1, LK_CLUSTERS_ONE = 2,
                                      callers that never rewrite input buffers behind the
                                      GPU's caches between items (measurement variant) */
 #define LK_F_ANY_PLACEMENT  0x4u  /* do not require distinct CUs for the workers */
+#define LK_F_NO_LOOKAHEAD   0x8u  /* queue_depth > 1: do not read the next ring slot while an
+                                     item runs (by default a worker does, and takes a command
+                                     the host has already posted without another round trip) */
 
 typedef struct lk_config {
   int32_t device;              /* HIP device ordinal */

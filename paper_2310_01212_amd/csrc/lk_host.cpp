@@ -211,7 +211,7 @@ int validate_config(const lk_config *cfg) {
   }
   if (cfg->poll_sleep > 127) return fail(LK_EINVAL, "poll_sleep %u > 127", cfg->poll_sleep);
   if (cfg->idle_timeout_ms > 3600000u) return fail(LK_EINVAL, "idle_timeout_ms %u > 3600000", cfg->idle_timeout_ms);
-  if (cfg->flags & ~(LK_F_REPORT_WORKING | LK_F_NO_ACQUIRE | LK_F_ANY_PLACEMENT))
+  if (cfg->flags & ~(LK_F_REPORT_WORKING | LK_F_NO_ACQUIRE | LK_F_ANY_PLACEMENT | LK_F_NO_LOOKAHEAD))
     return fail(LK_EINVAL, "unknown flags 0x%x", cfg->flags);
   if (cfg->init_timeout_ns < 0) return fail(LK_EINVAL, "init_timeout_ns < 0");
   if (cfg->log_capacity > (1u << 24)) return fail(LK_EINVAL, "log_capacity %u > 2^24", cfg->log_capacity);
@@ -392,12 +392,16 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   p.poll_sleep = cfg.poll_sleep;
   p.threads = c->threads;
   p.flags = ((cfg.flags & LK_F_REPORT_WORKING) ? LKW_K_REPORT_WORKING : 0u) |
-            ((cfg.flags & LK_F_NO_ACQUIRE) ? LKW_K_NO_ACQUIRE : 0u);
+            ((cfg.flags & LK_F_NO_ACQUIRE) ? LKW_K_NO_ACQUIRE : 0u) |
+            ((cfg.flags & LK_F_NO_LOOKAHEAD) ? LKW_K_NO_LOOKAHEAD : 0u);
   const uint32_t idle_ms = cfg.idle_timeout_ms ? cfg.idle_timeout_ms : 10000u;
   p.idle_ticks = c->wall_hz / 1000ull * idle_ms;
   p.first_delay = cfg.first_poll_delay;
   p.b2b_ticks = static_cast<uint32_t>(c->wall_hz / 100000ull);  // 10 us
   p.lds_bytes = lds_pad;
+  // About a host round trip (1.6 us): a look-ahead read waits at most that long, so it
+  // is issued only when the previous item ran longer and the read hides under the item.
+  p.la_ticks = static_cast<uint32_t>(c->wall_hz / 625000ull);
 
   if (!c->wq->start(p, c->n_workers, c->threads, lds_pad, &err))
     return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));

@@ -121,7 +121,7 @@ typedef struct lkw_params {
   int32_t first_delay;   /* s_sleep(1) units before the first poll after a completion; -1 = adaptive */
   uint32_t b2b_ticks;    /* a command found this soon after a completion counts as back-to-back */
   uint32_t lds_bytes;    /* dynamic LDS of each worker (the pinned-input buffer) */
-  uint32_t pad;
+  uint32_t la_ticks;     /* look-ahead only after an item that ran at least this long */
 } lkw_params;
 
 /* Descriptor flags, carried in bits 32..47 of LKW_W_B (same values as LK_DF_*). */
@@ -130,6 +130,7 @@ typedef struct lkw_params {
 
 #define LKW_K_REPORT_WORKING 0x1u
 #define LKW_K_NO_ACQUIRE 0x2u
+#define LKW_K_NO_LOOKAHEAD 0x4u
 
 /* Dynamic LDS requested per worker so that two workers never fit on one CU
  * (160 KiB of LDS per CU on gfx950). */

@@ -136,6 +136,17 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   // Input held in lds_pin: device address and element count of the last pinned x
   // (pin_n == 0: nothing pinned).
   uint64_t pin_addr = 0, pin_n = 0;
+  // Look-ahead (ring depth > 1): wave 0 reads the next slot while the current item runs,
+  // so a command the host has already posted is taken without another host round trip.
+  // The read is issued only when the previous item ran for at least p.la_ticks (about a
+  // host round trip): the item's completion waits for the read, which then costs nothing
+  // extra, while for short items it would delay every completion.  have_next / v_next
+  // (wave 0, lanes 0..7: the slot's words) carry a validated command into the next
+  // iteration; its acquire has then already been performed.
+  const bool look = p.depth > 1 && !(p.flags & LKW_K_NO_LOOKAHEAD);
+  bool have_next = false;
+  uint64_t v_next = 0;
+  uint64_t last_busy = 0;  // pickup to completion of the previous item (wave 0)
 
   for (;;) {
     const uint64_t want = seq + 1;
@@ -150,9 +161,9 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       const uint64_t tag = want & 0xffffu;
       const uint64_t t0 = wall_clock64();
       uint32_t polls = 0, outcome = 0;
-      uint64_t v = 0;
-      if (seq > 0) backoff(p.first_delay < 0 ? pre : static_cast<uint32_t>(p.first_delay));
-      for (;;) {
+      uint64_t v = v_next;
+      if (!have_next && seq > 0) backoff(p.first_delay < 0 ? pre : static_cast<uint32_t>(p.first_delay));
+      while (!have_next) {
         if (tid < LKW_CMD_WORDS) v = ld_sys(src + tid);
         bool ok = true;
         if (tid == 0) ok = LKW_SEQ(v) == want;
@@ -169,9 +180,11 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
         }
         backoff(p.poll_sleep);
       }
-      if (p.first_delay < 0 && seq > 0 && outcome == 0 && wall_clock64() - t0 < p.b2b_ticks)
-        pre = polls == 0 ? (pre > 0 ? pre - 1 : 0u) : (pre + 2 > 96 ? 96u : pre + 2);
-      if (outcome == 0 && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      if (!have_next) {
+        if (p.first_delay < 0 && seq > 0 && outcome == 0 && wall_clock64() - t0 < p.b2b_ticks)
+          pre = polls == 0 ? (pre > 0 ? pre - 1 : 0u) : (pre + 2 > 96 ? 96u : pre + 2);
+        if (outcome == 0 && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      }
       if (tid < LKW_CMD_WORDS) s_w[tid] = (tid == 0 && outcome != 0) ? kIdleExit : v;
       t_pick = wall_clock64();
       hw = read_hw_id();
@@ -225,6 +238,13 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     } else {
       reply = LKW_FROM_ERROR;
     }
+    // Look-ahead read of the next slot, issued before this wave's own data accesses so
+    // that it returns while the item runs (vector memory completes in order).
+    const uint32_t slot_next = slot + 1 == p.depth ? 0u : slot + 1;
+    uint64_t v_ahead = 0;
+    const bool ahead_read = look && last_busy >= p.la_ticks;  // wave 0's decision
+    if (ahead_read && tid < LKW_CMD_WORDS) v_ahead = ld_sys(ring[slot_next].w + tid);
+
     int64_t partial = 0;
     if (s.op == lkd::kOpBatch) {
       partial = run_batch(static_cast<const lkd::Tile *>(s.in), s.n, static_cast<int64_t *>(s.out),
@@ -262,6 +282,21 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     __syncthreads();
     if (tid < 64) {
       const uint64_t t_done = wall_clock64();
+      // A complete next command (doorbell sequence and every word's tag) is taken now;
+      // its acquire comes before this item's status so that the next item can start as
+      // soon as the status is out.
+      bool ahead = false;
+      last_busy = t_done - t_pick;
+      if (ahead_read) {
+        const uint64_t nseq = want + 1;
+        bool ok = true;
+        if (tid == 0) ok = LKW_SEQ(v_ahead) == nseq;
+        else if (tid < LKW_CMD_WORDS) ok = (v_ahead >> LKW_TAG_SHIFT) == (nseq & 0xffffu);
+        ahead = __all(ok);
+        if (ahead && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      }
+      have_next = ahead;
+      v_next = v_ahead;
       const int64_t part0 = static_cast<int64_t>(uniform_u64(static_cast<uint64_t>(partial)));  // thread 0's
       if (tid < LKW_S_WORDS) publish_status(sring + slot, want, reply, part0, t_pick, t_done, hw, xcc);
       if (tid == 0 && wlog) {
@@ -275,7 +310,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
       }
     }
     seq = want;
-    slot = slot + 1 == p.depth ? 0u : slot + 1;
+    slot = slot_next;
     log_i = log_i + 1 == p.log_cap ? 0u : log_i + 1;
   }
 }

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblk.so")
 OK, EINVAL, EAGAIN, ETIMEDOUT, ESTATE, ENODEV, EHIP, EFAULT = 0, -1, -2, -3, -4, -5, -6, -7
 OP_NOP, OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_SPIN, OP_BATCH, OP_AXPY_F32 = range(8)
 CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4)
-F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT = 1, 2, 4
+F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT, F_NO_LOOKAHEAD = 1, 2, 4, 8
 POLL_DELAY_ADAPTIVE = -1
 DF_PIN_INPUT, DF_PIN_RELOAD = 1, 2
 COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2

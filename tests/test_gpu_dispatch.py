@@ -552,21 +552,82 @@ def test_ring_full_timeout_and_disposed_state():
     ctx.close()  # idempotent
 
 
-def test_deeper_ring_keeps_fifo():
+@pytest.mark.parametrize("in_flight,flags", [(8, 0), (8, lk.F_NO_LOOKAHEAD), (1, 0), (3, 0)])
+def test_deeper_ring_keeps_fifo(in_flight, flags):
+    """Depth 8 with the ring kept full (the look-ahead read finds the next command), with
+    the look-ahead switched off, and with fewer items in flight than slots (it finds an
+    old sequence number in the next slot and falls back to polling)."""
     rng = np.random.default_rng(5)
     n = 4096
     x0 = rng.standard_normal(n).astype(np.float32)
     y0 = rng.standard_normal(n).astype(np.float32)
     alphas = rng.uniform(-2, 2, 200).astype(np.float32)
-    say("depth 8: 200 SAXPY items on one mailbox, up to 8 in flight")
+    say(f"depth 8: 200 SAXPY items on one mailbox, {in_flight} in flight, flags {flags}")
     x, y = to_dev(x0), to_dev(y0)
-    with lk.Context(n_workers=1, depth=8, log_capacity=256) as ctx:
+    with lk.Context(n_workers=1, depth=8, log_capacity=256, flags=flags) as ctx:
         items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x), addr(y), alpha=alphas)[None, :]
-        res, lat, el = ctx.run_lanes([0], items, in_flight=8, threads=1)
+        res, lat, el = ctx.run_lanes([0], items, in_flight=in_flight, threads=1)
     want = y0.copy()
     oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=x0, out=want, alpha=a) for a in alphas])
     assert np.array_equal(y.cpu().numpy().view(np.uint32), want.view(np.uint32))
     check_log(ctx.log(0), 200, lk.CODE_WORK + lk.OP_SAXPY_F32)
+
+
+@pytest.mark.parametrize("flags", [0, lk.F_NO_LOOKAHEAD])
+def test_lookahead_mixed_ops_all_cus_depth4_exact(flags):
+    """All CUs at depth 4, each mailbox fed a FIFO mix of affine + sum, SAXPY, NOP and
+    sum items four ahead.  The items are long enough (65,532 elements) for the worker to
+    read the next slot while each one runs, so most commands are taken by that look-ahead
+    read (the device-side gap from one completion to the next pickup stays under a host
+    round trip).  Every result, the final outputs and the log order match the oracle,
+    with the look-ahead and without it."""
+    items_per_lane, n = 64, 65532
+    with lk.Context(n_workers=0, depth=4, log_capacity=128, idle_timeout_ms=20000, flags=flags) as ctx:
+        lanes = ctx.info()["n_workers"]
+        say(f"look-ahead: {lanes} lanes x {items_per_lane} mixed items at depth 4")
+        rng = np.random.default_rng(71)
+        span = n + 4
+        XI = rng.integers(-2 ** 31, 2 ** 31, (lanes, span), dtype=np.int64).astype(np.int32)
+        XF = rng.standard_normal((lanes, span)).astype(np.float32)
+        YF0 = rng.standard_normal((lanes, span)).astype(np.float32)
+        AB = rng.integers(-2 ** 31, 2 ** 31, (lanes, items_per_lane, 2), dtype=np.int64).astype(np.int32)
+        AL = rng.uniform(-2, 2, (lanes, items_per_lane)).astype(np.float32)
+        xi, xf, yf = to_dev(XI), to_dev(XF), to_dev(YF0)
+        yi = sentinel_i32((lanes, span))
+        torch.cuda.synchronize()
+        li = np.arange(lanes, dtype=np.uint64)[:, None]
+        kinds = np.array([lk.OP_AFFINE_SUM_I32, lk.OP_SAXPY_F32, lk.OP_NOP, lk.OP_SUM_I32_I64])
+        op = np.broadcast_to(kinds[np.arange(items_per_lane) % 4], (lanes, items_per_lane))
+        is_f = op == lk.OP_SAXPY_F32
+        inp = np.where(is_f, addr(xf) + li * span * 4, addr(xi) + li * span * 4)
+        out = np.where(is_f, addr(yf) + li * span * 4, addr(yi) + li * span * 4)
+        nn = np.where(op == lk.OP_NOP, 0, n)
+        it = lk.make_items(op, nn, inp, out, a=AB[..., 0], b=AB[..., 1], alpha=AL)
+        res, lat, el = ctx.run_lanes(np.arange(lanes), it, in_flight=4, threads=8)
+    YI, YF = yi.cpu().numpy(), yf.cpu().numpy()
+    hz = ctx.info()["wall_clock_hz"]
+    gaps = []
+    for w in range(lanes):
+        x = XI[w, :n].copy()
+        s_sum = oracle.sum_i32_i64(x)
+        y_last = None
+        for k in range(items_per_lane):
+            if op[w, k] == lk.OP_AFFINE_SUM_I32:
+                y_last, sr = oracle.affine_sum_i32(x, int(AB[w, k, 0]), int(AB[w, k, 1]))
+                assert res[w, k] == sr, (w, k)
+            elif op[w, k] == lk.OP_SUM_I32_I64:
+                assert res[w, k] == s_sum, (w, k)
+        assert np.array_equal(YI[w, :n], y_last), w
+        want = YF0[w, :n].copy()
+        oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, XF[w, :n].copy(), want, AL[w, is_f[w]]))
+        assert np.array_equal(YF[w, :n].view(np.uint32), want.view(np.uint32)), w
+        e = ctx.log(w)
+        assert np.array_equal(e["seq"], np.arange(1, items_per_lane + 1, dtype=np.uint32))
+        assert np.array_equal(e["code"], lk.CODE_WORK + op[w])
+        gaps.append(np.median((e["t_pick"][1:] - e["t_done"][:-1]) * 1e6 / hz))
+    say(f"  median gap completion -> next pickup {np.median(gaps):.2f} us")
+    if not flags:
+        assert np.median(gaps) < 1.0, "the look-ahead read did not take the posted commands"
 
 
 def test_idle_watchdog_ends_workers():
