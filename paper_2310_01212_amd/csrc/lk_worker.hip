@@ -92,35 +92,12 @@ __device__ __forceinline__ void publish_status(lkw_status *st, uint64_t seq, uin
 // (0xff) is no command code, so no posted doorbell can equal it.
 constexpr uint64_t kIdleExit = ~0ull;
 
-extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
-  // Dynamic LDS: holds the CU's LDS share and serves as the pinned-input buffer.
-  extern __shared__ float4 lds_pin[];
-  // Command words broadcast by wave 0; word 0 holds kIdleExit instead of the doorbell
-  // when the idle watchdog fired, so one batch of LDS reads tells every wave what to do.
-  __shared__ __align__(16) uint64_t s_w[LKW_CMD_WORDS];
-  __shared__ uint64_t s_batch_next;
-  __shared__ uint32_t s_mb;
-  __shared__ int64_t s_red[lkops::kMaxWaves];
+// The command loop of one worker (mailbox m), compiled once with the look-ahead read and
+// once without it, so a depth-1 context runs none of its bookkeeping.
+template <bool LOOK>
+__device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *lds_pin, uint64_t *s_w,
+                                      uint64_t *s_batch_next, int64_t *s_red) {
   const uint32_t tid = threadIdx.x;
-
-  // Boot: claim a mailbox, record the physical placement, announce INIT (Table 1).
-  if (tid == 0) {
-    const uint32_t m = atomicAdd(p.claim, 1u);
-    s_mb = m;
-    if (m < p.n_workers) {
-      const uint32_t hw = read_hw_id(), xcc = read_xcc_id();
-      lkw_worker *wr = p.workers + m;
-      st_sys_u32(&wr->hwid, hw);
-      st_sys_u32(&wr->xcc, xcc);
-      st_sys_u32(&wr->wg, blockIdx.x);
-      st_sys(&wr->t_boot, wall_clock64());
-      st_sys_release(&wr->word, LKW_WORD(0, LKW_FROM_INIT));
-    }
-  }
-  __syncthreads();
-  const uint32_t m = s_mb;
-  if (m >= p.n_workers) return;
-
   const uint64_t stride = LKW_RING_STRIDE(p.depth);
   lkw_cmd *ring = p.cmd + m * stride;
   lkw_status *sring = p.status + m * stride;
@@ -143,7 +120,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   // extra, while for short items it would delay every completion.  have_next / v_next
   // (wave 0, lanes 0..7: the slot's words) carry a validated command into the next
   // iteration; its acquire has then already been performed.
-  const bool look = p.depth > 1 && !(p.flags & LKW_K_NO_LOOKAHEAD);
+  constexpr bool look = LOOK;
   bool have_next = false;
   uint64_t v_next = 0;
   uint64_t last_busy = 0;  // pickup to completion of the previous item (wave 0)
@@ -249,7 +226,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     if (s.op == lkd::kOpBatch) {
       partial = run_batch(static_cast<const lkd::Tile *>(s.in), s.n, static_cast<int64_t *>(s.out),
                           reinterpret_cast<uint64_t *>(const_cast<void *>(s.in2)),
-                          static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, &s_batch_next,
+                          static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, s_batch_next,
                           p.threads);
     } else if (s.op != 0) {
       // Pinned input (AXPY forms only): x is served from LDS when this worker's last
@@ -279,22 +256,23 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     if (tid == 0 && s.in2 && (s.op == 1 || s.op == 2))  // ops with an int64 result
       st_sys_i64(reinterpret_cast<int64_t *>(const_cast<void *>(s.in2)), partial);
     drain_wave_memory();
+    // A complete next command (doorbell sequence and every word's tag) found by the
+    // look-ahead read is taken here, by wave 0 once its own part of the item is done: its
+    // acquire then overlaps the other waves' store drain, and the next item starts as
+    // soon as this item's status is out.
+    bool ahead = false;
+    if (look && ahead_read && tid < 64) {
+      const uint64_t nseq = want + 1;
+      bool ok = true;
+      if (tid == 0) ok = LKW_SEQ(v_ahead) == nseq;
+      else if (tid < LKW_CMD_WORDS) ok = (v_ahead >> LKW_TAG_SHIFT) == (nseq & 0xffffu);
+      ahead = __all(ok);
+      if (ahead && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    }
     __syncthreads();
     if (tid < 64) {
       const uint64_t t_done = wall_clock64();
-      // A complete next command (doorbell sequence and every word's tag) is taken now;
-      // its acquire comes before this item's status so that the next item can start as
-      // soon as the status is out.
-      bool ahead = false;
       last_busy = t_done - t_pick;
-      if (ahead_read) {
-        const uint64_t nseq = want + 1;
-        bool ok = true;
-        if (tid == 0) ok = LKW_SEQ(v_ahead) == nseq;
-        else if (tid < LKW_CMD_WORDS) ok = (v_ahead >> LKW_TAG_SHIFT) == (nseq & 0xffffu);
-        ahead = __all(ok);
-        if (ahead && !(p.flags & LKW_K_NO_ACQUIRE)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      }
       have_next = ahead;
       v_next = v_ahead;
       const int64_t part0 = static_cast<int64_t>(uniform_u64(static_cast<uint64_t>(partial)));  // thread 0's
@@ -313,4 +291,39 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     slot = slot_next;
     log_i = log_i + 1 == p.log_cap ? 0u : log_i + 1;
   }
+}
+
+extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
+  // Dynamic LDS: holds the CU's LDS share and serves as the pinned-input buffer.
+  extern __shared__ float4 lds_pin[];
+  // Command words broadcast by wave 0; word 0 holds kIdleExit instead of the doorbell
+  // when the idle watchdog fired, so one batch of LDS reads tells every wave what to do.
+  __shared__ __align__(16) uint64_t s_w[LKW_CMD_WORDS];
+  __shared__ uint64_t s_batch_next;
+  __shared__ uint32_t s_mb;
+  __shared__ int64_t s_red[lkops::kMaxWaves];
+  const uint32_t tid = threadIdx.x;
+
+  // Boot: claim a mailbox, record the physical placement, announce INIT (Table 1).
+  if (tid == 0) {
+    const uint32_t m = atomicAdd(p.claim, 1u);
+    s_mb = m;
+    if (m < p.n_workers) {
+      const uint32_t hw = read_hw_id(), xcc = read_xcc_id();
+      lkw_worker *wr = p.workers + m;
+      st_sys_u32(&wr->hwid, hw);
+      st_sys_u32(&wr->xcc, xcc);
+      st_sys_u32(&wr->wg, blockIdx.x);
+      st_sys(&wr->t_boot, wall_clock64());
+      st_sys_release(&wr->word, LKW_WORD(0, LKW_FROM_INIT));
+    }
+  }
+  __syncthreads();
+  const uint32_t m = s_mb;
+  if (m >= p.n_workers) return;
+
+  if (p.depth > 1 && !(p.flags & LKW_K_NO_LOOKAHEAD))
+    serve<true>(p, m, lds_pin, s_w, &s_batch_next, s_red);
+  else
+    serve<false>(p, m, lds_pin, s_w, &s_batch_next, s_red);
 }
