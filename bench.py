@@ -62,15 +62,21 @@ def int_sum_check(x, a=None, b=None):
 
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
                  ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md")]
-WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h"]
+WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h", "lk_device.h", "lk_common.h"]
 
 
 def worker_source_digest():
+    """First 16 hex digits of the sha256 of the worker's sources with comments removed and
+    whitespace collapsed, so that a counter summary stays valid across comment edits."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in WORKER_SOURCES:
-        with open(os.path.join(ROOT, "paper_2310_01212_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2310_01212_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

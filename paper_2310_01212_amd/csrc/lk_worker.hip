@@ -1,15 +1,19 @@
 /*
  * lk_worker.hip -- the persistent worker of the LightKernel dispatch loop for gfx950.
  *
- * One workgroup per CU (Sec. 2.3: one block per cluster, pinned at boot), dispatched once
- * for the whole session on an HSA queue of its own (see lk_queue.cpp).  Each workgroup:
+ * One workgroup per CU (Sec. 2.3: one block per cluster, pinned at boot; up to four per
+ * CU on request), dispatched once for the whole session on an HSA queue of its own (see
+ * lk_queue.cpp).  Each workgroup:
  *   1. claims a mailbox, reads its physical placement from the HW_ID / XCC_ID registers
  *      and announces THREAD_INIT (Table 1);
  *   2. polls its to_GPU command slot: wave 0 reads the whole 64-byte slot with lanes 0..7,
- *      with s_sleep backoff and an idle watchdog on the device wall clock;
+ *      with s_sleep backoff and an idle watchdog on the device wall clock (with a ring
+ *      deeper than one slot, a command already posted is usually found by the look-ahead
+ *      read issued during the previous item instead);
  *   3. on a new command, takes one system-scope acquire and broadcasts the descriptor to
  *      the workgroup through LDS;
- *   4. runs the work item over its slice with all its waves (lk_ops.hpp);
+ *   4. runs the work item over its slice with all its waves (lk_ops.hpp), reading a
+ *      pinned x from its LDS when the descriptor asks for it;
  *   5. every wave drains its own output stores, which are written through to memory
  *      (SystemStore, lk_ops.hpp); after a barrier wave 0 publishes THREAD_FINISHED as one
  *      64-byte status record (Sec. 2.4: the master thread owns the two mailboxes).
