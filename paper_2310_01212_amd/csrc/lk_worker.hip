@@ -173,9 +173,18 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
     }
     __syncthreads();
 
-    // All eight command words in one batch of 16-byte LDS reads, then wave-uniform.
+    // All eight command words in one batch of 16-byte LDS reads, then wave-uniform.  Only
+    // lane 0 of each wave reads (readfirstlane takes its values): a full-wave read would
+    // move 64 copies of the record through the LDS return path, 64 KiB per item for 16
+    // waves.
     const ulonglong2 *sw2 = reinterpret_cast<const ulonglong2 *>(s_w);
-    const ulonglong2 q0 = sw2[0], q1 = sw2[1], q2 = sw2[2], q3 = sw2[3];
+    ulonglong2 q0 = {0, 0}, q1 = {0, 0}, q2 = {0, 0}, q3 = {0, 0};
+    if ((tid & 63u) == 0) {
+      q0 = sw2[0];
+      q1 = sw2[1];
+      q2 = sw2[2];
+      q3 = sw2[3];
+    }
     const uint64_t w0 = uniform_u64(q0.x);
     if (w0 == kIdleExit) {  // idle watchdog: leave the loop
       if (tid == 0) {
@@ -223,7 +232,8 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
     // that it returns while the item runs (vector memory completes in order).
     const uint32_t slot_next = slot + 1 == p.depth ? 0u : slot + 1;
     uint64_t v_ahead = 0;
-    const bool ahead_read = look && last_busy >= p.la_ticks;  // wave 0's decision
+    // (Not for a batch: its first tile claim would wait behind the read.)
+    const bool ahead_read = look && last_busy >= p.la_ticks && s.op != lkd::kOpBatch;  // wave 0's decision
     if (ahead_read && tid < LKW_CMD_WORDS) v_ahead = ld_sys(ring[slot_next].w + tid);
 
     int64_t partial = 0;
