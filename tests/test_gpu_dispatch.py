@@ -552,19 +552,21 @@ def test_ring_full_timeout_and_disposed_state():
     ctx.close()  # idempotent
 
 
-@pytest.mark.parametrize("in_flight,flags", [(8, 0), (8, lk.F_NO_LOOKAHEAD), (1, 0), (3, 0)])
-def test_deeper_ring_keeps_fifo(in_flight, flags):
+@pytest.mark.parametrize("in_flight,flags,threads,n", [(8, 0, 256, 4096), (8, lk.F_NO_LOOKAHEAD, 256, 4096),
+                                                        (1, 0, 256, 4096), (3, 0, 256, 4096),
+                                                        (8, 0, 64, 65536), (8, 0, 1024, 65536)])
+def test_deeper_ring_keeps_fifo(in_flight, flags, threads, n):
     """Depth 8 with the ring kept full (the look-ahead read finds the next command), with
-    the look-ahead switched off, and with fewer items in flight than slots (it finds an
-    old sequence number in the next slot and falls back to polling)."""
+    the look-ahead switched off, with fewer items in flight than slots (it finds an old
+    sequence number in the next slot and falls back to polling), and with items long
+    enough for the look-ahead on workers of one wave and of sixteen."""
     rng = np.random.default_rng(5)
-    n = 4096
     x0 = rng.standard_normal(n).astype(np.float32)
     y0 = rng.standard_normal(n).astype(np.float32)
     alphas = rng.uniform(-2, 2, 200).astype(np.float32)
-    say(f"depth 8: 200 SAXPY items on one mailbox, {in_flight} in flight, flags {flags}")
+    say(f"depth 8: 200 SAXPY items of {n} on one mailbox, {in_flight} in flight, flags {flags}, {threads} threads")
     x, y = to_dev(x0), to_dev(y0)
-    with lk.Context(n_workers=1, depth=8, log_capacity=256, flags=flags) as ctx:
+    with lk.Context(n_workers=1, depth=8, log_capacity=256, flags=flags, threads=threads) as ctx:
         items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x), addr(y), alpha=alphas)[None, :]
         res, lat, el = ctx.run_lanes([0], items, in_flight=in_flight, threads=1)
     want = y0.copy()
