@@ -647,24 +647,30 @@ def bench_allcu(args):
                 off = (li * P + pair) * n * 4
                 cit.append(lk.make_items(lk.OP_SAXPY_F32, n, cx.data_ptr() + off, cy.data_ptr() + off,
                                          alpha=A[:, s * per:(s + 1) * per]))
-            with lk.Context(n_workers=lanes, threads=args.threads_per_worker, poll_sleep=args.poll_sleep,
-                            idle_timeout_ms=60000) as cc:
-                cc.run_lanes(np.arange(lanes), cit[0], in_flight=1, threads=args.threads)
-                clat, ct = [], 0.0
-                for s in range(1, csteps):
-                    _, lat, el = cc.run_lanes(np.arange(lanes), cit[s], in_flight=1, threads=args.threads)
-                    clat.append(lat)
-                    ct += el
-            cinfo = cc.info()
+            cold = {}
+            # depth 1 (the headline's form), then the ring kept args.pipelined_depth ahead:
+            # with the look-ahead read the CUs stay busy and HBM becomes the bound
+            for cd in sorted({1, max(1, args.pipelined_depth)}):
+                with lk.Context(n_workers=lanes, depth=cd, threads=args.threads_per_worker,
+                                poll_sleep=args.poll_sleep, idle_timeout_ms=60000) as cc:
+                    cc.run_lanes(np.arange(lanes), cit[0], in_flight=cd, threads=args.threads)
+                    clat, ct = [], 0.0
+                    for s in range(1, csteps):
+                        _, lat, el = cc.run_lanes(np.arange(lanes), cit[s], in_flight=cd, threads=args.threads)
+                        clat.append(lat)
+                        ct += el
+                cinfo = cc.info()
+                clat = np.concatenate([l.ravel() for l in clat])
+                c_items = lanes * per * csteps
+                c_gbps = c_items * bytes_per_item / (cinfo["device_span_ms"] * 1e-3) / 1e9
+                cold[cd] = {"queue_depth": cd, "items_per_s": round(clat.size / ct, 1), "latency_us": lat_summary(clat),
+                            "kernel_ms": round(cinfo["device_span_ms"], 3), "items_per_launch": c_items,
+                            "achieved_gbps": round(c_gbps, 1), "frac_of_peak": round(c_gbps / HBM_PEAK_GBPS, 4)}
+                log(f"cold ({P} pairs per mailbox, depth {cd}): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
             del cx, cy
-            clat = np.concatenate([l.ravel() for l in clat])
-            c_items = lanes * per * csteps
-            c_gbps = c_items * bytes_per_item / (cinfo["device_span_ms"] * 1e-3) / 1e9
-            result["cold_variant"] = {"pairs_per_mailbox": P, "footprint_bytes": lanes * P * n * 8,
-                                      "items_per_s": round(clat.size / ct, 1), "latency_us": lat_summary(clat),
-                                      "kernel_ms": round(cinfo["device_span_ms"], 3), "items_per_launch": c_items,
-                                      "achieved_gbps": round(c_gbps, 1), "frac_of_peak": round(c_gbps / HBM_PEAK_GBPS, 4)}
-            log(f"cold ({P} pairs per mailbox): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
+            result["cold_variant"] = {"pairs_per_mailbox": P, "footprint_bytes": lanes * P * n * 8, **cold[1]}
+            if len(cold) > 1:
+                result["cold_variant"]["pipelined"] = cold[max(cold)]
 
         # pinned-input variants: x kept in each worker's LDS across items (descriptor flag
         # DF_PIN_INPUT).  "hot" is the headline workload with the flag; "y_cold" keeps x per
@@ -672,13 +678,13 @@ def bench_allcu(args):
         # run without and with the flag.  Bandwidths are algorithmic (12n bytes per item),
         # as for the headline
         if args.pinned and not args.pin_input:
-            def timed(ctx_kw, items_of_step, nsteps):
-                with lk.Context(n_workers=lanes, threads=args.threads_per_worker, poll_sleep=args.poll_sleep,
-                                idle_timeout_ms=60000, **ctx_kw) as cx:
-                    cx.run_lanes(np.arange(lanes), items_of_step(0), in_flight=1, threads=args.threads)
+            def timed(ctx_kw, items_of_step, nsteps, depth=1):
+                with lk.Context(n_workers=lanes, depth=depth, threads=args.threads_per_worker,
+                                poll_sleep=args.poll_sleep, idle_timeout_ms=60000, **ctx_kw) as cx:
+                    cx.run_lanes(np.arange(lanes), items_of_step(0), in_flight=depth, threads=args.threads)
                     ll, tt = [], 0.0
                     for s in range(1, nsteps):
-                        _, lat, el = cx.run_lanes(np.arange(lanes), items_of_step(s), in_flight=1,
+                        _, lat, el = cx.run_lanes(np.arange(lanes), items_of_step(s), in_flight=depth,
                                                   threads=args.threads)
                         ll.append(lat)
                         tt += el
@@ -697,6 +703,12 @@ def bench_allcu(args):
                   "latency_us": lat_summary(pl), "items": int(pl.size),
                   "pin_capacity_bytes": pinf["pin_capacity"]}
             log(f"pinned (hot): {pl.size / pt:,.0f} items/s")
+            if args.pipelined_depth > 1:
+                d = args.pipelined_depth
+                ql, qt, _ = timed({}, lambda s: pin_items[s], psteps, depth=d)
+                pv["pipelined"] = {"queue_depth": d, "items_per_s": round(ql.size / qt, 1),
+                                   "latency_us": lat_summary(ql), "items": int(ql.size)}
+                log(f"pinned (hot), depth {d}: {ql.size / qt:,.0f} items/s")
             P = 32
             g = torch.Generator(device=dev)
             g.manual_seed(3)
