@@ -565,19 +565,26 @@ def bench_allcu(args):
     # ---------------- baselines on the same workload
     if not args.skip_baselines:
         base = {}
-        for name, mode in (("launch", 0), ("graph", lk.USE_GRAPH)):
-            bl = []
+        # launch: one hipLaunchKernelGGL per item; graph: a single-node graph relaunched per
+        # item (its parameters updated); graph_chain: each lane's items captured once as a
+        # chain of kernel nodes and launched as one graph (throughput only: the timed region
+        # is the native runner's, excluding capture and instantiation)
+        for name, mode in (("launch", 0), ("graph", lk.USE_GRAPH), ("graph_chain", lk.GRAPH_CHAIN)):
+            bl, el_native = [], 0.0
             t0 = time.perf_counter()
             for s in range(args.baseline_steps):
                 _, lat, el = lk.launch_lanes(step_items(s), streams=args.streams, threads_host=args.threads,
                                              threads=args.threads_per_worker, mode=mode)
                 bl.append(lat)
-            el = time.perf_counter() - t0
+                el_native += el
+            el = el_native if mode == lk.GRAPH_CHAIN else time.perf_counter() - t0
             bl = np.concatenate([b.ravel() for b in bl])
-            base[name] = {"items_per_s": round(bl.size / el, 1), "latency_us": lat_summary(bl),
+            base[name] = {"items_per_s": round(bl.size / el, 1),
+                          "latency_us": None if mode == lk.GRAPH_CHAIN else lat_summary(bl),
                           "streams": args.streams, "threads_per_wg": args.threads_per_worker,
                           "items": int(bl.size)}
-            log(f"{name}: {bl.size / el:,.0f} items/s, p50 {pct(bl, .5):.2f} us")
+            log(f"{name}: {bl.size / el:,.0f} items/s" +
+                ("" if mode == lk.GRAPH_CHAIN else f", p50 {pct(bl, .5):.2f} us"))
         result["baselines"] = base
         result["speedup_items_per_s"] = {k: round(items_per_s / v["items_per_s"], 2) for k, v in base.items()}
 
@@ -755,6 +762,10 @@ def bench_allcu(args):
             serial[name + "_launch_call"] = lat_summary(lau_b)
         rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
         serial["pingpong_rtt"] = lat_summary(rtt)
+        # the same echo with every CU's wave resident and polling its own word (host pings
+        # them in turn): the floor under all-CU load
+        rtt_all = lk.pingpong(workers=lanes, iters=200)[:, 20:]
+        serial["pingpong_rtt_all_cus"] = lat_summary(rtt_all)
         # one-CU streaming copy: the bandwidth one worker can reach on its own
         cb = 32 << 20
         csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
@@ -768,6 +779,7 @@ def bench_allcu(args):
                                             "+ int64 sum over 4096 elements", **serial}
         result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
                                       "floor_us": serial["pingpong_rtt"]["p50"],
+                                      "floor_us_all_cus_polling": serial["pingpong_rtt_all_cus"]["p50"],
                                       "dispatch_p50_us": serial["persistent"]["p50"],
                                       "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
                                       "item_bytes": item_bytes,

@@ -104,6 +104,7 @@ LK_API int lkb_launch_burst(int device, const lkb_item *items, uint32_t count, u
                                  kernel's last workgroup writes (system-scope release) */
 #define LKB_USE_GRAPH 2u      /* launch through a single-node hipGraph whose kernel node
                                  parameters are updated per item */
+#define LKB_GRAPH_CHAIN 4u     /* lkb_launch_lanes: one captured chain of kernel nodes per lane */
 
 /* One launch per item on one stream, grid = k workgroups of `threads` (slice j per
  * workgroup, the same slicing rule and op bodies as the persistent path).
@@ -114,7 +115,12 @@ LK_API int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb
 
 /* The lanes workload with one launch per item: lane l runs on stream l % n_streams, one
  * item in flight per lane, completion observed through the flag form, host thread
- * l % n_threads.  mode = 0 or LKB_USE_GRAPH.  Outputs as lkb_lanes. */
+ * l % n_threads.  mode = 0 or LKB_USE_GRAPH.  Outputs as lkb_lanes.
+ * mode = LKB_GRAPH_CHAIN instead captures each lane's items once as one hipGraph, a chain
+ * of items_per_lane kernel nodes (capture and instantiation not timed), then times the
+ * launch of every lane's graph on stream l % n_streams until all streams are idle: the
+ * throughput form of the graph baseline.  results[] are filled; no per-item completion is
+ * observed, so lat_us[] entries are set to 0 and *elapsed_s covers the whole run. */
 LK_API int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64_t items_per_lane,
                      uint32_t n_streams, uint32_t n_threads, uint32_t threads, uint32_t mode,
                      int64_t *results, double *lat_us, double *elapsed_s);

@@ -162,6 +162,60 @@ lkd::ItemArgs item_args(const lkb_item &it, uint32_t k) {
   return a;
 }
 
+// LKB_GRAPH_CHAIN form of lkb_launch_lanes: each lane's items captured once, in order, as
+// one hipGraph on the lane's stream; the timed region launches every lane's graph and
+// waits until every stream is idle.
+int graph_chain_lanes(uint32_t n_lanes, const lkb_item *items, uint64_t items_per_lane,
+                      std::vector<hipStream_t> &streams, uint32_t threads, int64_t *results, double *lat_us,
+                      double *elapsed_s) {
+  const uint64_t total = static_cast<uint64_t>(n_lanes) * items_per_lane;
+  CoherentRegion parts;  // one int64 partial per item
+  hipError_t e = parts.alloc(8ull * (total ? total : 1));
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  std::vector<hipGraphExec_t> execs(n_lanes, nullptr);
+  int rc = LK_OK;
+  for (uint32_t l = 0; l < n_lanes && rc == LK_OK; ++l) {
+    hipStream_t s = streams[l % streams.size()];
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+      rc = bfail(LK_EHIP, "begin capture: %s", hipGetErrorString(e));
+      break;
+    }
+    hipError_t le = hipSuccess;
+    for (uint64_t k = 0; k < items_per_lane && le == hipSuccess; ++k) {
+      const uint64_t idx = static_cast<uint64_t>(l) * items_per_lane + k;
+      lkd::ItemArgs a = item_args(items[idx], 1);
+      a.partials = static_cast<int64_t *>(parts.p) + idx;
+      le = lkd::launch_item(a, threads, s);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+      rc = bfail(LK_EHIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+    } else if ((e = hipGraphInstantiate(&execs[l], g, nullptr, nullptr, 0)) != hipSuccess) {
+      rc = bfail(LK_EHIP, "instantiate: %s", hipGetErrorString(e));
+    }
+    if (g) (void)hipGraphDestroy(g);
+  }
+  if (rc == LK_OK) {
+    const auto start = clk::now();
+    for (uint32_t l = 0; l < n_lanes && rc == LK_OK; ++l)
+      if ((e = hipGraphLaunch(execs[l], streams[l % streams.size()])) != hipSuccess)
+        rc = bfail(LK_EHIP, "graph launch: %s", hipGetErrorString(e));
+    for (hipStream_t s : streams)
+      if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == LK_OK)
+        rc = bfail(LK_EHIP, "synchronize: %s", hipGetErrorString(e));
+    if (elapsed_s) *elapsed_s = std::chrono::duration<double>(clk::now() - start).count();
+  }
+  for (hipGraphExec_t x : execs)
+    if (x) (void)hipGraphExecDestroy(x);
+  if (rc != LK_OK) return rc;
+  for (uint64_t i = 0; i < total; ++i) {
+    if (results) results[i] = __atomic_load_n(static_cast<int64_t *>(parts.p) + i, __ATOMIC_RELAXED);
+    if (lat_us) lat_us[i] = 0.0;
+  }
+  return LK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -606,6 +660,12 @@ int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64
   CoherentRegion reg;  // per lane: done word + partial, 64 bytes apart
   if (rc == LK_OK && (e = reg.alloc(64ull * n_lanes)) != hipSuccess)
     rc = bfail(LK_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  if (mode & LKB_GRAPH_CHAIN) {
+    if (rc == LK_OK) rc = graph_chain_lanes(n_lanes, items, items_per_lane, streams, threads, results, lat_us, elapsed_s);
+    for (auto &s : streams)
+      if (s) (void)hipStreamDestroy(s);
+    return rc;
+  }
   std::vector<ItemGraph> graphs(mode & LKB_USE_GRAPH ? n_lanes : 0);
   for (auto &g : graphs)
     if (rc == LK_OK && (e = g.build(1, threads)) != hipSuccess) rc = bfail(LK_EHIP, "graph build: %s", hipGetErrorString(e));

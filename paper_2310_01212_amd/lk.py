@@ -19,7 +19,7 @@ CLUSTERS_PER_WORKER, CLUSTERS_PER_XCD, CLUSTERS_ONE, CLUSTERS_EXPLICIT = range(4
 F_REPORT_WORKING, F_NO_ACQUIRE, F_ANY_PLACEMENT, F_NO_LOOKAHEAD = 1, 2, 4, 8
 POLL_DELAY_ADAPTIVE = -1
 DF_PIN_INPUT, DF_PIN_RELOAD = 1, 2
-COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH = 0, 1, 2
+COMPLETE_SYNC, COMPLETE_FLAG, USE_GRAPH, GRAPH_CHAIN = 0, 1, 2, 4
 
 # Table 1 values of the command codes recorded in the device log.
 CODE_NOP, CODE_EXIT, CODE_WORK = 4, 8, 16
@@ -494,6 +494,10 @@ def launch_burst(items, elems_per_wg=16384, threads=256, graph=True, reps=1, dev
 
 
 def launch_lanes(items, streams=4, threads_host=8, threads=256, mode=0, device=0):
+    """The lanes workload as ordinary launches (lkb_launch_lanes): mode 0 one launch per
+    item, USE_GRAPH a single-node graph relaunched per item, GRAPH_CHAIN one captured
+    chain per lane (no per-item latency: lat is all zeros).  Returns (results, lat_us,
+    elapsed_s)."""
     items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
     lanes, per = items.shape
     res = np.zeros((lanes, per), np.int64)

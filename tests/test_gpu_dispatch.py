@@ -676,13 +676,13 @@ def test_per_launch_baseline_matches_oracle(mode):
 
 
 def test_launch_lanes_baseline_matches_oracle():
-    say("baseline launch lanes: 16 lanes x 20 SAXPY items, 4 streams, plain and graph")
+    say("baseline launch lanes: 16 lanes x 20 SAXPY items, 4 streams, plain, graph and graph chain")
     rng = np.random.default_rng(6)
     lanes, per, n = 16, 20, 3000
     X = rng.standard_normal((lanes, n)).astype(np.float32)
     Y0 = rng.standard_normal((lanes, n)).astype(np.float32)
     A = rng.uniform(-2, 2, (lanes, per)).astype(np.float32)
-    for mode in (0, lk.USE_GRAPH):
+    for mode in (0, lk.USE_GRAPH, lk.GRAPH_CHAIN):
         x, y = to_dev(X), to_dev(Y0)
         li = np.arange(lanes, dtype=np.uint64)[:, None]
         items = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * n * 4, addr(y) + li * n * 4, alpha=A)
