@@ -434,14 +434,30 @@ def bench_isolation(args):
         ncl = ctx.info()["n_clusters"]
         assert ncl == 8, f"expected 8 XCD clusters, got {ncl}"
         ctx.run_isolation(0, crit[:200], args.period_us * 1e-6, [], bg[:0])  # warm-up, untimed
+        wall = float(ctx.info()["wall_clock_hz"])
+        # one XCD's copy ceiling: the same 256 MiB copy on cluster 1 with every other
+        # cluster idle, timed on the device wall clock (first pickup to last completion)
+        spans = []
+        for rep in range(6):
+            t = ctx.submit(1, lk.OP_COPY_F32, x=int(bg["inp"][0]), y=int(bg["out"][0]), n=elems)
+            ci = ctx.wait_info(1, t, timeout=30.0)
+            if rep:
+                spans.append((ci["t_done_max"] - ci["t_pick_min"]) / wall)
+        xcd_gbps = 2 * elems * 4 / float(np.median(spans)) / 1e9
+        out["xcd_copy_gbps"] = round(xcd_gbps, 1)
+        log(f"isolation: one XCD copies at {xcd_gbps:,.0f} GB/s")
         for name, bgc in (("off", []), ("on", list(range(1, 8)))):
             log(f"isolation: interference {name}")
             r = ctx.run_isolation(0, crit, args.period_us * 1e-6, bgc, bg[:len(bgc)])
-            wall = 1e8
             span = (r["info"]["t_done_max"] - r["info"]["t_pick_min"]) / wall * 1e6
             v = {"latency_us": lat_summary(r["lat_us"]), "device_span_us": lat_summary(span),
                  "release_lateness_us": lat_summary(r["late_us"]),
                  "submit_to_done_us": lat_summary(r["lat_us"] - r["late_us"]), "elapsed_s": round(r["elapsed_s"], 3)}
+            # the critical item's own bandwidth (8n + 8 bytes over its device span) against
+            # one XCD's copy ceiling
+            crit_gbps = (8 * xh.size + 8) / (float(np.median(span)) * 1e-6) / 1e9
+            v["critical_gbps_p50"] = round(crit_gbps, 1)
+            v["critical_frac_of_xcd_copy"] = round(crit_gbps / xcd_gbps, 3)
             if bgc:
                 copied = float(r["bg_done"].sum()) * 2 * (elems * 4)
                 v["interference_copy_gbps"] = round(copied / r["elapsed_s"] / 1e9, 1)
