@@ -405,8 +405,8 @@ def bench_replay(args):
 def bench_isolation(args):
     """Cluster isolation: 8 clusters = 8 XCDs; cluster 0 gets a critical int32 affine +
     int64 sum item over 262,144 elements every period, released by a host busy-wait, while
-    clusters 1-7 copy private fp32 buffers back-to-back (interference on) or idle-poll
-    (interference off)."""
+    clusters 1-7 copy private fp32 buffers back-to-back (interference on), idle-poll
+    (interference off) or do not exist (absent: a context whose workers are all on XCD 0)."""
     import torch
     from paper_2310_01212_amd import lk, workloads
 
@@ -446,9 +446,8 @@ def bench_isolation(args):
         xcd_gbps = 2 * elems * 4 / float(np.median(spans)) / 1e9
         out["xcd_copy_gbps"] = round(xcd_gbps, 1)
         log(f"isolation: one XCD copies at {xcd_gbps:,.0f} GB/s")
-        for name, bgc in (("off", []), ("on", list(range(1, 8)))):
-            log(f"isolation: interference {name}")
-            r = ctx.run_isolation(0, crit, args.period_us * 1e-6, bgc, bg[:len(bgc)])
+
+        def summarize(r, bgc):
             span = (r["info"]["t_done_max"] - r["info"]["t_pick_min"]) / wall * 1e6
             v = {"latency_us": lat_summary(r["lat_us"]), "device_span_us": lat_summary(span),
                  "release_lateness_us": lat_summary(r["late_us"]),
@@ -464,9 +463,20 @@ def bench_isolation(args):
                 v["interference_items"] = int(r["bg_done"].sum())
             # sanity check of the sums of 20 sampled periods
             idx = np.linspace(0, P - 1, 20).astype(int)
-            bad = sum(int(r["results"][k] != int_sum_check(xh, int(AB[k, 0]), int(AB[k, 1]))) for k in idx)
-            v["sampled_sum_mismatches"] = bad
-            out[name] = v
+            v["sampled_sum_mismatches"] = sum(int(r["results"][k] != int_sum_check(xh, int(AB[k, 0]), int(AB[k, 1])))
+                                              for k in idx)
+            return v
+
+        for name, bgc in (("off", []), ("on", list(range(1, 8)))):
+            log(f"isolation: interference {name}")
+            r = ctx.run_isolation(0, crit, args.period_us * 1e-6, bgc, bg[:len(bgc)])
+            out[name] = summarize(r, bgc)
+    # absent: only XCD 0's workers exist (the context's XCD mask), nothing else runs
+    log("isolation: other clusters absent")
+    with lk.Context(n_workers=0, xcd_mask=0x1, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=600000) as ca:
+        assert ca.info()["n_clusters"] == 1
+        ca.run_isolation(0, crit[:200], args.period_us * 1e-6, [], bg[:0])  # warm-up, untimed
+        out["absent"] = summarize(ca.run_isolation(0, crit, args.period_us * 1e-6, [], bg[:0]), [])
     out["value"] = out["on"]["latency_us"]["max"]
     out["ms_per_step"] = round(out["on"]["elapsed_s"] * 1e3 / P, 4)
     print(json.dumps(out), flush=True)

@@ -183,7 +183,15 @@ typedef struct lk_config {
                                   has posted the next command and then costs a whole PCIe
                                   round trip; the pause never delays a command that arrives
                                   later than it */
-  uint32_t reserved;
+  uint32_t xcd_mask;           /* bit j set: workers only on XCD j (XCC_ID j), so the other
+                                  XCDs stay free for other work (Sec. 1: work allocated on a
+                                  subset of the cores); 0 = every XCD.  A context with a mask
+                                  dispatches one workgroup per CU of the whole GPU, those on
+                                  other XCDs leave at boot, so it needs every CU free when it
+                                  starts and counts as holding all of them until disposed.
+                                  n_workers = 0 then means workers_per_cu on every CU of
+                                  the named XCDs; a bit beyond the device's XCDs is
+                                  LK_EINVAL */
 } lk_config;
 
 #define LK_POLL_DELAY_ADAPTIVE (-1)
@@ -308,7 +316,7 @@ typedef struct lk_info {
   uint32_t workers_per_cu;     /* as configured */
   uint32_t max_workers_on_a_cu; /* most workers found on one physical CU at boot */
   uint32_t pin_capacity;       /* bytes of x one worker can keep pinned (LK_DF_PIN_INPUT) */
-  uint32_t reserved;
+  uint32_t xcd_mask;           /* XCDs holding workers (every XCD unless the config named some) */
 } lk_info;
 
 LK_API int lk_get_info(lk_ctx *ctx, lk_info *info);

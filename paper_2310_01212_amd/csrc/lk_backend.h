@@ -18,6 +18,7 @@ namespace lkbe {
 
 struct DeviceInfo {
   uint32_t cu_count;    // compute units
+  uint32_t xcc_count;   // XCDs (accelerator complexes), each with its own L2
   uint32_t lds_per_cu;  // bytes of LDS per CU
   uint64_t wall_hz;     // device wall-clock rate
 };
@@ -37,9 +38,9 @@ int device_to_host(void *dst, const void *src, size_t bytes, std::string *err);
 class Dispatch {
  public:
   virtual ~Dispatch() = default;
-  // One launch of n_workers workgroups of `threads`, each with dyn_lds bytes of LDS on
-  // top of the kernel's own.
-  virtual bool start(const lkw_params &p, uint32_t n_workers, uint32_t threads, uint32_t dyn_lds,
+  // One launch of n_groups workgroups of `threads`, each with dyn_lds bytes of LDS on
+  // top of the kernel's own (p.n_workers of them become workers; any others leave at boot).
+  virtual bool start(const lkw_params &p, uint32_t n_groups, uint32_t threads, uint32_t dyn_lds,
                      std::string *err) = 0;
   // True once the launch has ended (or if there was none).
   virtual bool finished() const = 0;

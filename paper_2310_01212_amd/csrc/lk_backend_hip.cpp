@@ -24,8 +24,8 @@ int hip_error(hipError_t e, const char *what, std::string *err) {
 class HsaDispatch final : public Dispatch {
  public:
   lkq::Queue q;
-  bool start(const lkw_params &p, uint32_t n_workers, uint32_t threads, uint32_t dyn_lds, std::string *err) override {
-    return q.dispatch(p, n_workers, threads, dyn_lds, *err);
+  bool start(const lkw_params &p, uint32_t n_groups, uint32_t threads, uint32_t dyn_lds, std::string *err) override {
+    return q.dispatch(p, n_groups, threads, dyn_lds, *err);
   }
   bool finished() const override { return q.finished(); }
   double kernel_ms() const override { return q.kernel_ms(); }
@@ -59,6 +59,13 @@ int device_info(int device, DeviceInfo *out, std::string *err) {
     return LK_ENODEV;
   }
   out->cu_count = static_cast<uint32_t>(prop.multiProcessorCount);
+  int nxcc = 0;
+  if ((e = hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, device)) != hipSuccess || nxcc <= 0 ||
+      nxcc > 32 || out->cu_count % static_cast<uint32_t>(nxcc) != 0) {
+    *err = "unexpected XCD count " + std::to_string(nxcc) + " for " + std::to_string(out->cu_count) + " CUs";
+    return LK_ENODEV;
+  }
+  out->xcc_count = static_cast<uint32_t>(nxcc);
   out->lds_per_cu = static_cast<uint32_t>(prop.maxSharedMemoryPerMultiProcessor);
   out->wall_hz = 100000000ull;
   int wc_khz = 0;

@@ -103,6 +103,8 @@ struct lk_ctx {
   uint32_t per_cu = 1, max_on_a_cu = 0;
   uint32_t cus_held = 0;  // CUs counted for this context in the process registry
   uint32_t pin_bytes = 0; // dynamic LDS of each worker: the largest x slice it can pin
+  uint32_t xcd_mask = 0;  // XCDs that hold workers (every XCD when the config names none)
+  bool masked = false;    // xcd_mask leaves some XCD out: the dispatch spans every CU
   uint32_t log_cap = 0;
   uint64_t wall_hz = 100000000ull;
   State state = RUNNING;
@@ -308,15 +310,27 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   c->device = cfg.device;
   c->cu_count = dev.cu_count;
   c->per_cu = cfg.workers_per_cu ? cfg.workers_per_cu : 1;
-  c->n_workers = cfg.n_workers ? cfg.n_workers : c->cu_count * c->per_cu;
+  // XCD restriction: workers only on the named XCDs (equal CU counts per XCD).
+  const uint32_t nx = dev.xcc_count ? dev.xcc_count : 1;
+  const uint32_t all_xcd = nx >= 32 ? ~0u : (1u << nx) - 1u;
+  if (cfg.xcd_mask & ~all_xcd) {
+    delete c;
+    return fail(LK_EINVAL, "xcd_mask 0x%x names an XCD beyond the device's %u", cfg.xcd_mask, nx);
+  }
+  c->xcd_mask = cfg.xcd_mask ? cfg.xcd_mask : all_xcd;
+  c->masked = c->xcd_mask != all_xcd;
+  const uint32_t cus_usable =
+      c->masked ? c->cu_count / nx * static_cast<uint32_t>(__builtin_popcount(c->xcd_mask)) : c->cu_count;
+  c->n_workers = cfg.n_workers ? cfg.n_workers : cus_usable * c->per_cu;
   c->depth = cfg.queue_depth ? cfg.queue_depth : 1;
   c->threads = cfg.threads_per_worker ? cfg.threads_per_worker : 256;
   c->log_cap = cfg.log_capacity;
-  if (c->n_workers > c->cu_count * c->per_cu || c->n_workers > LK_MAX_WORKERS) {
-    const uint32_t cap = std::min(c->cu_count * c->per_cu, LK_MAX_WORKERS);
+  if (c->n_workers > cus_usable * c->per_cu || c->n_workers > LK_MAX_WORKERS) {
+    const uint32_t cap = std::min(cus_usable * c->per_cu, LK_MAX_WORKERS);
+    const bool masked = c->masked;
     delete c;
-    return fail(LK_EINVAL, "n_workers %u exceeds %u (%u per CU)", cfg.n_workers, cap,
-                cfg.workers_per_cu ? cfg.workers_per_cu : 1);
+    return fail(LK_EINVAL, "n_workers %u exceeds %u (%u per CU%s)", cfg.n_workers, cap,
+                cfg.workers_per_cu ? cfg.workers_per_cu : 1, masked ? " of the masked XCDs" : "");
   }
   // Dynamic LDS per worker: one worker per CU takes 96 KiB, so a second never fits;
   // k workers per CU take an even share of the CU's LDS less 2 KiB (room for the static
@@ -325,9 +339,10 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   const uint32_t lds_pad = c->per_cu == 1 ? LKW_LDS_PAD_BYTES : (lds_cu / c->per_cu - 2048u) / 256u * 256u;
   c->pin_bytes = lds_pad;
   {
-    // Until the hardware ids are known every worker may sit on a CU of its own.
+    // Until the hardware ids are known every worker may sit on a CU of its own; a masked
+    // context dispatches over every CU.
     uint32_t in_use = 0;
-    c->cus_held = std::min(c->n_workers, c->cu_count);
+    c->cus_held = c->masked ? c->cu_count : std::min(c->n_workers, c->cu_count);
     if (!reserve_cus(cfg.device, c->cus_held, c->cu_count, &in_use)) {
       const uint32_t want = c->cus_held, cus = c->cu_count;
       delete c;
@@ -402,8 +417,12 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
   // About a host round trip (1.6 us): a look-ahead read waits at most that long, so it
   // is issued only when the previous item ran longer and the read hides under the item.
   p.la_ticks = static_cast<uint32_t>(c->wall_hz / 625000ull);
+  p.xcc_mask = c->masked ? c->xcd_mask : ~0u;
 
-  if (!c->wq->start(p, c->n_workers, c->threads, lds_pad, &err))
+  // A masked context dispatches one workgroup per CU slot of the whole GPU; the ones on
+  // other XCDs leave at once (and so do any beyond n_workers).
+  const uint32_t grid = c->masked ? c->cu_count * c->per_cu : c->n_workers;
+  if (!c->wq->start(p, grid, c->threads, lds_pad, &err))
     return bail(fail(LK_EHIP, "persistent worker dispatch: %s", err.c_str()));
   c->kernel_launched = true;
 
@@ -454,6 +473,17 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
     run = same ? run + 1 : 1;
     c->max_on_a_cu = std::max(c->max_on_a_cu, run);
   }
+  for (const WorkerInfo &w : ws)
+    if (!((c->xcd_mask >> w.xcc) & 1u)) {  // cannot happen unless XCC_ID disagrees with the mask's numbering
+      for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
+      if (!join_kernel(c, 2.0 + idle_ms / 1000.0)) {
+        c->state = POISONED;
+        *out = c;
+        return fail(LK_ENODEV, "a worker booted on XCD %u outside xcd_mask 0x%x; kernel did not end", w.xcc,
+                    c->xcd_mask);
+      }
+      return bail(fail(LK_ENODEV, "a worker booted on XCD %u outside xcd_mask 0x%x", w.xcc, c->xcd_mask));
+    }
   if (!(cfg.flags & LK_F_ANY_PLACEMENT) && c->max_on_a_cu > c->per_cu) {
     for (uint32_t m = 0; m < c->n_workers; ++m) post_cmd(c, m, 1, LKW_TO_EXIT, 0, 0, 0, 0, 0, 0, 0.f, 0);
     if (!join_kernel(c, 2.0 + idle_ms / 1000.0)) {
@@ -825,6 +855,7 @@ int lk_get_info(lk_ctx *c, lk_info *info) {
   info->workers_per_cu = c->per_cu;
   info->max_workers_on_a_cu = c->max_on_a_cu;
   info->pin_capacity = c->pin_bytes;
+  info->xcd_mask = c->xcd_mask;
   return LK_OK;
 }
 

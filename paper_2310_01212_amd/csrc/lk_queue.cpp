@@ -164,7 +164,7 @@ bool Queue::open(int hip_device, std::string &err) {
   return true;
 }
 
-bool Queue::dispatch(const lkw_params &p, uint32_t n_workers, uint32_t threads, uint32_t dyn_lds, std::string &err) {
+bool Queue::dispatch(const lkw_params &p, uint32_t n_groups, uint32_t threads, uint32_t dyn_lds, std::string &err) {
   if (kernarg_size < sizeof(lkw_params)) {
     err = "worker kernarg segment smaller than lkw_params";
     return false;
@@ -180,7 +180,7 @@ bool Queue::dispatch(const lkw_params &p, uint32_t n_workers, uint32_t threads, 
   pkt->workgroup_size_x = static_cast<uint16_t>(threads);
   pkt->workgroup_size_y = 1;
   pkt->workgroup_size_z = 1;
-  pkt->grid_size_x = n_workers * threads;
+  pkt->grid_size_x = n_groups * threads;
   pkt->grid_size_y = 1;
   pkt->grid_size_z = 1;
   pkt->private_segment_size = private_size;

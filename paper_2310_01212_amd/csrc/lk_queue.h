@@ -29,9 +29,9 @@ struct Queue {
 
   // Find the HSA agent of a HIP device, load lk_worker.hsaco, create the queue.
   bool open(int hip_device, std::string &err);
-  // Write the single dispatch packet: n_workers workgroups of `threads`, plus dyn_lds
+  // Write the single dispatch packet: n_groups workgroups of `threads`, plus dyn_lds
   // bytes of LDS per workgroup on top of the worker's static LDS.
-  bool dispatch(const lkw_params &p, uint32_t n_workers, uint32_t threads, uint32_t dyn_lds, std::string &err);
+  bool dispatch(const lkw_params &p, uint32_t n_groups, uint32_t threads, uint32_t dyn_lds, std::string &err);
   // True once the dispatch has completed (or if nothing was dispatched).
   bool finished() const;
   // Duration of the completed dispatch from the packet processor's timestamps.

@@ -122,6 +122,8 @@ typedef struct lkw_params {
   uint32_t b2b_ticks;    /* a command found this soon after a completion counts as back-to-back */
   uint32_t lds_bytes;    /* dynamic LDS of each worker (the pinned-input buffer) */
   uint32_t la_ticks;     /* look-ahead only after an item that ran at least this long */
+  uint32_t xcc_mask;     /* a workgroup whose XCC_ID bit is clear leaves at boot */
+  uint32_t pad;
 } lkw_params;
 
 /* Descriptor flags, carried in bits 32..47 of LKW_W_B (same values as LK_DF_*). */

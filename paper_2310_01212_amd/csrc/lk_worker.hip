@@ -318,12 +318,14 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   __shared__ int64_t s_red[lkops::kMaxWaves];
   const uint32_t tid = threadIdx.x;
 
-  // Boot: claim a mailbox, record the physical placement, announce INIT (Table 1).
+  // Boot: claim a mailbox (only on an XCD the context uses), record the physical
+  // placement, announce INIT (Table 1).
   if (tid == 0) {
-    const uint32_t m = atomicAdd(p.claim, 1u);
+    const uint32_t xcc = read_xcc_id();
+    const uint32_t m = ((p.xcc_mask >> (xcc & 31u)) & 1u) ? atomicAdd(p.claim, 1u) : ~0u;
     s_mb = m;
     if (m < p.n_workers) {
-      const uint32_t hw = read_hw_id(), xcc = read_xcc_id();
+      const uint32_t hw = read_hw_id();
       lkw_worker *wr = p.workers + m;
       st_sys_u32(&wr->hwid, hw);
       st_sys_u32(&wr->xcc, xcc);

@@ -48,7 +48,7 @@ class Config(ctypes.Structure):
                 ("poll_sleep", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("log_capacity", ctypes.c_uint32), ("idle_timeout_ms", ctypes.c_uint32),
                 ("workers_per_cu", ctypes.c_uint32), ("init_timeout_ns", ctypes.c_int64),
-                ("first_poll_delay", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+                ("first_poll_delay", ctypes.c_int32), ("xcd_mask", ctypes.c_uint32)]
 
 
 class Desc(ctypes.Structure):
@@ -73,7 +73,7 @@ class Info(ctypes.Structure):
                 ("dispose_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("device_span_ms", ctypes.c_double), ("workers_per_cu", ctypes.c_uint32),
                 ("max_workers_on_a_cu", ctypes.c_uint32), ("pin_capacity", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("xcd_mask", ctypes.c_uint32)]
 
 
 class LogEntry(ctypes.Structure):
@@ -235,7 +235,7 @@ class Context:
     def __init__(self, n_workers=0, threads=256, depth=1, clusters=CLUSTERS_PER_WORKER,
                  cluster_of_worker=None, poll_sleep=0, flags=0, log_capacity=0,
                  idle_timeout_ms=10000, init_timeout_s=5.0, device=0, workers_per_cu=1,
-                 first_poll_delay=POLL_DELAY_ADAPTIVE):
+                 first_poll_delay=POLL_DELAY_ADAPTIVE, xcd_mask=0):
         L = lib()
         cfg = Config()
         L.lk_config_default(ctypes.byref(cfg))
@@ -250,6 +250,7 @@ class Context:
         cfg.init_timeout_ns = int(init_timeout_s * 1e9)
         cfg.workers_per_cu = workers_per_cu
         cfg.first_poll_delay = first_poll_delay
+        cfg.xcd_mask = xcd_mask
         self._cow = None
         if cluster_of_worker is not None:
             cow = np.ascontiguousarray(cluster_of_worker, dtype=np.uint32)

@@ -470,6 +470,52 @@ static void cu_reservation() {
   printf("OK %s\n", g_case);
 }
 
+// Workers restricted to XCDs 0 and 2 (2 fake CUs each): 4 workers, all on those XCDs,
+// two XCD clusters computing exactly; the masked context holds every CU; masks beyond
+// the device and worker counts beyond the masked CUs are refused.
+static void xcd_mask() {
+  g_case = "xcd_mask";
+  lk_config cfg;
+  lk_config_default(&cfg);
+  cfg.xcd_mask = 0x5;
+  cfg.cluster_policy = LK_CLUSTERS_PER_XCD;
+  cfg.idle_timeout_ms = 20000;
+  lk_ctx *c = nullptr;
+  CHECK(lk_init(&cfg, &c) == LK_OK && c);
+  lk_info info{};
+  CHECK(lk_get_info(c, &info) == LK_OK);
+  CHECK(info.n_workers == 4 && info.n_clusters == 2 && info.xcd_mask == 0x5 && info.xcd_count == 2);
+  for (uint32_t w = 0; w < 4; ++w) {
+    uint32_t xcc = 9, se, sh, cu;
+    CHECK(lk_topology(c, w, &xcc, &se, &sh, &cu) == LK_OK && (xcc == 0 || xcc == 2));
+  }
+  const uint64_t n = 5000;
+  std::vector<int32_t> x(n), y(n), yr(n);
+  for (uint64_t i = 0; i < n; ++i) x[i] = static_cast<int32_t>(i * 2654435761u);
+  for (uint32_t cl = 0; cl < 2; ++cl) {
+    lk_desc d = desc(LK_OP_AFFINE_SUM_I32, n, 3 + cl, -7);
+    uint64_t t;
+    int64_t s = 0, sr = 0;
+    CHECK(lk_submit(c, cl, &d, x.data(), y.data(), &t) == LK_OK);
+    CHECK(lk_wait(c, cl, t, 5000000000ll, &s) == LK_OK);
+    affine_ref(x.data(), n, 3 + cl, -7, yr.data(), &sr);
+    CHECK(s == sr && y == yr);
+  }
+  lk_config other;
+  lk_config_default(&other);
+  other.n_workers = 1;
+  lk_ctx *b = nullptr;
+  CHECK(lk_init(&other, &b) == LK_ENODEV && b == nullptr);  // the masked context holds every CU
+  CHECK(lk_dispose(c) == LK_OK);
+  lk_free(c);
+  cfg.xcd_mask = 0x100;  // 8 fake XCDs
+  CHECK(lk_init(&cfg, &c) == LK_EINVAL);
+  cfg.xcd_mask = 0x1;
+  cfg.n_workers = 3;  // XCD 0 has 2 CUs
+  CHECK(lk_init(&cfg, &c) == LK_EINVAL);
+  printf("OK %s\n", g_case);
+}
+
 int main() {
   single_worker_1000();
   concurrent_clusters();
@@ -482,6 +528,7 @@ int main() {
   dispose_in_flight();
   dispose_hung_worker();
   cu_reservation();
+  xcd_mask();
   printf("ALL OK\n");
   return 0;
 }

@@ -96,13 +96,13 @@ int64_t run_slice(const Slice &s) {
 }
 
 void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
-  const uint32_t m = __atomic_fetch_add(p.claim, 1u, __ATOMIC_RELAXED);
+  // Distinct fake placement per workgroup: XCC = wg % 8, CU/SH/SE from the rest.
+  const uint32_t xcc = wg % 8, cu = (wg / 8) % 16, sh = (wg / 128) % 2, se = (wg / 256) % 4;
+  const uint32_t m = ((p.xcc_mask >> xcc) & 1u) ? __atomic_fetch_add(p.claim, 1u, __ATOMIC_RELAXED) : ~0u;
   if (m >= p.n_workers) {
     running->fetch_sub(1, std::memory_order_release);
     return;
   }
-  // Distinct fake placement per workgroup: XCC = wg % 8, CU/SH/SE from the rest.
-  const uint32_t xcc = wg % 8, cu = (wg / 8) % 16, sh = (wg / 128) % 2, se = (wg / 256) % 4;
   const uint32_t hw = (cu << 8) | (sh << 12) | (se << 13);
   lkw_worker *wr = p.workers + m;
   __atomic_store_n(&wr->hwid, hw, __ATOMIC_RELAXED);
@@ -236,10 +236,10 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
 
 class FakeDispatch final : public lkbe::Dispatch {
  public:
-  bool start(const lkw_params &p, uint32_t n_workers, uint32_t, uint32_t, std::string *) override {
+  bool start(const lkw_params &p, uint32_t n_groups, uint32_t, uint32_t, std::string *) override {
     started_ = clk::now();
-    running_.store(n_workers, std::memory_order_relaxed);
-    for (uint32_t wg = 0; wg < n_workers; ++wg) th_.emplace_back(worker, p, wg, &running_);
+    running_.store(n_groups, std::memory_order_relaxed);
+    for (uint32_t wg = 0; wg < n_groups; ++wg) th_.emplace_back(worker, p, wg, &running_);
     launched_ = true;
     return true;
   }
@@ -271,6 +271,11 @@ int device_info(int device, DeviceInfo *out, std::string *err) {
   }
   const char *e = getenv("LKFAKE_CUS");
   out->cu_count = e ? static_cast<uint32_t>(atoi(e)) : 16u;
+  if (out->cu_count == 0 || out->cu_count % 8 != 0) {
+    *err = "fake device: the CU count must be a multiple of 8 (8 fake XCDs)";
+    return LK_ENODEV;
+  }
+  out->xcc_count = 8;
   out->lds_per_cu = 160u * 1024u;
   out->wall_hz = 100000000ull;
   return LK_OK;

@@ -42,18 +42,20 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_c_headers(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text('#include "lk.h"\n#include "lk_bench.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lk_desc),'
                    ' sizeof(lk_config), sizeof(lk_completion), sizeof(lk_info), sizeof(lk_log_entry), sizeof(lkb_item),'
                    ' offsetof(lk_config, init_timeout_ns), offsetof(lk_desc, aux), sizeof(lk_tile),'
                    ' offsetof(lk_config, workers_per_cu), offsetof(lk_info, workers_per_cu),'
-                   ' offsetof(lk_config, first_poll_delay)); return 0;}\n')
+                   ' offsetof(lk_config, first_poll_delay), offsetof(lk_config, xcd_mask),'
+                   ' offsetof(lk_info, xcd_mask)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(lk.Desc), ctypes.sizeof(lk.Config), ctypes.sizeof(lk.Completion),
             ctypes.sizeof(lk.Info), ctypes.sizeof(lk.LogEntry), lk.ITEM_DTYPE.itemsize,
             lk.Config.init_timeout_ns.offset, lk.Desc.aux.offset, lk.TILE_DTYPE.itemsize,
-            lk.Config.workers_per_cu.offset, lk.Info.workers_per_cu.offset, lk.Config.first_poll_delay.offset]
+            lk.Config.workers_per_cu.offset, lk.Info.workers_per_cu.offset, lk.Config.first_poll_delay.offset,
+            lk.Config.xcd_mask.offset, lk.Info.xcd_mask.offset]
     assert got == want
     assert lk.LOG_DTYPE.itemsize == ctypes.sizeof(lk.LogEntry)
     assert lk.COMPLETION_DTYPE.itemsize == ctypes.sizeof(lk.Completion)

@@ -16,7 +16,7 @@ SOURCES = [os.path.join(ROOT, "tests", "fake", "fake_device_test.cpp"),
            os.path.join(ROOT, "tests", "fake", "lk_backend_fake.cpp"),
            os.path.join(CSRC, "lk_host.cpp"), os.path.join(CSRC, "lk_serve.cpp")]
 SCENARIOS = ["single_worker_1000", "concurrent_clusters", "error_paths", "pinned_input", "cluster_split", "batch_tiles",
-             "serving", "idle_watchdog", "dispose_in_flight", "dispose_hung_worker", "cu_reservation"]
+             "serving", "idle_watchdog", "dispose_in_flight", "dispose_hung_worker", "cu_reservation", "xcd_mask"]
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")

@@ -485,6 +485,42 @@ def test_clusters_per_xcd_split_items_and_placement():
 
 
 # ------------------------------------------------------------------ I4 visibility and coexistence
+def test_xcd_mask_places_workers_only_on_the_named_xcds():
+    """Workers restricted to XCD 0, then to XCDs 5 and 7: worker counts, placement from the
+    hardware ids (at boot and in every log entry), XCD clusters computing exactly; masks
+    beyond the device and too many workers for the masked CUs are refused."""
+    rng = np.random.default_rng(29)
+    n = 262144 + 1000
+    X = rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32)
+    AB = rng.integers(-2 ** 31, 2 ** 31, (4, 2), dtype=np.int64).astype(np.int32)
+    x = to_dev(X)
+    for mask, xcds in ((0x1, [0]), (0xA0, [5, 7])):
+        say(f"xcd_mask {mask:#x}: workers on XCDs {xcds}")
+        with lk.Context(n_workers=0, xcd_mask=mask, clusters=lk.CLUSTERS_PER_XCD, log_capacity=16,
+                        idle_timeout_ms=20000) as ctx:
+            info = ctx.info()
+            per_xcd = info["cu_count"] // 8
+            assert info["n_workers"] == per_xcd * len(xcds) and info["xcd_mask"] == mask
+            assert info["n_clusters"] == len(xcds) and info["xcd_count"] == len(xcds)
+            for cl, xcd in enumerate(xcds):
+                assert {ctx.topology(w)[0] for w in ctx.members(cl)} == {xcd}
+            outs = []
+            for cl in range(len(xcds)):
+                y = sentinel_i32((n,))
+                torch.cuda.synchronize()
+                t = ctx.submit(cl, lk.OP_AFFINE_SUM_I32, x=x, y=y, a=int(AB[cl, 0]), b=int(AB[cl, 1]))
+                outs.append((cl, y, ctx.wait(cl, t)))
+        for cl, y, s_got in outs:
+            yr, sr = oracle.affine_sum_i32(X, int(AB[cl, 0]), int(AB[cl, 1]))
+            assert s_got == sr and np.array_equal(y.cpu().numpy(), yr), (mask, cl)
+        for w in range(info["n_workers"]):
+            assert set(np.unique(ctx.log(w)["xcc"]).tolist()) <= set(xcds)
+    for kw in (dict(xcd_mask=0x100), dict(xcd_mask=0x1, n_workers=33)):
+        with pytest.raises(lk.LKError) as e:
+            lk.Context(**kw)
+        assert e.value.code == lk.EINVAL
+
+
 def test_completion_implies_visibility_on_an_independent_stream():
     rng = np.random.default_rng(11)
     n = 1 << 20
