@@ -841,8 +841,14 @@ def bench_allcu(args):
         with cf.ThreadPoolExecutor(max_workers=cores) as ex:
             list(ex.map(lane_job, range(lanes)))
         el = time.perf_counter() - t0
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
         result["cpu_baseline"] = {"value": round(lanes * per_cpu / el, 1), "unit": "items/s", "cores": cores,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model,
                                   "sample": f"{lanes} mailboxes x {per_cpu} SAXPY items of {n} fp32 "
                                             f"({lanes * per_cpu} items), lanes spread over {cores} threads",
                                   "seconds": round(el, 3)}
