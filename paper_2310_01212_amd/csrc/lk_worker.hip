@@ -4,8 +4,9 @@
  * One workgroup per CU (Sec. 2.3: one block per cluster, pinned at boot; up to four per
  * CU on request), dispatched once for the whole session on an HSA queue of its own (see
  * lk_queue.cpp).  Each workgroup:
- *   1. claims a mailbox, reads its physical placement from the HW_ID / XCC_ID registers
- *      and announces THREAD_INIT (Table 1);
+ *   1. on an XCD the context uses (all of them unless it names some), claims a mailbox,
+ *      reads its physical placement from the HW_ID / XCC_ID registers and announces
+ *      THREAD_INIT (Table 1); on any other XCD it leaves at once;
  *   2. polls its to_GPU command slot: wave 0 reads the whole 64-byte slot with lanes 0..7,
  *      with s_sleep backoff and an idle watchdog on the device wall clock (with a ring
  *      deeper than one slot, a command already posted is usually found by the look-ahead
