@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "lk.h"
+#include "lk_affinity.hpp"
 #include "lk_bench.h"
 #include "lk_device.h"
 
@@ -45,29 +46,8 @@ int bfail(int code, const char *fmt, ...) {
 
 inline uint64_t load_acquire(const uint64_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
 
-// CPUs the process may run on, in ascending order (its affinity mask at first use).
-const std::vector<int> &allowed_cpus() {
-  static const std::vector<int> cpus = [] {
-    std::vector<int> v;
-    cpu_set_t set;
-    if (sched_getaffinity(0, sizeof set, &set) == 0)
-      for (int i = 0; i < CPU_SETSIZE; ++i)
-        if (CPU_ISSET(i, &set)) v.push_back(i);
-    return v;
-  }();
-  return cpus;
-}
-
-// Pin the calling thread to the i-th allowed CPU.  Host threads that poll mailboxes then
-// keep their cache lines and are not migrated mid-run.
-void pin_to_allowed_cpu(size_t i) {
-  const std::vector<int> &cpus = allowed_cpus();
-  if (i >= cpus.size()) return;
-  cpu_set_t one;
-  CPU_ZERO(&one);
-  CPU_SET(cpus[i], &one);
-  (void)pthread_setaffinity_np(pthread_self(), sizeof one, &one);
-}
+using lkaff::allowed_cpus;
+using lkaff::pin_to_allowed_cpu;
 
 lk_desc to_desc(const lkb_item &it) {
   lk_desc d{};

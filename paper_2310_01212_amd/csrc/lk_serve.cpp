@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "lk.h"
+#include "lk_affinity.hpp"
 #include "lk_arena.hpp"
 
 namespace {
@@ -76,7 +77,10 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
   clk::time_point t0;
   auto us_since = [&](clk::time_point t) { return std::chrono::duration<double, std::micro>(t - t0).count(); };
 
+  // Scheduler threads on distinct CPUs when there are enough (the caller's thread keeps one).
+  const bool pin = T < lkaff::allowed_cpus().size();
   auto shard = [&](uint32_t s) {
+    if (pin) lkaff::pin_to_allowed_cpu(s);
     Arena arena(cfg->arena + s * slice, slice);
     std::vector<uint32_t> workers;
     for (uint32_t w = s; w < info.n_workers; w += T) workers.push_back(w);
