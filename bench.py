@@ -65,14 +65,14 @@ TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
 WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h", "lk_device.h", "lk_common.h"]
 
 
-def worker_source_digest():
+def worker_source_digest(csrc=os.path.join(ROOT, "paper_2310_01212_amd", "csrc")):
     """First 16 hex digits of the sha256 of the worker's sources with comments removed and
     whitespace collapsed, so that a counter summary stays valid across comment edits."""
     import hashlib
     import re
     h = hashlib.sha256()
     for f in WORKER_SOURCES:
-        with open(os.path.join(ROOT, "paper_2310_01212_amd", "csrc", f)) as fh:
+        with open(os.path.join(csrc, f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)

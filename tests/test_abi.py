@@ -209,6 +209,22 @@ def test_committed_traffic_profiles_match_the_worker_sources():
         assert 8 * 16384 <= tr["bytes_per_item"] <= 12 * 16384
 
 
+def test_worker_digest_ignores_comments_but_not_code(tmp_path):
+    import shutil
+    import bench
+    src = os.path.join(ROOT, "paper_2310_01212_amd", "csrc")
+    for f in bench.WORKER_SOURCES:
+        shutil.copy(os.path.join(src, f), tmp_path / f)
+    base = bench.worker_source_digest(str(tmp_path))
+    assert base == bench.worker_source_digest()
+    w = tmp_path / "lk_worker.hip"
+    text = w.read_text()
+    w.write_text("// a new comment line\n/* and a block\n comment */\n" + text.replace("\n", "\n\n", 3))
+    assert bench.worker_source_digest(str(tmp_path)) == base
+    w.write_text(text.replace("uint32_t pre = 8;", "uint32_t pre = 9;"))
+    assert bench.worker_source_digest(str(tmp_path)) != base
+
+
 def test_make_items_carries_descriptor_flags():
     it = lk.make_items(lk.OP_SAXPY_F32, 64, [0x1000, 0x2000], 0x3000, alpha=1.0, flags=[lk.DF_PIN_INPUT, 0])
     assert it["flags"].tolist() == [lk.DF_PIN_INPUT, 0] and it["reserved"].tolist() == [0, 0]
