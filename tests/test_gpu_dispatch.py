@@ -494,13 +494,14 @@ def test_xcd_mask_places_workers_only_on_the_named_xcds():
     X = rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32)
     AB = rng.integers(-2 ** 31, 2 ** 31, (4, 2), dtype=np.int64).astype(np.int32)
     x = to_dev(X)
-    for mask, xcds in ((0x1, [0]), (0xA0, [5, 7])):
-        say(f"xcd_mask {mask:#x}: workers on XCDs {xcds}")
+    for mask, xcds, per_cu in ((0x1, [0], 1), (0xA0, [5, 7], 1), (0x2, [1], 2)):
+        say(f"xcd_mask {mask:#x}: workers on XCDs {xcds}, {per_cu} per CU")
         with lk.Context(n_workers=0, xcd_mask=mask, clusters=lk.CLUSTERS_PER_XCD, log_capacity=16,
-                        idle_timeout_ms=20000) as ctx:
+                        idle_timeout_ms=20000, workers_per_cu=per_cu, threads=256) as ctx:
             info = ctx.info()
             per_xcd = info["cu_count"] // 8
-            assert info["n_workers"] == per_xcd * len(xcds) and info["xcd_mask"] == mask
+            assert info["n_workers"] == per_xcd * len(xcds) * per_cu and info["xcd_mask"] == mask
+            assert info["max_workers_on_a_cu"] == per_cu
             assert info["n_clusters"] == len(xcds) and info["xcd_count"] == len(xcds)
             for cl, xcd in enumerate(xcds):
                 assert {ctx.topology(w)[0] for w in ctx.members(cl)} == {xcd}
