@@ -3,7 +3,8 @@
  * MI355X (gfx950).
  *
  * The method (paper Sec. 1, Sec. 2.3, Sec. 2.4): one persistent kernel is launched at
- * boot with exactly one workgroup ("worker") per compute unit.  Each worker owns a pair
+ * boot with exactly one workgroup ("worker") per compute unit (up to four per CU on
+ * request, and optionally only on some XCDs: lk_config).  Each worker owns a pair
  * of mailboxes: to_GPU, where the host posts a command, and from_GPU, where the worker
  * reports its status (Sec. 2.4, Fig. 2, Table 1).  A command carries a descriptor of the
  * work plus references to its input and output data (Sec. 1).  Workers are grouped into
@@ -206,9 +207,10 @@ LK_API void lk_config_default(lk_config *cfg);
  * mailboxes in fine-grained host-coherent memory, dispatches the persistent kernel with
  * workers_per_cu workgroups per CU on its own HSA queue and waits until every worker has
  * reported INIT (Table 1) with its physical placement.  On success *out holds a running
- * context.  Errors: LK_EINVAL (bad config), LK_ENODEV (no device, too few CUs, workers not
- * all resident within init_timeout_ns, or more than workers_per_cu of them on one CU),
- * LK_EHIP. */
+ * context.  Errors: LK_EINVAL (bad config, including an xcd_mask bit beyond the device's
+ * XCDs or more workers than the named XCDs' CUs hold), LK_ENODEV (no device, too few free
+ * CUs, workers not all resident within init_timeout_ns, more than workers_per_cu of them
+ * on one CU, or a worker outside xcd_mask), LK_EHIP. */
 LK_API int lk_init(const lk_config *cfg, lk_ctx **out);
 
 /* Trigger phase (Sec. 3): post one work item to every member of `cluster`.
@@ -218,7 +220,8 @@ LK_API int lk_init(const lk_config *cfg, lk_ctx **out);
  * cluster, gives undefined results.  Non-blocking: returns LK_EAGAIN without posting
  * anything if a member's ring is full.  *ticket receives the cluster's sequence number
  * of the item (1, 2, 3, ...).  One thread at a time may submit to a given cluster.
- * Errors: LK_EINVAL, LK_EAGAIN, LK_ESTATE (disposed, or a member's worker has exited). */
+ * Errors: LK_EINVAL (including descriptor flags the item cannot take: LK_DF_PIN_INPUT),
+ * LK_EAGAIN, LK_ESTATE (disposed, or a member's worker has exited). */
 LK_API int lk_submit(lk_ctx *ctx, uint32_t cluster, const lk_desc *desc, const void *in, void *out,
               uint64_t *ticket);
 
