@@ -229,8 +229,10 @@ def _check_tensor(t, op, what):
 
 
 class Context:
-    """A running LightKernel context: persistent workers, workers_per_cu on each CU
-    (lk_init)."""
+    """A running LightKernel context (lk_init): persistent workers, workers_per_cu on each
+    CU of the XCDs named by xcd_mask (0 = every XCD), grouped into clusters; depth ring
+    slots per mailbox; flags F_* (F_NO_LOOKAHEAD, ...).  Use as a context manager or call
+    close() (lk_dispose)."""
 
     def __init__(self, n_workers=0, threads=256, depth=1, clusters=CLUSTERS_PER_WORKER,
                  cluster_of_worker=None, poll_sleep=0, flags=0, log_capacity=0,
