@@ -813,6 +813,25 @@ def bench_allcu(args):
                                           item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
         log(f"serial: persistent p50 {serial['persistent']['p50']} us, launch p50 {serial['launch_sync']['p50']} us")
 
+        # all-CU latency bound: one headline item on one worker alone (device pickup to
+        # status record, from the device log) plus the host<->device echo with every CU's
+        # wave polling; 256 mailboxes at depth 1 cannot beat lanes / (echo + item)
+        with lk.Context(n_workers=1, threads=args.threads_per_worker, log_capacity=512,
+                        idle_timeout_ms=30000) as c1:
+            c1.run_lanes(np.arange(1), step_items(0)[:1, :500], in_flight=1, threads=1)
+        hz = float(c1.info()["wall_clock_hz"])
+        e1 = c1.log(0)[100:]
+        item_alone_us = float(np.median((e1["t_done"] - e1["t_pick"]) / hz * 1e6))
+        floor_all = serial["pingpong_rtt_all_cus"]["p50"] + item_alone_us
+        result["latency_roofline_all_cus"] = {
+            "floor": "all-CU ping-pong RTT p50 + the headline item's device span on one worker alone",
+            "item_alone_us": round(item_alone_us, 3), "floor_us": round(floor_all, 3),
+            "items_per_s_bound": round(lanes / (floor_all * 1e-6), 1),
+            "achieved_items_per_s": round(items_per_s, 1),
+            "frac": round(items_per_s * floor_all * 1e-6 / lanes, 3)}
+        log(f"all-CU latency bound: {lanes / (floor_all * 1e-6):,.0f} items/s "
+            f"(echo {serial['pingpong_rtt_all_cus']['p50']} us + item {item_alone_us:.2f} us)")
+
     # ---------------- streaming-copy probe (HBM roofline reference, known-size kernel)
     nbytes = args.copy_probe_mib << 20
     src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
