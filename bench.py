@@ -61,7 +61,8 @@ def int_sum_check(x, a=None, b=None):
 
 
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
-                 ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md")]
+                 ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md",
+                  "lk_worker_allcu_saxpy_depth4_traffic.md")]
 WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h", "lk_device.h", "lk_common.h"]
 
 
@@ -80,11 +81,11 @@ def worker_source_digest(csrc=os.path.join(ROOT, "paper_2310_01212_amd", "csrc")
     return h.hexdigest()[:16]
 
 
-def traffic_per_item(n, threads_per_worker, pin_input=False):
-    """HBM bytes per item of the worker kernel from a committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration); None when
-    no summary was taken for this item size, workgroup size and pinning, or the worker's
-    sources changed since."""
+def traffic_per_item(n, threads_per_worker, pin_input=False, depth=1):
+    """Memory bytes per item of the worker kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration); None
+    when no summary was taken for this item size, workgroup size, pinning and ring depth,
+    or the worker's sources changed since."""
     import re
     for path in TRAFFIC_FILES:
         if not os.path.exists(path):
@@ -95,7 +96,7 @@ def traffic_per_item(n, threads_per_worker, pin_input=False):
         d = json.loads(m.group(1))
         if (d.get("worker_source_digest") == worker_source_digest() and d.get("n") == n and
                 d.get("threads_per_worker", 256) == threads_per_worker and
-                bool(d.get("pin_input", False)) == bool(pin_input)):
+                bool(d.get("pin_input", False)) == bool(pin_input) and d.get("queue_depth", 1) == depth):
             return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(path, ROOT)}
     return None
 
@@ -583,7 +584,7 @@ def bench_allcu(args):
                           "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
                           "items_per_launch": session_items, "algorithmic_bytes_per_item": hbm_bytes_per_item,
                           "algorithmic_bytes": session_items * hbm_bytes_per_item}
-    tr = traffic_per_item(n, args.threads_per_worker, args.pin_input)
+    tr = traffic_per_item(n, args.threads_per_worker, args.pin_input, args.depth)
     if tr is not None:
         result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
         result["roofline"]["traffic_source"] = tr["source"]

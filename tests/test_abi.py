@@ -200,12 +200,13 @@ def test_bench_quotes_the_paper_tables_as_printed():
 
 
 def test_committed_traffic_profiles_match_the_worker_sources():
-    """The HBM-traffic summaries bench.py quotes were taken with the worker as it is now
-    (plain and pinned-input all-CU workloads, n = 16,384, 1024 threads per worker)."""
+    """The memory-traffic summaries bench.py quotes were taken with the worker as it is now
+    (plain, pinned-input and depth-4 all-CU workloads, n = 16,384, 1024 threads per
+    worker)."""
     import bench
-    for pin in (False, True):
-        tr = bench.traffic_per_item(16384, 1024, pin)
-        assert tr is not None, f"traffic summary for pin_input={pin} is stale or missing"
+    for pin, depth in ((False, 1), (True, 1), (False, 4)):
+        tr = bench.traffic_per_item(16384, 1024, pin, depth)
+        assert tr is not None, f"traffic summary for pin_input={pin}, depth {depth} is stale or missing"
         assert 8 * 16384 <= tr["bytes_per_item"] <= 12 * 16384
 
 
