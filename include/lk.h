@@ -285,6 +285,12 @@ LK_API int lk_wait_info(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int64_t 
 /* Non-blocking completion test: *done = 1 if every member finished `ticket`. */
 LK_API int lk_poll(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, int *done);
 
+/* Non-blocking Wait: if every member has finished `ticket`, releases it exactly as
+ * lk_wait_info does (out may be NULL) and returns LK_OK; otherwise changes nothing and
+ * returns LK_EAGAIN.  One call per check, for host loops that serve many clusters.
+ * Errors as lk_wait_info (LK_ESTATE when a member's worker exited before finishing). */
+LK_API int lk_try_wait(lk_ctx *ctx, uint32_t cluster, uint64_t ticket, lk_completion *out);
+
 /* Hint for a host thread that drives many clusters: start fetching the cache lines it will
  * touch next for `cluster` -- the status records of `ticket` (if it is posted and not yet
  * released; 0 = none) and the command slots of the cluster's next ticket -- so that the

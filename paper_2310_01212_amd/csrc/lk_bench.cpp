@@ -273,18 +273,15 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
         }
         while (L.done < L.next) {
           const uint64_t t = L.first_ticket + L.done;
-          int fin = 0;
-          int rc = lk_poll(c, L.cluster, t, &fin);
-          if (rc) return fail_all(rc);
-          if (!fin) {
+          lk_completion ci;
+          const int rc = lk_try_wait(c, L.cluster, t, &ci);
+          if (rc == LK_EAGAIN) {
             if (timeout_ns >= 0 && clk::now() - L.t_sub[L.done] > std::chrono::nanoseconds(timeout_ns))
               return fail_all(LK_ETIMEDOUT);
             break;
           }
-          const auto now = clk::now();
-          lk_completion ci;
-          rc = lk_wait_info(c, L.cluster, t, 0, &ci);
           if (rc) return fail_all(rc);
+          const auto now = clk::now();
           const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.done;
           if (results) results[idx] = ci.result;
           if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done], now);

@@ -672,51 +672,88 @@ int lk_batch_plan(const lk_desc *items, const uint64_t *in_addr, const uint64_t 
   return LK_OK;
 }
 
-static int wait_impl(lk_ctx *c, uint32_t cluster, uint64_t t, int64_t timeout_ns, lk_completion *info) {
-  if (!c) return fail(LK_EINVAL, "NULL context");
-  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
-  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
-  ClusterSeq &cs = c->seqs[cluster];
-  if (t == 0 || t > cs.posted) return fail(LK_EINVAL, "ticket %llu was not posted", static_cast<unsigned long long>(t));
-  if (t <= cs.consumed) return fail(LK_EINVAL, "ticket %llu already released", static_cast<unsigned long long>(t));
-  const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
-  const bool bounded = timeout_ns >= 0;
-  const auto deadline = bounded ? clk::now() + std::chrono::nanoseconds(timeout_ns) : clk::time_point::max();
+// Member records of one ticket, folded as they are read.
+struct Fold {
   int64_t sum = 0;
   uint64_t pmin = ~0ull, pmax = 0, dmin = ~0ull, dmax = 0;
   bool fault = false;
-  for (uint32_t mb : mbs) {
-    const lkw_status *st = slot_status(c, mb, t);
-    uint32_t spins = 0;
-    Status s;
-    while (!read_status(st, t, &s)) {
-      if ((++spins & 255u) == 0) {
-        if (bounded && clk::now() > deadline) return fail(LK_ETIMEDOUT, "ticket %llu not finished", static_cast<unsigned long long>(t));
-        if (exited_code(worker_code(c, mb))) {
-          if (read_status(st, t, &s)) break;
-          return fail(LK_ESTATE, "worker of mailbox %u exited before finishing ticket %llu", mb,
-                      static_cast<unsigned long long>(t));
-        }
-      }
-      _mm_pause();
-    }
-    if (s.code == LKW_FROM_ERROR) fault = true;
+  void add(const Status &s) {
+    fault |= s.code == LKW_FROM_ERROR;
     sum += s.partial;
     pmin = std::min(pmin, s.t_pick);
     pmax = std::max(pmax, s.t_pick);
     dmin = std::min(dmin, s.t_done);
     dmax = std::max(dmax, s.t_done);
   }
+};
+
+// Releases a ticket whose every member has finished and reports it.
+static int release_ticket(ClusterSeq &cs, uint64_t t, const Fold &f, lk_completion *info) {
   cs.consumed = t;
   if (info) {
-    info->result = sum;
-    info->t_pick_min = pmin;
-    info->t_pick_max = pmax;
-    info->t_done_min = dmin;
-    info->t_done_max = dmax;
+    info->result = f.sum;
+    info->t_pick_min = f.pmin;
+    info->t_pick_max = f.pmax;
+    info->t_done_min = f.dmin;
+    info->t_done_max = f.dmax;
   }
-  if (fault) return fail(LK_EFAULT, "a worker rejected ticket %llu", static_cast<unsigned long long>(t));
+  if (f.fault) return fail(LK_EFAULT, "a worker rejected ticket %llu", static_cast<unsigned long long>(t));
   return LK_OK;
+}
+
+// Checks shared by the Wait calls; on success *cs is the cluster's sequence state.
+static int wait_args(lk_ctx *c, uint32_t cluster, uint64_t t, ClusterSeq **cs) {
+  if (!c) return fail(LK_EINVAL, "NULL context");
+  if (c->state != RUNNING) return fail(LK_ESTATE, "context is not running");
+  if (cluster >= c->n_clusters) return fail(LK_EINVAL, "cluster %u of %u", cluster, c->n_clusters);
+  *cs = &c->seqs[cluster];
+  if (t == 0 || t > (*cs)->posted) return fail(LK_EINVAL, "ticket %llu was not posted", static_cast<unsigned long long>(t));
+  if (t <= (*cs)->consumed) return fail(LK_EINVAL, "ticket %llu already released", static_cast<unsigned long long>(t));
+  return LK_OK;
+}
+
+static int wait_impl(lk_ctx *c, uint32_t cluster, uint64_t t, int64_t timeout_ns, lk_completion *info) {
+  ClusterSeq *cs = nullptr;
+  if (const int rc = wait_args(c, cluster, t, &cs)) return rc;
+  const bool bounded = timeout_ns >= 0;
+  const auto deadline = bounded ? clk::now() + std::chrono::nanoseconds(timeout_ns) : clk::time_point::max();
+  Fold f;
+  for (uint32_t mb : c->cluster_mbox[cluster]) {
+    const lkw_status *rec = slot_status(c, mb, t);
+    uint32_t spins = 0;
+    Status s;
+    while (!read_status(rec, t, &s)) {
+      if ((++spins & 255u) == 0) {
+        if (bounded && clk::now() > deadline) return fail(LK_ETIMEDOUT, "ticket %llu not finished", static_cast<unsigned long long>(t));
+        if (exited_code(worker_code(c, mb))) {
+          if (read_status(rec, t, &s)) break;
+          return fail(LK_ESTATE, "worker of mailbox %u exited before finishing ticket %llu", mb,
+                      static_cast<unsigned long long>(t));
+        }
+      }
+      _mm_pause();
+    }
+    f.add(s);
+  }
+  return release_ticket(*cs, t, f, info);
+}
+
+int lk_try_wait(lk_ctx *c, uint32_t cluster, uint64_t t, lk_completion *info) {
+  ClusterSeq *cs = nullptr;
+  if (const int rc = wait_args(c, cluster, t, &cs)) return rc;
+  Fold f;
+  for (uint32_t mb : c->cluster_mbox[cluster]) {
+    const lkw_status *rec = slot_status(c, mb, t);
+    Status s;
+    if (!read_status(rec, t, &s)) {
+      if (!exited_code(worker_code(c, mb))) return LK_EAGAIN;  // not yet: nothing changes
+      if (!read_status(rec, t, &s))
+        return fail(LK_ESTATE, "worker of mailbox %u exited before finishing ticket %llu", mb,
+                    static_cast<unsigned long long>(t));
+    }
+    f.add(s);
+  }
+  return release_ticket(*cs, t, f, info);
 }
 
 int lk_wait(lk_ctx *c, uint32_t cluster, uint64_t ticket, int64_t timeout_ns, int64_t *result) {

@@ -26,6 +26,7 @@ CODE_NOP, CODE_EXIT, CODE_WORK = 4, 8, 16
 
 EXPORTED = [
     "lk_config_default", "lk_init", "lk_submit", "lk_submit_batch", "lk_batch_plan", "lk_wait", "lk_wait_info", "lk_poll",
+    "lk_try_wait",
     "lk_prefetch", "lk_dispose", "lk_free", "lk_get_info", "lk_topology", "lk_cluster_members",
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
     "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_replay", "lkb_batch", "lkb_launch_burst",
@@ -138,6 +139,7 @@ def lib():
         "lk_wait": (ctypes.c_int, [P, U32, U64, I64, PI64]),
         "lk_wait_info": (ctypes.c_int, [P, U32, U64, I64, ctypes.POINTER(Completion)]),
         "lk_poll": (ctypes.c_int, [P, U32, U64, ctypes.POINTER(ctypes.c_int)]),
+        "lk_try_wait": (ctypes.c_int, [P, U32, U64, ctypes.POINTER(Completion)]),
         "lk_prefetch": (ctypes.c_int, [P, U32, U64]),
         "lk_dispose": (ctypes.c_int, [P]),
         "lk_free": (ctypes.c_int, [P]),
@@ -329,6 +331,16 @@ class Context:
         d = ctypes.c_int()
         _check(lib().lk_poll(self._h, cluster, ticket, ctypes.byref(d)), "lk_poll")
         return bool(d.value)
+
+    def try_wait(self, cluster, ticket):
+        """Non-blocking Wait: the completion dict if every member finished (the ticket is
+        then released), else None."""
+        c = Completion()
+        rc = lib().lk_try_wait(self._h, cluster, ticket, ctypes.byref(c))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "lk_try_wait")
+        return {f: getattr(c, f) for f, _ in Completion._fields_}
 
     def prefetch(self, cluster, ticket=0):
         """Hint: fetch the cluster's status lines of `ticket` and its next command slots."""

@@ -161,6 +161,14 @@ static void error_paths() {
   CHECK(lk_wait(c, 0, t0, 20000000ll, nullptr) == LK_ETIMEDOUT);
   int done = 1;
   CHECK(lk_poll(c, 0, t0, &done) == LK_OK && done == 0);
+  lk_completion ci;
+  CHECK(lk_try_wait(c, 0, t0, &ci) == LK_EAGAIN);  // not finished: the ticket stays valid
+  lkfake_freeze(-1);
+  int rc;
+  while ((rc = lk_try_wait(c, 0, t0, &ci)) == LK_EAGAIN) std::this_thread::yield();
+  CHECK(rc == LK_OK && ci.result == 0);
+  CHECK(lk_try_wait(c, 0, t0, &ci) == LK_EINVAL);  // released
+  CHECK(lk_submit(c, 0, &nop, nullptr, nullptr, &t0) == LK_OK);
   lkfake_freeze(-1);
   CHECK(lk_wait(c, 0, t0, 5000000000ll, nullptr) == LK_OK);
   CHECK(lk_wait(c, 0, t0, 0, nullptr) == LK_EINVAL);  // already released

@@ -569,6 +569,7 @@ def test_ring_full_timeout_and_disposed_state():
         with pytest.raises(lk.LKError) as e:
             ctx.wait(0, t1, timeout=0.0)
         assert e.value.code == lk.ETIMEDOUT
+        assert ctx.try_wait(0, t1) is None  # not finished: nothing released
         assert ctx.wait(0, t1, timeout=10.0) == 0
         with pytest.raises(lk.LKError) as e:
             ctx.wait(0, t1)
@@ -576,6 +577,16 @@ def test_ring_full_timeout_and_disposed_state():
         t2 = ctx.submit(0, lk.OP_NOP)
         ctx.prefetch(0, t2)  # a hint: no effect on the result
         assert ctx.wait(0, t2) == 0
+        xs = torch.arange(1000, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t3 = ctx.submit(0, lk.OP_SUM_I32_I64, x=xs)
+        done = None
+        while done is None:
+            done = ctx.try_wait(0, t3)
+        assert done["result"] == 999 * 1000 // 2
+        with pytest.raises(lk.LKError) as e:
+            ctx.try_wait(0, t3)
+        assert e.value.code == lk.EINVAL  # already released
         ctx.prefetch(0, t2)  # released ticket: only the next command slot
         with pytest.raises(lk.LKError) as e:
             ctx.prefetch(1, 0)
