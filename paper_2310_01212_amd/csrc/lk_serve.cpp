@@ -145,17 +145,15 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
       for (size_t w = 0; w < workers.size(); ++w) {
         auto &pq = posted[w];
         while (!pq.empty()) {
-          int fin = 0;
-          int rc = lk_poll(c, workers[w], pq.front().ticket, &fin);
-          if (rc) return fail(rc);
-          if (!fin) {
+          lk_completion ci;
+          const int rc = lk_try_wait(c, workers[w], pq.front().ticket, &ci);
+          if (rc == LK_EAGAIN) {
             if (cfg->timeout_ns >= 0 && now - pq.front().t_post > std::chrono::nanoseconds(cfg->timeout_ns))
               return fail(LK_ETIMEDOUT);
             break;
           }
-          int64_t part = 0;
-          rc = lk_wait(c, workers[w], pq.front().ticket, 0, &part);
           if (rc) return fail(rc);
+          const int64_t part = ci.result;
           const uint64_t i = pq.front().req;
           pq.pop_front();
           ++tiles_done[s];
