@@ -21,6 +21,11 @@ reachable state graph) and these properties are checked:
                     the final state (everything consumed, every worker exited) is
                     reachable from every reachable state.
 
+With ``lookahead`` (depth > 1) a worker may also, at any point while it runs an item,
+snapshot its next command slot once, and at its next poll take the command from that
+snapshot when the snapshot holds the expected sequence number (the device's look-ahead
+read, whose timing is left free here).
+
 The ``bug`` argument plants a mistake in the model (never in the product) so that the
 tests can show the checker catches each class of error.
 """
@@ -31,7 +36,7 @@ from typing import Tuple
 FROM_INIT, FROM_FINISHED, FROM_WORKING, FROM_NOP = 0, 1, 2, 4
 TO_NOP, TO_EXIT, TO_WORK = 4, 8, 16
 
-BUGS = ("none", "cmd_before_payload", "status_before_output", "no_ring_check", "no_seq")
+BUGS = ("none", "cmd_before_payload", "status_before_output", "no_ring_check", "no_seq", "ahead_no_seq")
 
 
 @dataclass(frozen=True)
@@ -40,6 +45,10 @@ class Config:
     items: Tuple[int, ...]                  # cluster id of each item, in host submission order
     depth: int = 1
     bug: str = "none"
+    # look-ahead (depth > 1): while it runs an item a worker may snapshot its next slot
+    # once, and take the command from that snapshot instead of reading the slot again
+    # when the snapshot holds the expected sequence number
+    lookahead: bool = False
 
     @property
     def n_workers(self):
@@ -56,8 +65,9 @@ def _initial(cfg):
     # slot's payload describes (-1 = none); payload and word are written separately.
     cmd = tuple(tuple((0, TO_NOP, -1) for _ in range(D)) for _ in range(W))
     status = tuple(tuple((0, FROM_INIT) for _ in range(D)) for _ in range(W))
-    # worker: (done_seq, phase, cur_item, exited) phase: 0 poll, 1 exec, 2 publish, 3 exited
-    workers = tuple((0, 0, -1, 0) for _ in range(W))
+    # worker: (done_seq, phase, cur_item, exited, ahead) phase: 0 poll, 1 exec, 2 publish,
+    # 3 exited; ahead = snapshot (seq, code, payload_item) of the next slot, or None
+    workers = tuple((0, 0, -1, 0, None) for _ in range(W))
     outputs = frozenset()            # (item, worker) pairs whose output is written
     executed = ()                    # tuple of (worker, seq, item) in execution order
     # host: next item index to post, partially posted member index (-1 none),
@@ -152,39 +162,50 @@ def _steps(cfg, st):
             yield ("exit", (ncmd, status, workers, outputs, executed, nhost))
 
     # --- workers
-    for w, (done, phase, cur, exited) in enumerate(workers):
+    for w, (done, phase, cur, exited, ahead) in enumerate(workers):
         if phase == 3:
             continue
         if phase == 0:   # poll the next slot; accept only the expected sequence number
             slot = (done + 1) % D
-            seq, code, pay = cmd[w][slot]
-            # planted bug "no_seq": a lone code word without a sequence number, so any
-            # WORK word in the slot looks new (the naive reading of Table 1).
-            ok = seq == done + 1 or (cfg.bug == "no_seq" and code == TO_WORK and seq > 0)
+            if ahead is not None and (ahead[0] == done + 1 or cfg.bug == "ahead_no_seq"):
+                # the snapshot taken during the previous item is the command (planted bug
+                # "ahead_no_seq": used without checking its sequence number)
+                seq, code, pay = ahead
+                ok = True
+            else:
+                seq, code, pay = cmd[w][slot]
+                # planted bug "no_seq": a lone code word without a sequence number, so any
+                # WORK word in the slot looks new (the naive reading of Table 1).
+                ok = seq == done + 1 or (cfg.bug == "no_seq" and code == TO_WORK and seq > 0)
             if not ok:
                 continue
             if code == TO_EXIT:
-                nw = _set(workers, w, (done + 1, 3, -1, 1))
+                nw = _set(workers, w, (done + 1, 3, -1, 1, None))
                 yield (f"w{w}exit", (cmd, status, nw, outputs, executed, host))
                 continue
-            nw = _set(workers, w, (done + 1, 1, pay, 0))
+            nw = _set(workers, w, (done + 1, 1, pay, 0, None))
             nexec = executed + ((w, done + 1, pay),)
             yield (f"w{w}pick", (cmd, status, nw, outputs, nexec, host))
-        elif phase == 1:   # execute: write the output (or, planted bug, publish first)
+            continue
+        if cfg.lookahead and D > 1 and ahead is None:   # look-ahead read during the item
+            snap = cmd[w][(done + 1) % D]
+            nw = _set(workers, w, (done, phase, cur, 0, snap))
+            yield (f"w{w}ahead", (cmd, status, nw, outputs, executed, host))
+        if phase == 1:   # execute: write the output (or, planted bug, publish first)
             if cfg.bug == "status_before_output":
                 nst = _set(status, w, _set(status[w], done % D, (done, FROM_FINISHED)))
-                nw = _set(workers, w, (done, 2, cur, 0))
+                nw = _set(workers, w, (done, 2, cur, 0, ahead))
                 yield (f"w{w}pub", (cmd, nst, nw, outputs, executed, host))
             else:
-                nw = _set(workers, w, (done, 2, cur, 0))
+                nw = _set(workers, w, (done, 2, cur, 0, ahead))
                 yield (f"w{w}out", (cmd, status, nw, outputs | {(cur, w)}, executed, host))
         elif phase == 2:   # release: publish FINISHED (or, planted bug, write the output last)
             if cfg.bug == "status_before_output":
-                nw = _set(workers, w, (done, 0, -1, 0))
+                nw = _set(workers, w, (done, 0, -1, 0, ahead))
                 yield (f"w{w}out", (cmd, status, nw, outputs | {(cur, w)}, executed, host))
             else:
                 nst = _set(status, w, _set(status[w], done % D, (done, FROM_FINISHED)))
-                nw = _set(workers, w, (done, 0, -1, 0))
+                nw = _set(workers, w, (done, 0, -1, 0, ahead))
                 yield (f"w{w}pub", (cmd, nst, nw, outputs, executed, host))
 
 
@@ -210,7 +231,7 @@ def _check_state(cfg, st):
 
 def _is_final(cfg, st):
     cmd, status, workers, outputs, executed, host = st
-    return all(p == 3 for (_, p, _, _) in workers) and host[0] == len(cfg.items)
+    return all(p == 3 for (_, p, _, _, _) in workers) and host[0] == len(cfg.items)
 
 
 def check(cfg, max_states=2_000_000):

@@ -64,3 +64,34 @@ def test_checker_catches_planted_protocol_bugs(bug, expect):
             assert str(e).startswith(expect), str(e)
             caught += 1
     assert caught >= 3
+
+
+LOOKAHEAD_SYSTEMS = [
+    pm.Config(((0,),), (0, 0, 0), 2, lookahead=True),
+    pm.Config(((0,),), (0, 0, 0, 0), 3, lookahead=True),
+    pm.Config(((0,), (1,)), (0, 0, 1, 0), 2, lookahead=True),
+    pm.Config(((0, 1),), (0, 0, 0), 2, lookahead=True),
+]
+
+
+@pytest.mark.parametrize("cfg", LOOKAHEAD_SYSTEMS, ids=lambda c: f"{c.clusters}-{c.items}-d{c.depth}-ahead")
+def test_protocol_holds_with_the_lookahead_read(cfg):
+    """A worker may snapshot its next slot at any point while it runs an item and take
+    the command from the snapshot when its sequence number is the expected one: every
+    property still holds on every interleaving (the ring check keeps the slot from being
+    reused before the snapshot's command has run)."""
+    n = pm.check(cfg)
+    assert n > pm.check(pm.Config(cfg.clusters, cfg.items, cfg.depth))  # the snapshots add states
+
+
+def test_checker_catches_a_lookahead_without_sequence_check():
+    caught = 0
+    for cfg in LOOKAHEAD_SYSTEMS:
+        bad = pm.Config(cfg.clusters, cfg.items, cfg.depth, "ahead_no_seq", lookahead=True)
+        try:
+            pm.check(bad)
+        except pm.Violation as e:
+            assert str(e).startswith("I"), str(e)
+            caught += 1
+    assert caught == len(LOOKAHEAD_SYSTEMS)
+
