@@ -278,6 +278,18 @@ static void cluster_split() {
   CHECK(lk_wait(c, 0, t, 5000000000ll, &s) == LK_OK);
   affine_ref(x.data(), n, -5, 11, yr.data(), &sr);
   CHECK(s == sr && y == yr);
+  // the same item released through the non-blocking form, with one member held back:
+  // nothing is released until all 8 have finished
+  std::fill(y.begin(), y.end(), 0);
+  lkfake_freeze(5);
+  CHECK(lk_submit(c, 0, &d, x.data(), y.data(), &t) == LK_OK);
+  lk_completion ci;
+  std::this_thread::sleep_for(std::chrono::milliseconds(20));
+  CHECK(lk_try_wait(c, 0, t, &ci) == LK_EAGAIN);
+  lkfake_freeze(-1);
+  int rc;
+  while ((rc = lk_try_wait(c, 0, t, &ci)) == LK_EAGAIN) std::this_thread::yield();
+  CHECK(rc == LK_OK && ci.result == sr && y == yr && ci.t_pick_min <= ci.t_done_max);
   int64_t psum = 0;
   for (int64_t v : parts) psum += v;
   CHECK(psum == sr);
