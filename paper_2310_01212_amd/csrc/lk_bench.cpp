@@ -656,10 +656,14 @@ int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64
       uint32_t id;
       uint64_t next = 0;
       bool busy = false;
-      clk::time_point t0;
+      clk::time_point t0{};
     };
     std::vector<Lane> lanes;
-    for (uint32_t l = tix; l < n_lanes; l += n_threads) lanes.push_back(Lane{l});
+    for (uint32_t l = tix; l < n_lanes; l += n_threads) {
+      Lane L{};
+      L.id = l;
+      lanes.push_back(L);
+    }
     uint64_t remaining = lanes.size() * items_per_lane;
     while (remaining && !stop.load(std::memory_order_relaxed)) {
       for (Lane &L : lanes) {
