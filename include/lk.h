@@ -105,10 +105,11 @@ typedef struct lk_desc {
   uint64_t user_tag;  /* opaque to the library; not interpreted */
 } lk_desc;
 
-/* Descriptor flags: keep x of a SAXPY_F32 / AXPY_F32 item in each member worker's local
- * data share (LDS) across items, mapping that operand onto the cluster that computes with
- * it (Sec. 2.1: clusters are exposed so that data, as well as work, can be placed on
- * them, and their local memories keep data next to the computation).
+/* Descriptor flags: keep x (the `in` operand) of a SAXPY_F32, AXPY_F32, AFFINE_SUM_I32 or
+ * SUM_I32_I64 item in each member worker's local data share (LDS) across items, mapping
+ * that operand onto the cluster that computes with it (Sec. 2.1: clusters are exposed so
+ * that data, as well as work, can be placed on them, and their local memories keep data
+ * next to the computation).
  *
  *  LK_DF_PIN_INPUT   a member whose pinned copy has the same slice address and length
  *                    reads x from LDS instead of memory; otherwise it reads x from memory
@@ -117,10 +118,11 @@ typedef struct lk_desc {
  *  LK_DF_PIN_RELOAD  as LK_DF_PIN_INPUT, but always reads x from memory and replaces the
  *                    pinned copy: use it on the first item after x has changed.
  *
- * Each worker holds one pinned slice.  Items without these flags leave it in place.
- * lk_submit rejects a flagged item (LK_EINVAL) unless: the op is SAXPY_F32 or AXPY_F32;
- * in, out and (AXPY_F32) y are 16-byte aligned; and every member's slice is a multiple
- * of 4 elements of at most lk_info.pin_capacity bytes.  n = 0 is accepted and pins
+ * Each worker holds one pinned slice (its raw 32-bit words, whatever the op).  Items
+ * without these flags leave it in place.  lk_submit rejects a flagged item (LK_EINVAL)
+ * unless: the op is one of the four above; in, the out it writes (not SUM_I32_I64's) and
+ * (AXPY_F32) y are 16-byte aligned; and every member's slice is a multiple of 4 elements
+ * of at most lk_info.pin_capacity bytes.  n = 0 is accepted and pins
  * nothing.  Batches take no flags. */
 #define LK_DF_PIN_INPUT  0x1u
 #define LK_DF_PIN_RELOAD 0x2u

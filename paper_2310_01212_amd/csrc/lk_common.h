@@ -10,6 +10,8 @@
 namespace lkd {
 
 constexpr uint32_t kOpCount = 8;  // NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN, BATCH, AXPY_F32
+constexpr uint32_t kOpAffineSum = 1;
+constexpr uint32_t kOpSumI64 = 2;
 constexpr uint32_t kOpSaxpy = 3;
 constexpr uint32_t kOpBatch = 6;
 constexpr uint32_t kOpAxpy = 7;

@@ -573,9 +573,11 @@ int lk_submit(lk_ctx *c, uint32_t cluster, const lk_desc *d, const void *in, voi
   const uint32_t k = static_cast<uint32_t>(mbs.size());
   const uint32_t esz = 4;
   if (d->flags && d->n) {
-    if (d->op != LK_OP_SAXPY_F32 && d->op != LK_OP_AXPY_F32)
-      return fail(LK_EINVAL, "pinned input needs SAXPY_F32 or AXPY_F32, not op %u", d->op);
-    if ((ia | oa | (d->op == LK_OP_AXPY_F32 ? d->aux : 0)) & 15u)
+    if (d->op != LK_OP_SAXPY_F32 && d->op != LK_OP_AXPY_F32 && d->op != LK_OP_AFFINE_SUM_I32 &&
+        d->op != LK_OP_SUM_I32_I64)
+      return fail(LK_EINVAL, "pinned input needs SAXPY_F32, AXPY_F32, AFFINE_SUM_I32 or SUM_I32_I64, not op %u", d->op);
+    const uint64_t used_out = d->op == LK_OP_SUM_I32_I64 ? 0 : oa;  // SUM reads x only
+    if ((ia | used_out | (d->op == LK_OP_AXPY_F32 ? d->aux : 0)) & 15u)
       return fail(LK_EINVAL, "pinned input needs 16-byte aligned in, out and y");
     for (uint32_t j = 0; j < k; ++j) {
       uint64_t lo, hi;

@@ -77,10 +77,14 @@ constexpr uint64_t kSegmentElems = 1ull << 28;
 
 // Ordinary stores; the per-launch kernels rely on the end-of-kernel release.
 struct CachedStore {
-  __device__ __forceinline__ CachedStore(void *, uint64_t) {}
+  char *base;
+  __device__ __forceinline__ CachedStore(void *out, uint64_t) : base(static_cast<char *>(out)) {}
   template <typename T>
   __device__ __forceinline__ void put(T *p, T v) const { *p = v; }
   __device__ __forceinline__ void put(u32x4 *p, u32x4 v) const { __builtin_nontemporal_store(v, p); }
+  // 16 bytes at byte offset `off` of the segment's output.
+  template <typename T>
+  __device__ __forceinline__ void put_at(uint32_t off, T v) const { *reinterpret_cast<T *>(base + off) = v; }
 };
 
 // System-coherent stores (cache policy sc0 sc1) through a buffer resource covering the
@@ -125,7 +129,48 @@ struct SystemStore {
   __device__ __forceinline__ void put(float *p, float v) const {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, off(p), 0, kSysCoherent);
   }
+  // 16 bytes at byte offset `off` of the segment's output.
+  __device__ __forceinline__ void put_at(uint32_t off, float4 v) const {
+    const u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rsrc, static_cast<int>(off), 0, kSysCoherent);
+  }
+  __device__ __forceinline__ void put_at(uint32_t off, int4 v) const {
+    const u32x4 w = {static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y), static_cast<uint32_t>(v.z),
+                     static_cast<uint32_t>(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rsrc, static_cast<int>(off), 0, kSysCoherent);
+  }
 };
+
+// Reads of one segment of an input operand through a buffer resource.  The vector loops
+// index every operand of an item with the same 32-bit byte offset (their elements line up),
+// so one offset register per access serves the loads and the store, instead of a 64-bit
+// address per operand and access; these are also plain vector-memory reads, where a
+// generic pointer would give flat accesses that also wait on the LDS counter.
+struct BufIn {
+  __amdgpu_buffer_rsrc_t rsrc;
+  __device__ __forceinline__ BufIn(const void *p, uint64_t bytes) {
+    const uint64_t b = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(bytes));
+    rsrc = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>((static_cast<uint64_t>(hi) << 32) | lo), 0,
+                                             static_cast<int>(nb), 0x00020000);
+  }
+  __device__ __forceinline__ float4 f4(uint32_t off) const {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<int>(off), 0, 0);
+    return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w));
+  }
+  __device__ __forceinline__ int4 i4(uint32_t off) const {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<int>(off), 0, 0);
+    return make_int4(static_cast<int32_t>(w.x), static_cast<int32_t>(w.y), static_cast<int32_t>(w.z),
+                     static_cast<int32_t>(w.w));
+  }
+};
+
+// Byte offset of 16-byte vector k after a head of `head_bytes` (k < 2^26 in a segment).
+__device__ __forceinline__ uint32_t voff(uint32_t head_bytes, uint64_t k) {
+  return head_bytes + static_cast<uint32_t>(k) * 16u;
+}
 
 // int32 affine map modulo 2^32 and/or int64 sum.  STORE=false gives SUM_I32_I64 (a=1, b=0).
 template <bool STORE, class St>
@@ -146,36 +191,34 @@ __device__ __forceinline__ int64_t affine_sum(const int32_t *__restrict__ x, int
       if (STORE) st.put(y + tid, static_cast<int32_t>(v));
       acc += static_cast<int32_t>(v);
     }
-    const int4 *__restrict__ xv = reinterpret_cast<const int4 *>(x + head);
-    int4 *__restrict__ yv = STORE ? reinterpret_cast<int4 *>(y + head) : nullptr;
+    const BufIn xin(x, n * 4);
+    const uint32_t hb = static_cast<uint32_t>(head * 4);
     const uint64_t nv = (n - head) >> 2;
+    auto one = [&](uint32_t o, int4 r) {
+      int4 v;
+      v.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.x), b));
+      v.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
+      v.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
+      v.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
+      if (STORE) st.put_at(o, v);
+      acc += static_cast<int64_t>(v.x) + static_cast<int64_t>(v.y) + static_cast<int64_t>(v.z) +
+             static_cast<int64_t>(v.w);
+    };
     uint64_t k = tid;
     for (; k + (U - 1) * nt < nv; k += U * nt) {
+      uint32_t o[U];
       int4 r[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = xv[k + u * nt];
-#pragma unroll
       for (int u = 0; u < U; ++u) {
-        int4 o;
-        o.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].x), b));
-        o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].y), b));
-        o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].z), b));
-        o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r[u].w), b));
-        if (STORE) st.put(yv + k + u * nt, o);
-        acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
-               static_cast<int64_t>(o.w);
+        o[u] = voff(hb, k + u * nt);
+        r[u] = xin.i4(o[u]);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) one(o[u], r[u]);
     }
     for (; k < nv; k += nt) {
-      const int4 r = xv[k];
-      int4 o;
-      o.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.x), b));
-      o.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
-      o.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
-      o.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
-      if (STORE) st.put(yv + k, o);
-      acc += static_cast<int64_t>(o.x) + static_cast<int64_t>(o.y) + static_cast<int64_t>(o.z) +
-             static_cast<int64_t>(o.w);
+      const uint32_t o = voff(hb, k);
+      one(o, xin.i4(o));
     }
     done = head + nv * 4;
   }
@@ -209,24 +252,73 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
     uint64_t head = ((16u - xa) & 15u) >> 2;
     if (head > n) head = n;
     if (tid < head) st.put(y + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
-    const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
-    float4 *__restrict__ yv = reinterpret_cast<float4 *>(y + head);
+    const BufIn xin(x, n * 4), yin(y, n * 4);
+    const uint32_t hb = static_cast<uint32_t>(head * 4);
     const uint64_t nv = (n - head) >> 2;
     uint64_t k = tid;
     for (; k + (U - 1) * nt < nv; k += U * nt) {
+      uint32_t o[U];
       float4 rx[U], ry[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        rx[u] = xv[k + u * nt];
-        ry[u] = yv[k + u * nt];
+        o[u] = voff(hb, k + u * nt);
+        rx[u] = xin.f4(o[u]);
+        ry[u] = yin.f4(o[u]);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) st.put(yv + k + u * nt, fma4(alpha, rx[u], ry[u]));
+      for (int u = 0; u < U; ++u) st.put_at(o[u], fma4(alpha, rx[u], ry[u]));
     }
-    for (; k < nv; k += nt) st.put(yv + k, fma4(alpha, xv[k], yv[k]));
+    for (; k < nv; k += nt) {
+      const uint32_t o = voff(hb, k);
+      st.put_at(o, fma4(alpha, xin.f4(o), yin.f4(o)));
+    }
     done = head + nv * 4;
   }
   for (uint64_t i = done + tid; i < n; i += nt) st.put(y + i, __builtin_fmaf(alpha, x[i], y[i]));
+}
+
+// int32 affine map and/or int64 sum (STORE=false: SUM_I32_I64, a=1, b=0) with x kept in
+// the workgroup's LDS across items, under the same contract as axpy_pinned below: x (and
+// y when STORE) 16-byte aligned, n a multiple of 4, n * 4 bytes within the LDS buffer;
+// FILL reads x from memory and stores it to LDS on the way, each thread handling the same
+// vectors in both forms.  Returns this thread's part of the sum.
+template <bool STORE, class St, bool FILL>
+__device__ __forceinline__ int64_t affine_sum_pinned(const int32_t *__restrict__ x, int4 *__restrict__ lds,
+                                                     int32_t *y, uint64_t n, uint32_t a, uint32_t b, uint64_t nt) {
+  constexpr int U = 4;
+  const St st(y, n * 4);
+  const BufIn xin(x, FILL ? n * 4 : 0);
+  const uint64_t tid = threadIdx.x;
+  const uint64_t nv = n >> 2;
+  int64_t acc = 0;
+  auto one = [&](uint32_t o, int4 r) {
+    int4 v;
+    v.x = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.x), b));
+    v.y = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.y), b));
+    v.z = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.z), b));
+    v.w = static_cast<int32_t>(affine(a, static_cast<uint32_t>(r.w), b));
+    if (STORE) st.put_at(o, v);
+    acc += static_cast<int64_t>(v.x) + static_cast<int64_t>(v.y) + static_cast<int64_t>(v.z) +
+           static_cast<int64_t>(v.w);
+  };
+  uint64_t k = tid;
+  for (; k + (U - 1) * nt < nv; k += U * nt) {
+    int4 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = FILL ? xin.i4(voff(0, k + u * nt)) : lds[k + u * nt];
+    if (FILL) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) lds[k + u * nt] = r[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) one(voff(0, k + u * nt), r[u]);
+  }
+  for (; k < nv; k += nt) {
+    const int4 r = FILL ? xin.i4(voff(0, k)) : lds[k];
+    if (FILL) lds[k] = r;
+    one(voff(0, k), r);
+  }
+  return acc;
 }
 
 // out[i] = fma(alpha, x[i], y[i]) with x kept in the workgroup's LDS across items (SAXPY
@@ -240,31 +332,32 @@ __device__ __forceinline__ void axpy_pinned(const float *__restrict__ x, float4 
                                             float *out, uint64_t n, float alpha, uint64_t nt) {
   constexpr int U = 4;
   const St st(out, n * 4);
+  const BufIn xin(x, FILL ? n * 4 : 0), yin(y, n * 4);
   const uint64_t tid = threadIdx.x;
-  const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x);
-  const float4 *yv = reinterpret_cast<const float4 *>(y);
-  float4 *ov = reinterpret_cast<float4 *>(out);
   const uint64_t nv = n >> 2;
   uint64_t k = tid;
   for (; k + (U - 1) * nt < nv; k += U * nt) {
+    uint32_t o[U];
     float4 rx[U], ry[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      rx[u] = FILL ? xv[k + u * nt] : lds[k + u * nt];
-      ry[u] = yv[k + u * nt];
+      o[u] = voff(0, k + u * nt);
+      rx[u] = FILL ? xin.f4(o[u]) : lds[k + u * nt];
+      ry[u] = yin.f4(o[u]);
     }
     if (FILL) {
 #pragma unroll
       for (int u = 0; u < U; ++u) lds[k + u * nt] = rx[u];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) st.put(ov + k + u * nt, fma4(alpha, rx[u], ry[u]));
+    for (int u = 0; u < U; ++u) st.put_at(o[u], fma4(alpha, rx[u], ry[u]));
   }
   for (; k < nv; k += nt) {
-    const float4 rx = FILL ? xv[k] : lds[k];
-    const float4 ry = yv[k];
+    const uint32_t o = voff(0, k);
+    const float4 rx = FILL ? xin.f4(o) : lds[k];
+    const float4 ry = yin.f4(o);
     if (FILL) lds[k] = rx;
-    st.put(ov + k, fma4(alpha, rx, ry));
+    st.put_at(o, fma4(alpha, rx, ry));
   }
 }
 
@@ -281,22 +374,26 @@ __device__ __forceinline__ void axpy(const float *__restrict__ x, const float *_
     uint64_t head = ((16u - xa) & 15u) >> 2;
     if (head > n) head = n;
     if (tid < head) st.put(out + tid, __builtin_fmaf(alpha, x[tid], y[tid]));
-    const float4 *__restrict__ xv = reinterpret_cast<const float4 *>(x + head);
-    const float4 *__restrict__ yv = reinterpret_cast<const float4 *>(y + head);
-    float4 *__restrict__ ov = reinterpret_cast<float4 *>(out + head);
+    const BufIn xin(x, n * 4), yin(y, n * 4);
+    const uint32_t hb = static_cast<uint32_t>(head * 4);
     const uint64_t nv = (n - head) >> 2;
     uint64_t k = tid;
     for (; k + (U - 1) * nt < nv; k += U * nt) {
+      uint32_t o[U];
       float4 rx[U], ry[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        rx[u] = xv[k + u * nt];
-        ry[u] = yv[k + u * nt];
+        o[u] = voff(hb, k + u * nt);
+        rx[u] = xin.f4(o[u]);
+        ry[u] = yin.f4(o[u]);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) st.put(ov + k + u * nt, fma4(alpha, rx[u], ry[u]));
+      for (int u = 0; u < U; ++u) st.put_at(o[u], fma4(alpha, rx[u], ry[u]));
     }
-    for (; k < nv; k += nt) st.put(ov + k, fma4(alpha, xv[k], yv[k]));
+    for (; k < nv; k += nt) {
+      const uint32_t o = voff(hb, k);
+      st.put_at(o, fma4(alpha, xin.f4(o), yin.f4(o)));
+    }
     done = head + nv * 4;
   }
   for (uint64_t i = done + tid; i < n; i += nt) st.put(out + i, __builtin_fmaf(alpha, x[i], y[i]));

@@ -244,22 +244,41 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
                           static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, s_batch_next,
                           p.threads);
     } else if (s.op != 0) {
-      // Pinned input (AXPY forms only): x is served from LDS when this worker's last
-      // pinned copy has the same address and length, else loaded and kept.  The shape
-      // check repeats the host's so LDS is never addressed past the buffer.
+      // Pinned input (AXPY forms and the integer ops): x is served from LDS when this
+      // worker's last pinned copy has the same address and length, else loaded and kept.
+      // The shape check repeats the host's so LDS is never addressed past the buffer.
       const uint64_t ia = reinterpret_cast<uint64_t>(s.in);
+      const bool axpy_form = s.op == lkd::kOpSaxpy || s.op == lkd::kOpAxpy;
+      const bool int_form = s.op == lkd::kOpAffineSum || s.op == lkd::kOpSumI64;
       const float *y = s.op == lkd::kOpAxpy ? static_cast<const float *>(s.in2) : static_cast<const float *>(s.out);
-      const bool pin = (dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == lkd::kOpSaxpy || s.op == lkd::kOpAxpy) &&
-                       s.n > 0 && (s.n & 3u) == 0 && s.n * 4 <= p.lds_bytes &&
-                       ((ia | reinterpret_cast<uint64_t>(s.out) | reinterpret_cast<uint64_t>(y)) & 15u) == 0;
+      const uint64_t oa = s.op == lkd::kOpSumI64 ? 0 : reinterpret_cast<uint64_t>(s.out);
+      const uint64_t ya = axpy_form ? reinterpret_cast<uint64_t>(y) : 0;
+      const bool pin = (dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (axpy_form || int_form) && s.n > 0 &&
+                       (s.n & 3u) == 0 && s.n * 4 <= p.lds_bytes && ((ia | oa | ya) & 15u) == 0;
+      const bool hit = pin && !(dflags & LKW_DF_PIN_RELOAD) && ia == pin_addr && s.n == pin_n;
+      int4 *lds_i = reinterpret_cast<int4 *>(lds_pin);
+      const int32_t *xi = static_cast<const int32_t *>(s.in);
+      int32_t *yi = static_cast<int32_t *>(s.out);
       if (!pin) {
         partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
-      } else if (!(dflags & LKW_DF_PIN_RELOAD) && ia == pin_addr && s.n == pin_n) {
-        lkops::axpy_pinned<lkops::SystemStore, false>(static_cast<const float *>(s.in), lds_pin, y,
-                                                      static_cast<float *>(s.out), s.n, s.alpha, p.threads);
+      } else if (axpy_form) {
+        if (hit)
+          lkops::axpy_pinned<lkops::SystemStore, false>(static_cast<const float *>(s.in), lds_pin, y,
+                                                        static_cast<float *>(s.out), s.n, s.alpha, p.threads);
+        else
+          lkops::axpy_pinned<lkops::SystemStore, true>(static_cast<const float *>(s.in), lds_pin, y,
+                                                       static_cast<float *>(s.out), s.n, s.alpha, p.threads);
       } else {
-        lkops::axpy_pinned<lkops::SystemStore, true>(static_cast<const float *>(s.in), lds_pin, y,
-                                                     static_cast<float *>(s.out), s.n, s.alpha, p.threads);
+        int64_t acc;
+        if (s.op == lkd::kOpAffineSum)
+          acc = hit ? lkops::affine_sum_pinned<true, lkops::SystemStore, false>(xi, lds_i, yi, s.n, s.a, s.b, p.threads)
+                    : lkops::affine_sum_pinned<true, lkops::SystemStore, true>(xi, lds_i, yi, s.n, s.a, s.b, p.threads);
+        else
+          acc = hit ? lkops::affine_sum_pinned<false, lkops::SystemStore, false>(xi, lds_i, nullptr, s.n, 1u, 0u, p.threads)
+                    : lkops::affine_sum_pinned<false, lkops::SystemStore, true>(xi, lds_i, nullptr, s.n, 1u, 0u, p.threads);
+        partial = lkops::block_sum_i64(acc, s_red, p.threads);
+      }
+      if (pin && !hit) {
         pin_addr = ia;
         pin_n = s.n;
       }

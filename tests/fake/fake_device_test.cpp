@@ -236,13 +236,53 @@ static void pinned_input() {
   uint64_t t;
   CHECK(lk_submit(c, 1, &ax, x2, out, &t) == LK_OK && lk_wait(c, 1, t, 5000000000ll, nullptr) == LK_OK);
   for (uint64_t i = 0; i < n; ++i) CHECK(out[i] == std::fmaf(3.f, x2[i], yy[i]));
+  // The integer ops: the pinned words stand in for x in the sum and in AFFINE's y.
+  alignas(64) static int32_t xi[4096], yi[4096];
+  for (uint64_t i = 0; i < n; ++i) xi[i] = static_cast<int32_t>(rng());
+  auto isum = [&](int32_t a, int32_t b, const int32_t *xs, bool affine) {
+    int64_t s = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+      const int32_t v = affine ? static_cast<int32_t>(static_cast<uint32_t>(a) * static_cast<uint32_t>(xs[i]) +
+                                                      static_cast<uint32_t>(b))
+                               : xs[i];
+      s += v;
+      if (affine) CHECK(yi[i] == v);
+    }
+    return s;
+  };
+  auto irun = [&](lk_desc di, const int32_t *xp) {
+    int64_t r = 0;
+    CHECK(lk_submit(c, 1, &di, xp, di.op == LK_OP_SUM_I32_I64 ? nullptr : yi, &t) == LK_OK);
+    CHECK(lk_wait(c, 1, t, 5000000000ll, &r) == LK_OK);
+    return r;
+  };
+  lk_desc af = desc(LK_OP_AFFINE_SUM_I32, n, -7, 13);
+  af.flags = LK_DF_PIN_INPUT;
+  CHECK(irun(af, xi) == isum(-7, 13, xi, true));  // loads and pins xi (replacing x2)
+  int32_t iold[4096];
+  memcpy(iold, xi, sizeof iold);
+  for (uint64_t i = 0; i < n; ++i) xi[i] ^= 0x5a5a;
+  CHECK(irun(af, xi) == isum(-7, 13, iold, true));  // the pinned copy
+  lk_desc su = desc(LK_OP_SUM_I32_I64, n);
+  su.flags = LK_DF_PIN_INPUT;
+  CHECK(irun(su, xi) == isum(0, 0, iold, false));  // same address and length: the copy again
+  su.flags = LK_DF_PIN_RELOAD;
+  CHECK(irun(su, xi) == isum(0, 0, xi, false));
+  CHECK(irun(af, xi) == isum(-7, 13, xi, true));
   // shapes the pinned path refuses
   lk_desc e = d;
   e.flags = 0x4;
   CHECK(lk_submit(c, 0, &e, x, y, &t) == LK_EINVAL);
-  e = desc(LK_OP_AFFINE_SUM_I32, 64);
+  e = desc(LK_OP_COPY_F32, 64);
   e.flags = LK_DF_PIN_INPUT;
   CHECK(lk_submit(c, 0, &e, x, y, &t) == LK_EINVAL);
+  e = desc(LK_OP_SUM_I32_I64, 64);
+  e.flags = LK_DF_PIN_INPUT;
+  CHECK(lk_submit(c, 0, &e, xi, reinterpret_cast<int32_t *>(yi) + 1, &t) == LK_OK);  // SUM ignores out
+  CHECK(lk_wait(c, 0, t, 5000000000ll, nullptr) == LK_OK);
+  e = desc(LK_OP_AFFINE_SUM_I32, 64);
+  e.flags = LK_DF_PIN_INPUT;
+  CHECK(lk_submit(c, 0, &e, xi, yi + 1, &t) == LK_EINVAL);  // AFFINE's out must be aligned
   e = d;
   CHECK(lk_submit(c, 0, &e, x + 1, y + 1, &t) == LK_EINVAL);  // 4- but not 16-byte aligned
   e.n = n - 2;

@@ -115,8 +115,8 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
   lkw_cmd *ring = p.cmd + m * stride;
   lkw_status *sring = p.status + m * stride;
   uint64_t seq = 0;
-  // Model of the pinned input: one copy of x per worker, up to p.lds_bytes.
-  std::vector<float> pin;
+  // Model of the pinned input: one copy of x's 32-bit words per worker, up to p.lds_bytes.
+  std::vector<uint32_t> pin;
   uint64_t pin_addr = 0, pin_n = 0;
   for (;;) {
     const uint64_t want = seq + 1;
@@ -188,11 +188,13 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
       }
     } else if (reply != LKW_FROM_EXITED) {
       const uint32_t dflags = static_cast<uint32_t>(w[LKW_W_B] >> 32) & 0xffffu;
-      const uint64_t y = s.op == 7 ? s.in2 : s.out;
-      if ((dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == 3 || s.op == 7) && s.n > 0 &&
-          s.n % 4 == 0 && s.n * 4 <= p.lds_bytes && ((s.in | s.out | y) & 15u) == 0) {
+      // ops: 1 AFFINE_SUM_I32, 2 SUM_I32_I64 (reads x only), 3 SAXPY_F32, 7 AXPY_F32 (y = in2)
+      const uint64_t o = s.op == 2 ? 0 : s.out;
+      const uint64_t y = s.op == 7 ? s.in2 : 0;
+      if ((dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == 1 || s.op == 2 || s.op == 3 || s.op == 7) &&
+          s.n > 0 && s.n % 4 == 0 && s.n * 4 <= p.lds_bytes && ((s.in | o | y) & 15u) == 0) {
         if ((dflags & LKW_DF_PIN_RELOAD) || s.in != pin_addr || s.n != pin_n) {
-          pin.assign(reinterpret_cast<const float *>(s.in), reinterpret_cast<const float *>(s.in) + s.n);
+          pin.assign(reinterpret_cast<const uint32_t *>(s.in), reinterpret_cast<const uint32_t *>(s.in) + s.n);
           pin_addr = s.in;
           pin_n = s.n;
         }

@@ -443,6 +443,60 @@ def test_pinned_input_axpy_out_of_place():
         assert same_f32(o.cpu().numpy(), oracle.axpy_f32(a, x.copy(), yv.copy()))
 
 
+def _pinned_int_sequence(ctx, cluster, n, seed):
+    """AFFINE_SUM_I32 and SUM_I32_I64 with x pinned: after x changes in memory, flagged
+    items keep summing (and writing y from) the pinned copy until PIN_RELOAD.  Returns the
+    (got, want) results and the final y pair."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)
+    x0[:2] = [np.iinfo(np.int32).min, np.iinfo(np.int32).max]
+    dx = to_dev(x0)
+    dy = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    P, R = lk.DF_PIN_INPUT, lk.DF_PIN_RELOAD
+    x1 = x0 ^ np.int32(0x5A5A5A5)
+    got, want, last_y = [], [], [None]
+
+    def aff(a, b, flags, xs):
+        got.append(ctx.wait(cluster, ctx.submit(cluster, lk.OP_AFFINE_SUM_I32, x=addr(dx), y=addr(dy), a=a, b=b,
+                                                 n=n, flags=flags)))
+        last_y[0], s = oracle.affine_sum_i32(xs.copy(), a, b)
+        want.append(s)
+
+    def isum(flags, xs):
+        got.append(ctx.wait(cluster, ctx.submit(cluster, lk.OP_SUM_I32_I64, x=addr(dx), n=n, flags=flags)))
+        want.append(oracle.sum_i32_i64(xs.copy()))
+
+    aff(-3, 7, P, x0)                   # pins x0
+    dx.bitwise_xor_(0x5A5A5A5)          # x changes in memory: x1
+    torch.cuda.synchronize()
+    aff(5, -11, P, x0)                  # pinned copy
+    isum(P, x0)                         # same address and length: the copy again
+    isum(0, x1)                         # memory
+    aff(-1, 0, R, x1)                   # reload
+    isum(P, x1)
+    return got, want, dy.cpu().numpy(), last_y[0]
+
+
+@pytest.mark.parametrize("n", [4, 4100, 24576])
+def test_pinned_input_integer_ops_read_the_lds_copy_until_reload(n):
+    with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
+        say(f"pinned input, integer ops: one worker, n={n}")
+        got, want, gy, wy = _pinned_int_sequence(ctx, 0, n, seed=300 + n)
+    assert got == want
+    assert np.array_equal(gy, wy)
+
+
+def test_pinned_input_integer_ops_on_xcd_clusters():
+    n = 131084
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=20000) as ctx:
+        say(f"pinned input, integer ops: XCD clusters, n={n}")
+        res = [_pinned_int_sequence(ctx, c, n, seed=400 + c) for c in (0, ctx.info()["n_clusters"] - 1)]
+    for got, want, gy, wy in res:
+        assert got == want
+        assert np.array_equal(gy, wy)
+
+
 # ------------------------------------------------------------------ clusters = XCDs
 def test_clusters_per_xcd_split_items_and_placement():
     rng = np.random.default_rng(3)
