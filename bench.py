@@ -407,7 +407,9 @@ def bench_isolation(args):
     """Cluster isolation: 8 clusters = 8 XCDs; cluster 0 gets a critical int32 affine +
     int64 sum item over 262,144 elements every period, released by a host busy-wait, while
     clusters 1-7 copy private fp32 buffers back-to-back (interference on), idle-poll
-    (interference off) or do not exist (absent: a context whose workers are all on XCD 0)."""
+    (interference off) or do not exist (absent: a context whose workers are all on XCD 0).
+    on_pinned: interference on, the critical item's x (the same every period) kept in its
+    cluster's LDS, so the item reads nothing from memory and only writes y."""
     import torch
     from paper_2310_01212_amd import lk, workloads
 
@@ -424,6 +426,8 @@ def bench_isolation(args):
     dsts = [torch.empty_like(s) for s in srcs]
     torch.cuda.synchronize()
     crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, x.data_ptr(), y.data_ptr(), AB[:, 0], AB[:, 1])
+    crit_pinned = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, x.data_ptr(), y.data_ptr(), AB[:, 0], AB[:, 1],
+                                flags=lk.DF_PIN_INPUT)
     bg = lk.make_items(lk.OP_COPY_F32, elems, [s.data_ptr() for s in srcs], [d.data_ptr() for d in dsts])
     out = {"metric": "critical-item latency p50/p99/p99.9/max (µs) under cross-XCD interference",
            "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "int32/int64 (critical), f32 copy",
@@ -448,14 +452,15 @@ def bench_isolation(args):
         out["xcd_copy_gbps"] = round(xcd_gbps, 1)
         log(f"isolation: one XCD copies at {xcd_gbps:,.0f} GB/s")
 
-        def summarize(r, bgc):
+        def summarize(r, bgc, pinned=False):
             span = (r["info"]["t_done_max"] - r["info"]["t_pick_min"]) / wall * 1e6
             v = {"latency_us": lat_summary(r["lat_us"]), "device_span_us": lat_summary(span),
                  "release_lateness_us": lat_summary(r["late_us"]),
                  "submit_to_done_us": lat_summary(r["lat_us"] - r["late_us"]), "elapsed_s": round(r["elapsed_s"], 3)}
-            # the critical item's own bandwidth (8n + 8 bytes over its device span) against
-            # one XCD's copy ceiling
-            crit_gbps = (8 * xh.size + 8) / (float(np.median(span)) * 1e-6) / 1e9
+            # the critical item's own memory bandwidth (8n + 8 bytes, 4n + 8 with x pinned,
+            # over its device span) against one XCD's copy ceiling
+            crit_bytes = (4 if pinned else 8) * xh.size + 8
+            crit_gbps = crit_bytes / (float(np.median(span)) * 1e-6) / 1e9
             v["critical_gbps_p50"] = round(crit_gbps, 1)
             v["critical_frac_of_xcd_copy"] = round(crit_gbps / xcd_gbps, 3)
             if bgc:
@@ -468,10 +473,11 @@ def bench_isolation(args):
                                               for k in idx)
             return v
 
-        for name, bgc in (("off", []), ("on", list(range(1, 8)))):
+        for name, bgc, items in (("off", [], crit), ("on", list(range(1, 8)), crit),
+                                 ("on_pinned", list(range(1, 8)), crit_pinned)):
             log(f"isolation: interference {name}")
-            r = ctx.run_isolation(0, crit, args.period_us * 1e-6, bgc, bg[:len(bgc)])
-            out[name] = summarize(r, bgc)
+            r = ctx.run_isolation(0, items, args.period_us * 1e-6, bgc, bg[:len(bgc)])
+            out[name] = summarize(r, bgc, pinned=items is crit_pinned)
     # absent: only XCD 0's workers exist (the context's XCD mask), nothing else runs
     log("isolation: other clusters absent")
     with lk.Context(n_workers=0, xcd_mask=0x1, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=600000) as ca:

@@ -836,11 +836,13 @@ def test_isolation_runner_critical_items_and_copies_exact():
     assert np.all(r["lat_us"] > 0) and np.all(r["late_us"] < r["lat_us"])
 
 
-def test_isolation_full_size_critical_items_and_256mib_copies_exact():
+@pytest.mark.parametrize("pinned", [False, True])
+def test_isolation_full_size_critical_items_and_256mib_copies_exact(pinned):
     """The isolation workload at its full sizes: a 262,144-element critical item every
-    1 ms on XCD 0 (32 slices) while XCDs 1-7 copy private 256 MiB buffers."""
+    1 ms on XCD 0 (32 slices) while XCDs 1-7 copy private 256 MiB buffers; pinned: the
+    critical item's x kept in its members' LDS (each pins its 8,192-element slice)."""
     periods = 100
-    say(f"isolation full size: {periods} periods of 1 ms, 7 x 256 MiB copies")
+    say(f"isolation full size: {periods} periods of 1 ms, 7 x 256 MiB copies, pinned={pinned}")
     xh, AB = workloads.isolation(periods=periods)
     x = to_dev(xh)
     y = sentinel_i32(xh.shape)
@@ -848,7 +850,8 @@ def test_isolation_full_size_critical_items_and_256mib_copies_exact():
     srcs = [workloads.isolation_copy_source_device(c, elems, "cuda") for c in range(1, 8)]
     dsts = [torch.zeros_like(t) for t in srcs]
     torch.cuda.synchronize()
-    crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, addr(x), addr(y), AB[:, 0], AB[:, 1])
+    crit = lk.make_items(lk.OP_AFFINE_SUM_I32, xh.size, addr(x), addr(y), AB[:, 0], AB[:, 1],
+                         flags=lk.DF_PIN_INPUT if pinned else 0)
     bg = lk.make_items(lk.OP_COPY_F32, elems, [addr(t) for t in srcs], [addr(d) for d in dsts])
     with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=30000) as ctx:
         assert ctx.info()["n_clusters"] == 8
