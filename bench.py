@@ -62,7 +62,7 @@ def int_sum_check(x, a=None, b=None):
 
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
                  ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md",
-                  "lk_worker_allcu_saxpy_depth4_traffic.md")]
+                  "lk_worker_allcu_saxpy_depth4_traffic.md", "lk_worker_allcu_saxpy_cold_traffic.md")]
 WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h", "lk_device.h", "lk_common.h"]
 
 
@@ -81,11 +81,11 @@ def worker_source_digest(csrc=os.path.join(ROOT, "paper_2310_01212_amd", "csrc")
     return h.hexdigest()[:16]
 
 
-def traffic_per_item(n, threads_per_worker, pin_input=False, depth=1):
+def traffic_per_item(n, threads_per_worker, pin_input=False, depth=1, cold_pairs=0):
     """Memory bytes per item of the worker kernel from a committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-probe calibration); None
-    when no summary was taken for this item size, workgroup size, pinning and ring depth,
-    or the worker's sources changed since."""
+    when no summary was taken for this item size, workgroup size, pinning, ring depth and
+    operand rotation, or the worker's sources changed since."""
     import re
     for path in TRAFFIC_FILES:
         if not os.path.exists(path):
@@ -96,7 +96,8 @@ def traffic_per_item(n, threads_per_worker, pin_input=False, depth=1):
         d = json.loads(m.group(1))
         if (d.get("worker_source_digest") == worker_source_digest() and d.get("n") == n and
                 d.get("threads_per_worker", 256) == threads_per_worker and
-                bool(d.get("pin_input", False)) == bool(pin_input) and d.get("queue_depth", 1) == depth):
+                bool(d.get("pin_input", False)) == bool(pin_input) and d.get("queue_depth", 1) == depth and
+                d.get("cold_pairs", 0) == cold_pairs):
             return {"bytes_per_item": d["hbm_bytes_per_item"], "source": os.path.relpath(path, ROOT)}
     return None
 
@@ -122,6 +123,10 @@ def parse():
     ap.add_argument("--pin-input", action="store_true",
                     help="time the all-CU workload itself with x pinned in each worker's LDS "
                          "(its roofline then counts the 8n HBM bytes per item of y alone)")
+    ap.add_argument("--cold", type=int, default=0, metavar="P",
+                    help="time the all-CU workload itself in its cold form: each mailbox rotates through "
+                         "P (x, y) pairs (item k uses pair k mod P; 512 MiB in aggregate at 16), so the "
+                         "operands stream from HBM (0/1 = the headline's fixed pair)")
     ap.add_argument("--variant-per-cu", type=int, default=2,
                     help="workers per CU of the variant reported beside the one-per-CU headline (0/1 = skip)")
     ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
@@ -515,9 +520,25 @@ def bench_allcu(args):
     li = np.arange(lanes, dtype=np.uint64)[:, None]
     x_addr = x_d.data_ptr() + li * n * 4
     y_addr = y_d.data_ptr() + li * n * 4
+    cold_pairs = args.cold if args.cold > 1 else 0
+    if cold_pairs:
+        if args.pin_input:
+            sys.exit("--cold and --pin-input select different workloads; give one of them")
+        g = torch.Generator(device=dev)
+        g.manual_seed(2)
+        cx = torch.randn((lanes, cold_pairs, n), generator=g, device=dev, dtype=torch.float32)
+        cy = torch.randn((lanes, cold_pairs, n), generator=g, device=dev, dtype=torch.float32)
+        torch.cuda.synchronize()
+
+    def operands(s):
+        if not cold_pairs:
+            return x_addr, y_addr
+        pair = ((s * per + np.arange(per)) % cold_pairs).astype(np.uint64)[None, :]
+        off = (li * cold_pairs + pair) * n * 4
+        return cx.data_ptr() + off, cy.data_ptr() + off
 
     # every step's descriptors are built before any timed region
-    steps_items = [lk.make_items(lk.OP_SAXPY_F32, n, x_addr, y_addr, alpha=A[:, s * per:(s + 1) * per],
+    steps_items = [lk.make_items(lk.OP_SAXPY_F32, n, *operands(s), alpha=A[:, s * per:(s + 1) * per],
                                  flags=lk.DF_PIN_INPUT if args.pin_input else 0)
                    for s in range(args.warmup + args.steps)]
 
@@ -573,9 +594,11 @@ def bench_allcu(args):
         "dtype": "f32",
         "data": "synthetic (seeded: x, y ~ N(0,1), alpha ~ U(-2,2) per mailbox)",
         "config": {"workload": "all-CU SAXPY: one worker per CU, each mailbox fed items back-to-back" +
-                               (", x pinned in each worker's LDS" if args.pin_input else ""),
+                               (", x pinned in each worker's LDS" if args.pin_input else "") +
+                               (f", each mailbox rotating through {cold_pairs} (x, y) pairs" if cold_pairs else ""),
                    "workers": lanes, "items_per_mailbox": per * args.steps, "n": n,
                    "item_bytes": bytes_per_item, "queue_depth": args.depth, "pin_input": args.pin_input,
+                   "cold_pairs": cold_pairs,
                    "host_threads": args.threads, "threads_per_worker": args.threads_per_worker,
                    "poll_sleep": args.poll_sleep},
         "latency_us": lat_summary(lat_all),
@@ -590,7 +613,7 @@ def bench_allcu(args):
                           "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
                           "items_per_launch": session_items, "algorithmic_bytes_per_item": hbm_bytes_per_item,
                           "algorithmic_bytes": session_items * hbm_bytes_per_item}
-    tr = traffic_per_item(n, args.threads_per_worker, args.pin_input, args.depth)
+    tr = traffic_per_item(n, args.threads_per_worker, args.pin_input, args.depth, cold_pairs)
     if tr is not None:
         result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
         result["roofline"]["traffic_source"] = tr["source"]

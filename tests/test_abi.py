@@ -201,13 +201,14 @@ def test_bench_quotes_the_paper_tables_as_printed():
 
 def test_committed_traffic_profiles_match_the_worker_sources():
     """The memory-traffic summaries bench.py quotes were taken with the worker as it is now
-    (plain, pinned-input and depth-4 all-CU workloads, n = 16,384, 1024 threads per
-    worker)."""
+    (plain, pinned-input, depth-4 and cold all-CU workloads, n = 16,384, 1024 threads per
+    worker).  The cold workload streams every operand from HBM, so its traffic is the
+    12n algorithmic bytes plus the mailbox records."""
     import bench
-    for pin, depth in ((False, 1), (True, 1), (False, 4)):
-        tr = bench.traffic_per_item(16384, 1024, pin, depth)
-        assert tr is not None, f"traffic summary for pin_input={pin}, depth {depth} is stale or missing"
-        assert 8 * 16384 <= tr["bytes_per_item"] <= 12 * 16384
+    for pin, depth, cold, hi in ((False, 1, 0, 12.0), (True, 1, 0, 12.0), (False, 4, 0, 12.0), (False, 1, 16, 12.1)):
+        tr = bench.traffic_per_item(16384, 1024, pin, depth, cold)
+        assert tr is not None, f"traffic summary for pin_input={pin}, depth {depth}, cold {cold} is stale or missing"
+        assert 8 * 16384 <= tr["bytes_per_item"] <= hi * 16384
 
 
 def test_bench_percentiles_are_nearest_rank():
