@@ -111,15 +111,17 @@ typedef struct lk_desc {
  * that data, as well as work, can be placed on them, and their local memories keep data
  * next to the computation).
  *
- *  LK_DF_PIN_INPUT   a member whose pinned copy has the same slice address and length
+ *  LK_DF_PIN_INPUT   a member holding a pinned slice with the same address and length
  *                    reads x from LDS instead of memory; otherwise it reads x from memory
  *                    and keeps it.  By setting the flag the caller promises that those
  *                    bytes are unchanged since the member pinned them.
  *  LK_DF_PIN_RELOAD  as LK_DF_PIN_INPUT, but always reads x from memory and replaces the
  *                    pinned copy: use it on the first item after x has changed.
  *
- * Each worker holds one pinned slice (its raw 32-bit words, whatever the op).  Items
- * without these flags leave it in place.  lk_submit rejects a flagged item (LK_EINVAL)
+ * Each worker keeps up to 4 pinned slices (their raw 32-bit words, whatever the op), placed
+ * one after another in its LDS: a new slice goes after the others while fewer than 4 are
+ * held and all fit in lk_info.pin_capacity, otherwise it replaces all of them.  Items
+ * without these flags leave the slices in place.  lk_submit rejects a flagged item (LK_EINVAL)
  * unless: the op is one of the four above; in, the out it writes (not SUM_I32_I64's) and
  * (AXPY_F32) y are 16-byte aligned; and every member's slice is a multiple of 4 elements
  * of at most lk_info.pin_capacity bytes.  n = 0 is accepted and pins

@@ -129,6 +129,8 @@ typedef struct lkw_params {
 /* Descriptor flags, carried in bits 32..47 of LKW_W_B (same values as LK_DF_*). */
 #define LKW_DF_PIN_INPUT 0x1u
 #define LKW_DF_PIN_RELOAD 0x2u
+// Pinned slices a worker keeps at once (its LDS table: address, length, LDS offset).
+#define LKW_PIN_SLOTS 4u
 
 #define LKW_K_REPORT_WORKING 0x1u
 #define LKW_K_NO_ACQUIRE 0x2u

@@ -100,7 +100,7 @@ constexpr uint64_t kIdleExit = ~0ull;
 // The command loop of one worker (mailbox m), compiled once with the look-ahead read and
 // once without it, so a depth-1 context runs none of its bookkeeping.
 template <bool LOOK>
-__device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *lds_pin, uint64_t *s_w,
+__device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *lds_pin, uint64_t *s_pin, uint64_t *s_w,
                                       uint64_t *s_batch_next, int64_t *s_red) {
   const uint32_t tid = threadIdx.x;
   const uint64_t stride = LKW_RING_STRIDE(p.depth);
@@ -115,9 +115,6 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
   // command missed by that first read lengthens it by 2 units, one it finds shortens it
   // by 1, so the first read tends to arrive just after the host has posted.
   uint32_t pre = 8;
-  // Input held in lds_pin: device address and element count of the last pinned x
-  // (pin_n == 0: nothing pinned).
-  uint64_t pin_addr = 0, pin_n = 0;
   // Look-ahead (ring depth > 1): wave 0 reads the next slot while the current item runs,
   // so a command the host has already posted is taken without another host round trip.
   // The read is issued only when the previous item ran for at least p.la_ticks (about a
@@ -244,9 +241,13 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
                           static_cast<uint64_t>(s.a) | (static_cast<uint64_t>(s.b) << 32), s_red, s_batch_next,
                           p.threads);
     } else if (s.op != 0) {
-      // Pinned input (AXPY forms and the integer ops): x is served from LDS when this
-      // worker's last pinned copy has the same address and length, else loaded and kept.
-      // The shape check repeats the host's so LDS is never addressed past the buffer.
+      // Pinned input (AXPY forms and the integer ops): x is served from LDS when one of
+      // the worker's pinned slices has the same address and length, else loaded and kept:
+      // after the other slices while they fit together, else in place of all of them;
+      // RELOAD refills a slice in place.  The table (s_pin) is read here by every thread
+      // and written by thread 0 after the completion barrier, so no thread can see an
+      // entry whose LDS words it has not filled itself.  The shape check repeats the
+      // host's so LDS is never addressed past the buffer.
       const uint64_t ia = reinterpret_cast<uint64_t>(s.in);
       const bool axpy_form = s.op == lkd::kOpSaxpy || s.op == lkd::kOpAxpy;
       const bool int_form = s.op == lkd::kOpAffineSum || s.op == lkd::kOpSumI64;
@@ -255,18 +256,42 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
       const uint64_t ya = axpy_form ? reinterpret_cast<uint64_t>(y) : 0;
       const bool pin = (dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (axpy_form || int_form) && s.n > 0 &&
                        (s.n & 3u) == 0 && s.n * 4 <= p.lds_bytes && ((ia | oa | ya) & 15u) == 0;
-      const bool hit = pin && !(dflags & LKW_DF_PIN_RELOAD) && ia == pin_addr && s.n == pin_n;
-      int4 *lds_i = reinterpret_cast<int4 *>(lds_pin);
+      uint32_t found = LKW_PIN_SLOTS, off16 = 0;  // matching slice and its LDS offset (16-byte units)
+      uint32_t fill_slot = 0, fill_off = 0;
+      bool reset = false;
+      if (pin) {
+        for (uint32_t k = 0; k < LKW_PIN_SLOTS; ++k) {
+          const uint64_t a = uniform_u64(s_pin[2 * k]), w = uniform_u64(s_pin[2 * k + 1]);
+          if (found == LKW_PIN_SLOTS && a == ia && static_cast<uint32_t>(w) == s.n) {
+            found = k;
+            off16 = static_cast<uint32_t>(w >> 32);
+          }
+        }
+        const uint64_t fl = uniform_u64(s_pin[2 * LKW_PIN_SLOTS]);  // fill level (16-byte units) | count << 32
+        const uint32_t used = static_cast<uint32_t>(fl), count = static_cast<uint32_t>(fl >> 32);
+        if (found < LKW_PIN_SLOTS) {
+          fill_slot = found;
+          fill_off = off16;
+        } else if (count < LKW_PIN_SLOTS && used + s.n / 4 <= p.lds_bytes / 16) {
+          fill_slot = count;
+          fill_off = used;
+        } else {
+          reset = true;
+        }
+      }
+      const bool hit = found < LKW_PIN_SLOTS && !(dflags & LKW_DF_PIN_RELOAD);
+      float4 *lds_x = lds_pin + (hit ? off16 : fill_off);
+      int4 *lds_i = reinterpret_cast<int4 *>(lds_x);
       const int32_t *xi = static_cast<const int32_t *>(s.in);
       int32_t *yi = static_cast<int32_t *>(s.out);
       if (!pin) {
         partial = lkops::run_slice<lkops::SystemStore>(s, s_red, p.threads);
       } else if (axpy_form) {
         if (hit)
-          lkops::axpy_pinned<lkops::SystemStore, false>(static_cast<const float *>(s.in), lds_pin, y,
+          lkops::axpy_pinned<lkops::SystemStore, false>(static_cast<const float *>(s.in), lds_x, y,
                                                         static_cast<float *>(s.out), s.n, s.alpha, p.threads);
         else
-          lkops::axpy_pinned<lkops::SystemStore, true>(static_cast<const float *>(s.in), lds_pin, y,
+          lkops::axpy_pinned<lkops::SystemStore, true>(static_cast<const float *>(s.in), lds_x, y,
                                                        static_cast<float *>(s.out), s.n, s.alpha, p.threads);
       } else {
         int64_t acc;
@@ -278,9 +303,12 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
                     : lkops::affine_sum_pinned<false, lkops::SystemStore, true>(xi, lds_i, nullptr, s.n, 1u, 0u, p.threads);
         partial = lkops::block_sum_i64(acc, s_red, p.threads);
       }
-      if (pin && !hit) {
-        pin_addr = ia;
-        pin_n = s.n;
+      // A filled slice is recorded by thread 0 in the pending words; it enters the table
+      // after the completion barrier, once every thread has done its lookup.
+      if (tid == 0 && pin && !hit) {
+        s_pin[2 * LKW_PIN_SLOTS + 1] = ia;
+        s_pin[2 * LKW_PIN_SLOTS + 2] = (static_cast<uint64_t>(fill_off) << 32) | s.n;
+        s_pin[2 * LKW_PIN_SLOTS + 3] = 0x400u | fill_slot | (reset ? 0x100u : 0u) | (found < LKW_PIN_SLOTS ? 0x200u : 0u);
       }
     }
 
@@ -320,6 +348,24 @@ __device__ __forceinline__ void serve(const lkw_params &p, uint32_t m, float4 *l
         st_sys(&e->t_pick, t_pick);
         st_sys(&e->t_done, t_done);
       }
+      if (tid == 0) {
+        // pending word: slot | 0x100 (reset the table first) | 0x200 (refill in place) | 0x400 (valid)
+        const uint64_t pend = s_pin[2 * LKW_PIN_SLOTS + 3];
+        if (pend & 0x400u) {
+          const uint32_t k = static_cast<uint32_t>(pend) & 0xffu;
+          const uint64_t entry = s_pin[2 * LKW_PIN_SLOTS + 2];
+          const uint64_t need = (entry & 0xffffffffu) / 4;
+          if (pend & 0x100u) {
+            for (uint32_t j = 0; j < LKW_PIN_SLOTS; ++j) s_pin[2 * j + 1] = 0;
+            s_pin[2 * LKW_PIN_SLOTS] = need | (1ull << 32);
+          } else if (!(pend & 0x200u)) {
+            s_pin[2 * LKW_PIN_SLOTS] += need + (1ull << 32);
+          }
+          s_pin[2 * k] = s_pin[2 * LKW_PIN_SLOTS + 1];
+          s_pin[2 * k + 1] = entry;
+          s_pin[2 * LKW_PIN_SLOTS + 3] = 0;
+        }
+      }
     }
     seq = want;
     slot = slot_next;
@@ -336,6 +382,10 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   __shared__ uint64_t s_batch_next;
   __shared__ uint32_t s_mb;
   __shared__ int64_t s_red[lkops::kMaxWaves];
+  // Pinned-slice table: per slot the device address, then length | LDS offset (16-byte
+  // units) << 32 (length 0: empty); then the fill level (16-byte units) | count << 32;
+  // then the pending entry of the current item (address, length | offset, flags).
+  __shared__ uint64_t s_pin[2 * LKW_PIN_SLOTS + 4];
   const uint32_t tid = threadIdx.x;
 
   // Boot: claim a mailbox (only on an XCD the context uses), record the physical
@@ -344,6 +394,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
     const uint32_t xcc = read_xcc_id();
     const uint32_t m = ((p.xcc_mask >> (xcc & 31u)) & 1u) ? atomicAdd(p.claim, 1u) : ~0u;
     s_mb = m;
+    for (uint32_t j = 0; j < 2 * LKW_PIN_SLOTS + 4; ++j) s_pin[j] = 0;
     if (m < p.n_workers) {
       const uint32_t hw = read_hw_id();
       lkw_worker *wr = p.workers + m;
@@ -359,7 +410,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   if (m >= p.n_workers) return;
 
   if (p.depth > 1 && !(p.flags & LKW_K_NO_LOOKAHEAD))
-    serve<true>(p, m, lds_pin, s_w, &s_batch_next, s_red);
+    serve<true>(p, m, lds_pin, s_pin, s_w, &s_batch_next, s_red);
   else
-    serve<false>(p, m, lds_pin, s_w, &s_batch_next, s_red);
+    serve<false>(p, m, lds_pin, s_pin, s_w, &s_batch_next, s_red);
 }

@@ -236,6 +236,36 @@ static void pinned_input() {
   uint64_t t;
   CHECK(lk_submit(c, 1, &ax, x2, out, &t) == LK_OK && lk_wait(c, 1, t, 5000000000ll, nullptr) == LK_OK);
   for (uint64_t i = 0; i < n; ++i) CHECK(out[i] == std::fmaf(3.f, x2[i], yy[i]));
+  // Several slices per worker: worker 0 holds x and x2 already; two more make four, each
+  // served from its copy after x changes in memory; a fifth address resets the table,
+  // after which an earlier one is loaded again from memory.
+  {
+    alignas(64) static float xs[3][4096], old0[4096], old1[4096], old2[4096];
+    for (auto &row : xs)
+      for (float &v : row) v = u(rng);
+    run(d, xs[0]);
+    ref(0.5f, xs[0]);
+    run(d, xs[1]);
+    ref(0.5f, xs[1]);
+    memcpy(old0, xs[0], sizeof old0);
+    memcpy(old1, xs[1], sizeof old1);
+    memcpy(old2, x2, sizeof old2);
+    for (uint64_t i = 0; i < n; ++i) xs[0][i] -= 2.f, xs[1][i] *= 3.f, x2[i] += 7.f;
+    run(d, xs[1]);
+    ref(0.5f, old1);
+    run(d, x2);
+    ref(0.5f, old2);
+    run(d, xs[0]);
+    ref(0.5f, old0);
+    CHECK(memcmp(y, yr, n * 4) == 0);
+    run(d, xs[2]);  // fifth slice: the table is reset
+    ref(0.5f, xs[2]);
+    run(d, xs[0]);  // loaded again: the changed x
+    ref(0.5f, xs[0]);
+    run(d, xs[2]);  // still pinned beside it
+    ref(0.5f, xs[2]);
+    CHECK(memcmp(y, yr, n * 4) == 0);
+  }
   // The integer ops: the pinned words stand in for x in the sum and in AFFINE's y.
   alignas(64) static int32_t xi[4096], yi[4096];
   for (uint64_t i = 0; i < n; ++i) xi[i] = static_cast<int32_t>(rng());

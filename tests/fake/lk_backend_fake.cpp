@@ -115,9 +115,14 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
   lkw_cmd *ring = p.cmd + m * stride;
   lkw_status *sring = p.status + m * stride;
   uint64_t seq = 0;
-  // Model of the pinned input: one copy of x's 32-bit words per worker, up to p.lds_bytes.
-  std::vector<uint32_t> pin;
-  uint64_t pin_addr = 0, pin_n = 0;
+  // Model of the pinned input: up to LKW_PIN_SLOTS copies of x's 32-bit words per worker,
+  // placed one after another in an LDS of p.lds_bytes; a slice that does not fit after
+  // the others (or finds every slot taken) replaces all of them.
+  std::vector<uint32_t> lds(p.lds_bytes / 4);
+  struct PinSlot {
+    uint64_t addr = 0, n = 0, off = 0;  // off in 32-bit words
+  };
+  std::vector<PinSlot> pins;
   for (;;) {
     const uint64_t want = seq + 1;
     const uint32_t slot = static_cast<uint32_t>(want % p.depth);
@@ -193,12 +198,20 @@ void worker(lkw_params p, uint32_t wg, std::atomic<uint32_t> *running) {
       const uint64_t y = s.op == 7 ? s.in2 : 0;
       if ((dflags & (LKW_DF_PIN_INPUT | LKW_DF_PIN_RELOAD)) && (s.op == 1 || s.op == 2 || s.op == 3 || s.op == 7) &&
           s.n > 0 && s.n % 4 == 0 && s.n * 4 <= p.lds_bytes && ((s.in | o | y) & 15u) == 0) {
-        if ((dflags & LKW_DF_PIN_RELOAD) || s.in != pin_addr || s.n != pin_n) {
-          pin.assign(reinterpret_cast<const uint32_t *>(s.in), reinterpret_cast<const uint32_t *>(s.in) + s.n);
-          pin_addr = s.in;
-          pin_n = s.n;
+        PinSlot *hit = nullptr;
+        for (PinSlot &e : pins)
+          if (e.addr == s.in && e.n == s.n) hit = &e;
+        if (!hit || (dflags & LKW_DF_PIN_RELOAD)) {
+          if (!hit) {
+            const uint64_t used = pins.empty() ? 0 : pins.back().off + pins.back().n;
+            if (pins.size() == LKW_PIN_SLOTS || (used + s.n) * 4 > p.lds_bytes) pins.clear();
+            const uint64_t off = pins.empty() ? 0 : pins.back().off + pins.back().n;
+            pins.push_back(PinSlot{s.in, s.n, off});
+            hit = &pins.back();
+          }
+          memcpy(lds.data() + hit->off, reinterpret_cast<const void *>(s.in), s.n * 4);
         }
-        s.in = reinterpret_cast<uint64_t>(pin.data());
+        s.in = reinterpret_cast<uint64_t>(lds.data() + hit->off);
       }
       partial = run_slice(s);
       if (s.in2 && (s.op == 1 || s.op == 2)) __atomic_store_n(reinterpret_cast<int64_t *>(s.in2), partial, __ATOMIC_RELAXED);

@@ -372,6 +372,78 @@ def test_pinned_input_reads_the_lds_copy_until_reload(n):
     assert same_f32(got, want)
 
 
+def _pinned_slices_expected(cap_bytes, slots=4):
+    """Which x a flagged item computes with, under the worker's table of pinned slices: a
+    match (same address and length) is served from its copy unless RELOAD; a new slice is
+    placed after the others while fewer than `slots` are held and all fit in cap_bytes,
+    else the table is cleared first.  Returns see(addr, n, flags, memory) -> x."""
+    table = []  # [addr, n, offset in elements, copy]
+
+    def see(a, n, flags, mem):
+        e = next((t for t in table if t[0] == a and t[1] == n), None)
+        if e is not None and not flags & lk.DF_PIN_RELOAD:
+            return e[3]
+        if e is None:
+            used = table[-1][2] + table[-1][1] if table else 0
+            if len(table) == slots or (used + n) * 4 > cap_bytes:
+                table.clear()
+                used = 0
+            e = [a, n, used, None]
+            table.append(e)
+        e[3] = mem.copy()
+        return e[3]
+    return see
+
+
+@pytest.mark.parametrize("per_cu,n", [(1, 4096), (2, 6144)])
+def test_pinned_input_keeps_several_slices_per_worker(per_cu, n):
+    """Five x buffers through one worker's table of pinned slices: four 16 KiB slices stay
+    pinned together at one worker per CU; at two per CU (78 KiB) 24 KiB slices overflow
+    the capacity at the fourth.  Every x is changed in memory after it is pinned, so each
+    flagged item shows which copy it read; the y chain is exact against the oracle's over
+    the x each item should see."""
+    rng = np.random.default_rng(500 + n)
+    X = rng.standard_normal((5, n)).astype(np.float32)
+    y0 = rng.standard_normal(n).astype(np.float32)
+    dX, dy = to_dev(X), to_dev(y0)
+    P, R = lk.DF_PIN_INPUT, lk.DF_PIN_RELOAD
+    mem = X.copy()
+    seq = []
+    with lk.Context(n_workers=1, workers_per_cu=per_cu, threads=1024 // per_cu, idle_timeout_ms=20000) as ctx:
+        cap = ctx.info()["pin_capacity"]
+        see = _pinned_slices_expected(cap)
+        say(f"pinned slices: {per_cu} per CU, capacity {cap}, n={n}")
+
+        def run(k, flags, alpha):
+            t = ctx.submit(0, lk.OP_SAXPY_F32, x=addr(dX[k]), y=addr(dy), alpha=alpha, n=n, flags=flags)
+            ctx.wait(0, t)
+            xs = see(addr(dX[k]), n, flags, mem[k]) if flags else mem[k].copy()
+            seq.append((xs, np.float32(alpha)))
+
+        def change(k, v):
+            dX[k].add_(v)
+            torch.cuda.synchronize()
+            mem[k] = mem[k] + np.float32(v)
+
+        for k in range(4):
+            run(k, P, 0.5 + k)
+        for k in range(5):
+            change(k, 1.0 + k)
+        for k in (3, 1, 0, 2):
+            run(k, P, -0.75)
+        run(1, 0, 1.25)                 # unflagged: memory
+        run(4, P, 0.25)                 # a fifth slice
+        run(0, P, -1.5)
+        run(4, P, 2.0)
+        change(4, -3.0)
+        run(4, R, 0.5)                  # reload in place
+        run(4, P, -0.5)
+    want = y0.copy()
+    oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=xs, out=want, alpha=a) for xs, a in seq])
+    torch.cuda.synchronize()
+    assert same_f32(dy.cpu().numpy(), want)
+
+
 def test_pinned_input_refuses_shapes_the_buffer_cannot_take():
     with lk.Context(n_workers=1, idle_timeout_ms=20000) as ctx:
         cap = ctx.info()["pin_capacity"]
