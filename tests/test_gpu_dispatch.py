@@ -354,7 +354,7 @@ def _pinned_sequence(ctx, cluster, n, seed):
     run(dx, al[4], R)                   # reload: x1
     run(dx, al[5], P)                   # x1
     run(dx2, al[6], P)                  # another address: x2
-    run(dx, al[7], P)                   # back: x1 reloaded
+    run(dx, al[7], P)                   # back: x1 (its slice is still held)
     want = y0.copy()
     oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=xs, out=want, alpha=a)
                      for xs, a in zip([x0, x0, x1, x0, x1, x1, x2, x1], al)])
