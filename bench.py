@@ -62,7 +62,8 @@ def int_sum_check(x, a=None, b=None):
 
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
                  ("lk_worker_allcu_saxpy_traffic.md", "lk_worker_allcu_saxpy_pinned_traffic.md",
-                  "lk_worker_allcu_saxpy_depth4_traffic.md", "lk_worker_allcu_saxpy_cold_traffic.md")]
+                  "lk_worker_allcu_saxpy_depth4_traffic.md", "lk_worker_allcu_saxpy_cold_traffic.md",
+                  "lk_worker_allcu_saxpy_cold_depth4_traffic.md")]
 WORKER_SOURCES = ["lk_worker.hip", "lk_ops.hpp", "lk_devutil.hpp", "lk_wire.h", "lk_device.h", "lk_common.h"]
 
 

@@ -205,7 +205,8 @@ def test_committed_traffic_profiles_match_the_worker_sources():
     worker).  The cold workload streams every operand from HBM, so its traffic is the
     12n algorithmic bytes plus the mailbox records."""
     import bench
-    for pin, depth, cold, hi in ((False, 1, 0, 12.0), (True, 1, 0, 12.0), (False, 4, 0, 12.0), (False, 1, 16, 12.1)):
+    for pin, depth, cold, hi in ((False, 1, 0, 12.0), (True, 1, 0, 12.0), (False, 4, 0, 12.0), (False, 1, 16, 12.1),
+                                 (False, 4, 16, 12.1)):
         tr = bench.traffic_per_item(16384, 1024, pin, depth, cold)
         assert tr is not None, f"traffic summary for pin_input={pin}, depth {depth}, cold {cold} is stale or missing"
         assert 8 * 16384 <= tr["bytes_per_item"] <= hi * 16384
