@@ -730,6 +730,12 @@ def bench_allcu(args):
                 cold[cd] = {"queue_depth": cd, "items_per_s": round(clat.size / ct, 1), "latency_us": lat_summary(clat),
                             "kernel_ms": round(cinfo["device_span_ms"], 3), "items_per_launch": c_items,
                             "achieved_gbps": round(c_gbps, 1), "frac_of_peak": round(c_gbps / HBM_PEAK_GBPS, 4)}
+                # measured memory bytes per item, from the committed counter summary of the
+                # same workload (bench.py --cold P --depth d) when one matches
+                ctr = traffic_per_item(n, args.threads_per_worker, False, cd, P)
+                if ctr is not None:
+                    cold[cd]["traffic_bytes_per_item"] = ctr["bytes_per_item"]
+                    cold[cd]["traffic_source"] = ctr["source"]
                 log(f"cold ({P} pairs per mailbox, depth {cd}): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
             del cx, cy
             result["cold_variant"] = {"pairs_per_mailbox": P, "footprint_bytes": lanes * P * n * 8, **cold[1]}
