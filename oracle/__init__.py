@@ -14,7 +14,7 @@ What each piece follows in the paper:
     or several clusters; ``orc_exec_cluster`` splits an item into per-member slices.
   * The item bodies (int32 affine mod 2^32 + int64 sum, int64 sum, fp32 fma SAXPY,
     fp32 copy) are the evaluation workloads' items; the paper's only item is a
-    compute-only loop (Sec. 3).
+    compute-only loop (Sec. 3), ``orc_spin``: no memory effect, result 0.
 """
 import ctypes
 import os
@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, AXPY_F32 = 0, 1, 2, 3, 4, 7
+NOP, AFFINE_SUM_I32, SUM_I32_I64, SAXPY_F32, COPY_F32, SPIN, AXPY_F32 = 0, 1, 2, 3, 4, 5, 7
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",
           "-shared", "-fPIC"]
@@ -68,6 +68,8 @@ def lib():
         L.orc_axpy_f32.restype = None
         L.orc_copy_f32.argtypes = [P, P, ctypes.c_uint64]
         L.orc_copy_f32.restype = None
+        L.orc_spin.argtypes = [ctypes.c_int32]
+        L.orc_spin.restype = ctypes.c_int64
         L.orc_slice.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.orc_slice.restype = None
@@ -138,6 +140,11 @@ def copy_f32(src, dst=None):
     return dst
 
 
+def spin(iters):
+    """The paper's compute-only item: returns its result (0); -1 for a negative count."""
+    return int(lib().orc_spin(int(iters)))
+
+
 def slice_bounds(n, k, j):
     lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
     lib().orc_slice(n, k, j, ctypes.byref(lo), ctypes.byref(hi))
@@ -175,7 +182,7 @@ def run_fifo(items):
     res = np.zeros(len(items), dtype=np.int64)
     rc = lib().orc_run_fifo(arr, len(items), _ptr(res))
     if rc != 0:
-        raise ValueError("unknown op in item list")
+        raise ValueError("unknown op, or a negative SPIN count, in item list")
     return res
 
 

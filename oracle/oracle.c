@@ -45,6 +45,11 @@ void orc_copy_f32(const float *in, float *out, uint64_t n) {
   for (uint64_t i = 0; i < n; i++) out[i] = in[i];
 }
 
+/* The paper's benchmark item (Sec. 3): a loop of `iters` iterations with no memory
+ * traffic.  Its iterations leave no trace in memory and it returns no value, so as a
+ * work item it has no memory effect and result 0. */
+int64_t orc_spin(int32_t iters) { return iters < 0 ? -1 : 0; }
+
 /* A stage that triggers several clusters' cores (Sec. 3) gives each member one
  * contiguous slice; slice lengths are rounded up to whole 256-element groups. */
 void orc_slice(uint64_t n, uint32_t k, uint32_t j, uint64_t *lo, uint64_t *hi) {
@@ -79,6 +84,9 @@ static int64_t exec_range(const orc_item *it, uint64_t lo, uint64_t hi) {
     case ORC_AXPY_F32:
       orc_axpy_f32((const float *)it->in + lo, (const float *)it->in2 + lo, (float *)it->out + lo, len, it->alpha);
       return 0;
+    case ORC_SPIN:
+      /* every member of a cluster runs the whole loop; the item touches none of its range */
+      return 0;
     default:
       return 0;
   }
@@ -101,7 +109,8 @@ int64_t orc_exec_cluster(const orc_item *it, uint32_t k) {
  * each exactly once. */
 int orc_run_fifo(const orc_item *items, uint64_t count, int64_t *results) {
   for (uint64_t i = 0; i < count; i++) {
-    if (items[i].op > ORC_COPY_F32 && items[i].op != ORC_AXPY_F32) return -1;
+    if (items[i].op > ORC_SPIN && items[i].op != ORC_AXPY_F32) return -1;
+    if (items[i].op == ORC_SPIN && orc_spin(items[i].a) < 0) return -1;
     int64_t r = orc_exec(&items[i]);
     if (results) results[i] = r;
   }

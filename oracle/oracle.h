@@ -16,7 +16,10 @@
  *   - the work-item bodies themselves are not defined by the paper (its only item is
  *     a compute-only loop, Sec. 3); they are the evaluation workloads' items:
  *     int32 affine map modulo 2^32 followed by an int64 sum, an int64 sum of int32,
- *     fp32 y = alpha*x + y with one fused multiply-add, and an fp32 copy.
+ *     fp32 y = alpha*x + y with one fused multiply-add, and an fp32 copy;
+ *   - Sec. 3: the paper's own work item is a compute-only loop of a given number of
+ *     iterations that touches no memory; to the dispatch loop it is an item with no
+ *     memory effect whose result is 0.
  */
 #ifndef LK_ORACLE_H
 #define LK_ORACLE_H
@@ -28,7 +31,7 @@ extern "C" {
 
 /* Work-item operation identifiers as the oracle numbers them (its own numbering). */
 enum { ORC_NOP = 0, ORC_AFFINE_SUM_I32 = 1, ORC_SUM_I32_I64 = 2, ORC_SAXPY_F32 = 3, ORC_COPY_F32 = 4,
-       ORC_AXPY_F32 = 7 };
+       ORC_SPIN = 5, ORC_AXPY_F32 = 7 };
 
 /* y[i] = (a*x[i] + b) mod 2^32, read as two's complement; returns sum of (int64)y[i]. */
 int64_t orc_affine_sum_i32(const int32_t *x, int32_t *y, uint64_t n, int32_t a, int32_t b);
@@ -41,6 +44,10 @@ void orc_saxpy_f32(const float *x, float *y, uint64_t n, float alpha);
 void orc_axpy_f32(const float *x, const float *y, float *out, uint64_t n, float alpha);
 /* out[i] = in[i], bit for bit. */
 void orc_copy_f32(const float *in, float *out, uint64_t n);
+/* The paper's compute-only item (Sec. 3): `iters` loop iterations (iters >= 0) that read
+ * and write no memory; what the loop computes is discarded, so the item's whole observable
+ * effect is its result, 0.  Returns 0, or -1 for a negative count. */
+int64_t orc_spin(int32_t iters);
 
 /* Slice j of an n-element item split over k workers of one cluster:
  * m = ceil(n/k) rounded up to a multiple of 256; slice j = [min(n, j*m), min(n, (j+1)*m)). */
@@ -50,7 +57,7 @@ void orc_slice(uint64_t n, uint32_t k, uint32_t j, uint64_t *lo, uint64_t *hi);
 typedef struct {
   uint32_t op;
   uint64_t n;
-  int32_t a, b;
+  int32_t a, b;  /* SPIN: a = iterations */
   float alpha;
   const void *in;
   void *out;
@@ -64,7 +71,7 @@ int64_t orc_exec(const orc_item *it);
 int64_t orc_exec_cluster(const orc_item *it, uint32_t k);
 /* Sequential specification of one mailbox: execute items[0..count) in submission order,
  * each exactly once; results[i] receives item i's int64 result. Returns 0, or -1 on an
- * unknown op (execution stops at that item). */
+ * unknown op or a SPIN item with a negative count (execution stops at that item). */
 int orc_run_fifo(const orc_item *items, uint64_t count, int64_t *results);
 /* One element of a SAXPY chain: y <- fmaf(alphas[k], x, y) for k = 0..count-1. */
 float orc_saxpy_chain_elem(float x, float y, const float *alphas, uint64_t count);

@@ -260,3 +260,59 @@ def test_out_of_place_axpy_matches_brute_force_and_leaves_y():
     got = np.empty_like(y)
     oracle.exec_item(oracle.AXPY_F32, inp=x, out=got, in2=y, alpha=np.float32(0.5))
     assert np.array_equal(_bits(got), _bits(np.array(brute.saxpy(np.float32(0.5), x, y), np.float32)))
+
+
+# ---------------------------------------------------------------- the paper's compute-only item
+SENT_WORD = 0x7FBADBAD
+
+
+@pytest.mark.parametrize("iters", [0, 1, 20000, 2 ** 31 - 1])
+def test_spin_item_leaves_memory_untouched_and_returns_zero(iters):
+    """Sec. 3: the benchmark item loops without memory traffic.  Given in/out references
+    and a length anyway, it must leave both buffers bit for bit as they were, whole or
+    sliced over a cluster, and its result is 0."""
+    inp = np.full(1000, SENT_WORD, np.uint32).view(np.float32)
+    out = np.full(1000, SENT_WORD ^ 0xFFFF, np.uint32).view(np.float32)
+    assert oracle.spin(iters) == 0
+    assert oracle.exec_item(oracle.SPIN, inp=inp, out=out, a=iters) == 0
+    assert oracle.exec_cluster(oracle.SPIN, 7, inp=inp, out=out, a=iters) == 0
+    assert np.all(inp.view(np.uint32) == SENT_WORD)
+    assert np.all(out.view(np.uint32) == (SENT_WORD ^ 0xFFFF))
+
+
+def test_spin_and_nop_inside_a_saxpy_fifo_change_nothing():
+    """A mailbox FIFO of SAXPY items with SPIN and NOP items between them (pointing at the
+    same x and y) leaves y equal to the brute-force chain of the SAXPY items alone; the
+    SPIN and NOP results are 0, and the chain stays order-sensitive."""
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(16).astype(np.float32)
+    y0 = rng.standard_normal(16).astype(np.float32)
+    alphas = rng.uniform(-2, 2, 12).astype(np.float32)
+    items, kinds = [], []
+    y = y0.copy()
+    for k, a in enumerate(alphas):
+        items.append(dict(op=oracle.SAXPY_F32, inp=x, out=y, alpha=a))
+        kinds.append("saxpy")
+        extra = oracle.SPIN if k % 2 == 0 else oracle.NOP
+        items.append(dict(op=extra, inp=x, out=y, n=x.size, a=20000, alpha=np.float32(3.0)))
+        kinds.append("other")
+    res = oracle.run_fifo(items)
+    want = []
+    for i in range(x.size):
+        v = y0[i]
+        for a in alphas:
+            v = brute.fma_f32(a, x[i], v)
+        want.append(v)
+    assert np.array_equal(_bits(y), _bits(np.array(want, np.float32)))
+    assert all(r == 0 for r, kd in zip(res, kinds) if kd == "other")
+    yr = y0.copy()
+    oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=x, out=yr, alpha=a) for a in alphas[::-1]])
+    assert not np.array_equal(_bits(yr), _bits(y))
+
+
+def test_fifo_rejects_negative_spin_counts_and_non_items():
+    assert oracle.spin(-1) == -1
+    for bad in (dict(op=oracle.SPIN, n=0, a=-5), dict(op=6, n=0), dict(op=8, n=0)):
+        with pytest.raises(ValueError):
+            oracle.run_fifo([dict(op=oracle.NOP, n=0), bad])
+    assert oracle.run_fifo([dict(op=oracle.SPIN, n=0, a=0)]).tolist() == [0]
