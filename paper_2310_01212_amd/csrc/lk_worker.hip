@@ -41,15 +41,19 @@ using namespace lkdev;
 // claim for the next tile is issued before the current tile runs so that the atomic's
 // round trip overlaps the tile's own loads.  Returns (in thread 0) the number of tiles
 // this member executed.
+// The claimed index travels through two LDS words used in turn (s_next[0] for the first
+// tile, then alternating): thread 0 writes the index of iteration i + 1 while a wave that
+// fell behind may still be reading that of iteration i, and the barrier that ends every
+// iteration keeps thread 0 from coming back to a word before every wave has read it.
 __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_tiles, int64_t *partials,
                                              uint64_t *counter, uint64_t base, int64_t *s_red, uint64_t *s_next,
                                              uint32_t nt) {
   int64_t executed = 0;
   if (threadIdx.x == 0)
-    *s_next = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) - base;
+    s_next[0] = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) - base;
   __syncthreads();
-  for (;;) {
-    const uint64_t t = uniform_u64(*s_next);
+  for (uint32_t par = 0;; par ^= 1u) {
+    const uint64_t t = uniform_u64(s_next[par]);
     if (t >= n_tiles) break;
     const lkd::Tile tile = tiles[t];
     uint64_t next = 0;
@@ -67,7 +71,7 @@ __device__ __forceinline__ int64_t run_batch(const lkd::Tile *tiles, uint64_t n_
     const int64_t part = lkops::run_slice<lkops::SystemStore>(sl, s_red, nt);
     if (threadIdx.x == 0) {
       st_sys_i64(partials + t, part);
-      *s_next = next - base;
+      s_next[par ^ 1u] = next - base;
     }
     ++executed;
     __syncthreads();
@@ -379,7 +383,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   // Command words broadcast by wave 0; word 0 holds kIdleExit instead of the doorbell
   // when the idle watchdog fired, so one batch of LDS reads tells every wave what to do.
   __shared__ __align__(16) uint64_t s_w[LKW_CMD_WORDS];
-  __shared__ uint64_t s_batch_next;
+  __shared__ uint64_t s_batch_next[2];
   __shared__ uint32_t s_mb;
   __shared__ int64_t s_red[lkops::kMaxWaves];
   // Pinned-slice table: per slot the device address, then length | LDS offset (16-byte
@@ -410,7 +414,7 @@ extern "C" __global__ void __launch_bounds__(1024) lk_worker(lkw_params p) {
   if (m >= p.n_workers) return;
 
   if (p.depth > 1 && !(p.flags & LKW_K_NO_LOOKAHEAD))
-    serve<true>(p, m, lds_pin, s_pin, s_w, &s_batch_next, s_red);
+    serve<true>(p, m, lds_pin, s_pin, s_w, s_batch_next, s_red);
   else
-    serve<false>(p, m, lds_pin, s_pin, s_w, &s_batch_next, s_red);
+    serve<false>(p, m, lds_pin, s_pin, s_w, s_batch_next, s_red);
 }
