@@ -90,7 +90,7 @@ class ServeConfig(ctypes.Structure):
 
 class ServeStats(ctypes.Structure):
     _fields_ = [("elapsed_s", ctypes.c_double), ("tiles", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
-                ("peak_bytes", ctypes.c_uint64)]
+                ("peak_bytes", ctypes.c_uint64), ("posted", ctypes.c_uint64), ("drained", ctypes.c_uint64)]
 
 
 REQUEST_DTYPE = np.dtype([("arrival_us", "<f8"), ("op", "<u4"), ("a", "<i4"), ("b", "<i4"), ("alpha", "<f4"),
@@ -153,7 +153,7 @@ def lib():
         "lkb_serial": (ctypes.c_int, [P, U32, P, U64, I64, P, P, P, P]),
         "lkb_lanes": (ctypes.c_int, [P, P, U32, P, U64, U32, U32, I64, P, P, PD, P]),
         "lkb_isolation": (ctypes.c_int, [P, U32, P, U64, I64, P, U32, P, P, P, P, P, P, PD]),
-        "lkb_replay": (ctypes.c_int, [I32, U32, U32, U32, P, P, P, P]),
+        "lkb_replay": (ctypes.c_int, [I32, U32, U32, U32, P, P, P, P, P]),
         "lkb_batch": (ctypes.c_int, [P, U32, P, U32, P, U32, I64, P, P]),
         "lkb_launch_burst": (ctypes.c_int, [I32, P, U32, U64, U32, U32, U32, P]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
@@ -230,6 +230,42 @@ def _check_tensor(t, op, what):
         raise ValueError(f"{what} must be {want}, got {t.dtype}")
 
 
+_READS_X = (OP_AFFINE_SUM_I32, OP_SUM_I32_I64, OP_SAXPY_F32, OP_COPY_F32, OP_AXPY_F32)
+_WRITES_Y = (OP_AFFINE_SUM_I32, OP_SAXPY_F32, OP_COPY_F32, OP_AXPY_F32)
+
+
+def submit_extent(op, n, x=None, y=None, aux=None, members=1):
+    """Element count of an item given as tensors (or addresses), checked against their
+    extent: n defaults to x's (else y's) element count; a tensor x the op reads, a tensor y
+    it writes (SAXPY_F32 also reads it) or a tensor aux holding AXPY_F32's y must hold at
+    least n elements, and a tensor aux receiving per-member int64 results at least
+    `members` of them, else ValueError.  Bare integer addresses are not checked."""
+    def size(t):
+        return None if t is None or isinstance(t, int) else int(t.numel())
+    if n is None:
+        ref = x if x is not None else y
+        n = size(ref) or 0
+    n = int(n)
+    if n < 0:
+        raise ValueError(f"n = {n} < 0")
+    sx, sy, sa = size(x), size(y), size(aux)
+    if n and op in _READS_X and sx is not None and n > sx:
+        raise ValueError(f"n = {n} exceeds x's {sx} elements")
+    if n and op in _WRITES_Y and sy is not None and n > sy:
+        raise ValueError(f"n = {n} exceeds y's {sy} elements")
+    if op == OP_AXPY_F32 and sa is not None:
+        if str(aux.dtype) != "torch.float32":
+            raise ValueError(f"aux (y of AXPY_F32) must be float32, got {aux.dtype}")
+        if n > sa:
+            raise ValueError(f"n = {n} exceeds aux's {sa} elements (y of AXPY_F32)")
+    if op in (OP_AFFINE_SUM_I32, OP_SUM_I32_I64) and sa is not None:
+        if str(aux.dtype) != "torch.int64":
+            raise ValueError(f"aux (per-member results) must be int64, got {aux.dtype}")
+        if members > sa:
+            raise ValueError(f"aux holds {sa} results, the cluster has {members} members")
+    return n
+
+
 class Context:
     """A running LightKernel context (lk_init): persistent workers, workers_per_cu on each
     CU of the XCDs named by xcd_mask (0 = every XCD), grouped into clusters; depth ring
@@ -264,6 +300,7 @@ class Context:
             cfg.cluster_of_worker = cow.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
         else:
             cfg.cluster_policy = clusters
+        self._sizes = None
         self._h = ctypes.c_void_p()
         rc = L.lk_init(ctypes.byref(cfg), ctypes.byref(self._h))
         if rc != OK:
@@ -275,14 +312,23 @@ class Context:
         self._closed = False
 
     # -- phases ---------------------------------------------------------------------------
+    def _cluster_size(self, cluster):
+        if self._sizes is None:
+            self._sizes = {}
+        if cluster not in self._sizes:
+            self._sizes[cluster] = len(self.members(cluster))
+        return self._sizes[cluster]
+
     def submit(self, cluster, op, x=None, y=None, a=0, b=0, alpha=0.0, n=None, aux=None, flags=0):
         """Trigger: post one item; returns its ticket.  Raises LKError(EAGAIN) if full.
-        flags: DF_PIN_INPUT / DF_PIN_RELOAD (keep x in the members' LDS across items)."""
+        flags: DF_PIN_INPUT / DF_PIN_RELOAD (keep x in the members' LDS across items).
+        Raises ValueError when a tensor given for x, y or aux is too short for n (the C ABI
+        receives bare addresses and cannot check their extent)."""
         _check_tensor(x, op, "x")
         _check_tensor(y, op, "y")
-        if n is None:
-            ref = x if x is not None else y
-            n = 0 if ref is None else (ref.numel() if not isinstance(ref, int) else 0)
+        k = self._cluster_size(cluster) if (aux is not None and not isinstance(aux, int)
+                                            and op in (OP_AFFINE_SUM_I32, OP_SUM_I32_I64)) else 1
+        n = submit_extent(op, n, x, y, aux, k)
         d = Desc(op, flags, n, _i32(a), _i32(b), float(np.float32(alpha)), 0, _ptr(aux) or 0, 0)
         t = ctypes.c_uint64()
         rc = lib().lk_submit(self._h, cluster, ctypes.byref(d), _ptr(x), _ptr(y), ctypes.byref(t))
@@ -528,14 +574,18 @@ REPLAY_PHASES_LK = ("Init", "Trigger", "Wait", "Dispose")
 REPLAY_PHASES_HIP = ("Alloc", "Spawn", "Wait", "Dispose")
 
 
-def replay(n_workers, spin_iters=20000, runs=100, device=0):
-    """The paper's phase protocol; returns (lk_us, hip_us, lk_cycles, hip_cycles), each (runs, 4)."""
+def replay(n_workers, spin_iters=20000, runs=100, device=0, with_results=False):
+    """The paper's phase protocol; returns (lk_us, hip_us, lk_cycles, hip_cycles), each (runs, 4),
+    plus the (runs, 2) item results (persistent, per-launch) when with_results is set."""
     lk_us = np.zeros((runs, 4), np.float64)
     hip_us = np.zeros((runs, 4), np.float64)
     lk_cy = np.zeros((runs, 4), np.uint64)
     hip_cy = np.zeros((runs, 4), np.uint64)
+    res = np.full((runs, 2), -1, np.int64)
     _check(lib().lkb_replay(device, n_workers, spin_iters, runs, _np_ptr(lk_us), _np_ptr(hip_us),
-                            _np_ptr(lk_cy), _np_ptr(hip_cy)), "lkb_replay")
+                            _np_ptr(lk_cy), _np_ptr(hip_cy), _np_ptr(res)), "lkb_replay")
+    if with_results:
+        return lk_us, hip_us, lk_cy, hip_cy, res
     return lk_us, hip_us, lk_cy, hip_cy
 
 

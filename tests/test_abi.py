@@ -59,6 +59,17 @@ def test_struct_layouts_match_the_c_headers(tmp_path):
     assert got == want
     assert lk.LOG_DTYPE.itemsize == ctypes.sizeof(lk.LogEntry)
     assert lk.COMPLETION_DTYPE.itemsize == ctypes.sizeof(lk.Completion)
+    # the serving structures (lk_serve.h)
+    src2 = tmp_path / "serve_sizes.c"
+    src2.write_text('#include "lk_serve.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lks_request), sizeof(lks_config),'
+                    ' sizeof(lks_outcome), sizeof(lks_stats), offsetof(lks_stats, posted), offsetof(lks_stats, drained));'
+                    ' return 0;}\n')
+    exe2 = tmp_path / "serve_sizes"
+    subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, "-o", str(exe2), str(src2)])
+    got2 = [int(v) for v in subprocess.check_output([str(exe2)]).split()]
+    assert got2 == [lk.REQUEST_DTYPE.itemsize, ctypes.sizeof(lk.ServeConfig), lk.OUTCOME_DTYPE.itemsize,
+                    ctypes.sizeof(lk.ServeStats), lk.ServeStats.posted.offset, lk.ServeStats.drained.offset]
 
 
 def _wire_defines():
@@ -182,6 +193,42 @@ def test_make_items_marshals_int32_and_addresses():
     assert lk._i32(2 ** 31) == -2 ** 31 and lk._i32(-1) == -1
 
 
+def test_submit_rejects_n_beyond_the_tensors_extent():
+    """Context.submit passes bare addresses to lk_submit, which cannot see a buffer's end;
+    the binding checks n against every tensor it was given before anything is posted."""
+    torch = pytest.importorskip("torch")
+    xi = torch.zeros(100, dtype=torch.int32)
+    xf = torch.zeros(100, dtype=torch.float32)
+    short_f = torch.zeros(60, dtype=torch.float32)
+    # defaults and in-range counts
+    assert lk.submit_extent(lk.OP_SAXPY_F32, None, xf, xf) == 100
+    assert lk.submit_extent(lk.OP_SUM_I32_I64, None, xi) == 100
+    assert lk.submit_extent(lk.OP_SAXPY_F32, 60, xf, short_f) == 60
+    assert lk.submit_extent(lk.OP_AXPY_F32, 60, xf, short_f, aux=short_f) == 60
+    assert lk.submit_extent(lk.OP_NOP, 0) == 0
+    assert lk.submit_extent(lk.OP_SAXPY_F32, 10 ** 9, 0x1000, 0x2000) == 10 ** 9  # bare addresses
+    # n past x, past y, past AXPY's y (aux)
+    with pytest.raises(ValueError, match="x's"):
+        lk.submit_extent(lk.OP_AFFINE_SUM_I32, 101, xi, torch.zeros(200, dtype=torch.int32))
+    with pytest.raises(ValueError, match="y's"):
+        lk.submit_extent(lk.OP_SAXPY_F32, 100, xf, short_f)
+    with pytest.raises(ValueError, match="y's"):
+        lk.submit_extent(lk.OP_COPY_F32, None, xf, short_f)
+    with pytest.raises(ValueError, match="aux"):
+        lk.submit_extent(lk.OP_AXPY_F32, 100, xf, xf, aux=short_f)
+    with pytest.raises(ValueError, match="float32"):
+        lk.submit_extent(lk.OP_AXPY_F32, 10, xf, xf, aux=xi)
+    # per-member int64 results: one per member of the cluster
+    res = torch.zeros(4, dtype=torch.int64)
+    assert lk.submit_extent(lk.OP_AFFINE_SUM_I32, 100, xi, xi, aux=res, members=4) == 100
+    with pytest.raises(ValueError, match="members"):
+        lk.submit_extent(lk.OP_SUM_I32_I64, 100, xi, aux=res, members=8)
+    with pytest.raises(ValueError, match="int64"):
+        lk.submit_extent(lk.OP_SUM_I32_I64, 100, xi, aux=xi, members=1)
+    with pytest.raises(ValueError):
+        lk.submit_extent(lk.OP_SUM_I32_I64, -1, xi)
+
+
 def test_bench_quotes_the_paper_tables_as_printed():
     import bench
     golden = {}
@@ -199,17 +246,32 @@ def test_bench_quotes_the_paper_tables_as_printed():
     assert seen == len(golden) == 24
 
 
-def test_committed_traffic_profiles_match_the_worker_sources():
-    """The memory-traffic summaries bench.py quotes were taken with the worker as it is now
-    (plain, pinned-input, depth-4 and cold all-CU workloads, n = 16,384, 1024 threads per
-    worker).  The cold workload streams every operand from HBM, so its traffic is the
-    12n algorithmic bytes plus the mailbox records."""
+def test_committed_traffic_profiles_are_used_only_while_they_match_the_worker():
+    """bench.py quotes the memory traffic of a committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes) only while the worker's sources hash to the digest recorded in it;
+    a summary taken with another worker gives no traffic figure (null).  A current summary
+    of the all-CU SAXPY workload (n = 16,384, 1024 threads) lies between the y-only bytes
+    (8n) and the algorithmic 12n plus the mailbox records."""
+    import json
     import bench
-    for pin, depth, cold, hi in ((False, 1, 0, 12.0), (True, 1, 0, 12.0), (False, 4, 0, 12.0), (False, 1, 16, 12.1),
-                                 (False, 4, 16, 12.1)):
-        tr = bench.traffic_per_item(16384, 1024, pin, depth, cold)
-        assert tr is not None, f"traffic summary for pin_input={pin}, depth {depth}, cold {cold} is stale or missing"
-        assert 8 * 16384 <= tr["bytes_per_item"] <= hi * 16384
+    digest = bench.worker_source_digest()
+    seen = 0
+    for path in bench.TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        assert m, f"{path}: no json block"
+        d = json.loads(m.group(1))
+        seen += 1
+        tr = bench.traffic_per_item(d["n"], d.get("threads_per_worker", 256), d.get("pin_input", False),
+                                    d.get("queue_depth", 1), d.get("cold_pairs", 0))
+        if d.get("worker_source_digest") != digest:
+            assert tr is None or tr["source"] != os.path.relpath(path, ROOT), path
+            continue
+        assert tr is not None and d["n"] == 16384
+        hi = 12.1 if d.get("cold_pairs", 0) else 12.0
+        assert 8 * 16384 <= tr["bytes_per_item"] <= hi * 16384, path
+    assert seen > 0
 
 
 def test_bench_percentiles_are_nearest_rank():
