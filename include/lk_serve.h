@@ -67,16 +67,26 @@ typedef struct lks_outcome {
 
 typedef struct lks_stats {
   double elapsed_s;       /* first arrival to last completion */
-  uint64_t tiles;         /* tiles executed */
+  uint64_t tiles;         /* tiles whose completion the schedulers took */
   uint64_t deferred;      /* admissions that had to wait for memory */
   uint64_t peak_bytes;    /* peak output memory in use, summed over shards */
+  uint64_t posted;        /* tiles posted */
+  uint64_t drained;       /* tiles waited for after an error stopped the run (posted =
+                             tiles + drained whenever lks_run returns with the context
+                             still running) */
 } lks_stats;
 
 /* Serve `count` requests on a running context whose clusters are one worker each
  * (LK_CLUSTERS_PER_WORKER).  Requests must be sorted by arrival time.  Fills out[i] for
  * every request and *stats.  Errors: LK_EINVAL (bad arguments, a request that can never
  * fit its shard's budget, or -- with retain -- a budget exhausted for good), errors of
- * lk_submit / lk_wait, LK_ETIMEDOUT. */
+ * lk_submit / lk_wait, LK_ETIMEDOUT.
+ * When a scheduler stops on an error, every scheduler stops and first waits for the tiles
+ * it has posted (each for max(timeout_ns, 1 s), or without a deadline when timeout_ns < 0),
+ * so that on return no tile of the run still reads or writes memory.  If a tile does not
+ * finish in that time, lks_run disposes the context (lk_dispose) before returning: either
+ * the workers end, or the context is left poisoned (lk_get_info state 2), in which case the
+ * arena and the request buffers may still be written by the GPU and must stay allocated. */
 LK_API int lks_run(lk_ctx *ctx, const lks_config *cfg, const lks_request *reqs, uint64_t count,
                    lks_outcome *out, lks_stats *stats);
 

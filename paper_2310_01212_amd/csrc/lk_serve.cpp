@@ -68,7 +68,8 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
   const uint64_t slice = cfg->arena_bytes / T / kGranule * kGranule;
   const uint32_t depth = info.queue_depth;
   std::atomic<int> error{LK_OK};
-  std::vector<uint64_t> tiles_done(T, 0), deferred(T, 0), peak(T, 0);
+  std::vector<uint64_t> tiles_done(T, 0), deferred(T, 0), peak(T, 0), tiles_posted(T, 0), tiles_drained(T, 0);
+  std::atomic<uint32_t> undrained{0};
   // The arrival clock starts only once every shard has built its tables (they are sized
   // by the trace and page-faulted in while being filled), so that set-up is not charged
   // to the first requests as queueing.
@@ -96,13 +97,12 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
     uint64_t finished = 0;
     uint64_t last_deferred = ~0ull;  // the waiting head already counted as deferred
     uint32_t rr = 0;
-    auto fail = [&](int rc) {
-      int expected = LK_OK;
-      error.compare_exchange_strong(expected, rc);
-    };
     ready.fetch_add(1, std::memory_order_acq_rel);
     while (t0_ns.load(std::memory_order_acquire) == 0) _mm_pause();
-    while (finished < mine.size() && error.load(std::memory_order_relaxed) == LK_OK) {
+    // One pass of the scheduler: arrivals, admission, completions, dispatch.  Returns
+    // LK_OK or the error that ends this shard; every way out of the loop below reaches the
+    // drain after it.
+    auto step = [&]() -> int {
       const auto now = clk::now();
       const double now_us = us_since(now);
       // 1. arrivals
@@ -114,11 +114,11 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
         uint64_t addr = 0;
         const uint64_t need = out_bytes(r);
         if (need) {
-          if (Arena::round(need) > arena.size()) return fail(LK_EINVAL);  // can never fit
+          if (Arena::round(need) > arena.size()) return LK_EINVAL;  // can never fit
           if (!arena.alloc(need, &addr)) {
             // Nothing in flight in this shard means nothing will ever be freed: the
             // budget is exhausted for good (possible only with `retain`).
-            if (n_active == 0) return fail(LK_EINVAL);
+            if (n_active == 0) return LK_EINVAL;
             if (i != last_deferred) {
               ++deferred[s];
               last_deferred = i;
@@ -149,10 +149,10 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           const int rc = lk_try_wait(c, workers[w], pq.front().ticket, &ci);
           if (rc == LK_EAGAIN) {
             if (cfg->timeout_ns >= 0 && now - pq.front().t_post > std::chrono::nanoseconds(cfg->timeout_ns))
-              return fail(LK_ETIMEDOUT);
+              return LK_ETIMEDOUT;
             break;
           }
-          if (rc) return fail(rc);
+          if (rc) return rc;
           const int64_t part = ci.result;
           const uint64_t i = pq.front().req;
           pq.pop_front();
@@ -187,18 +187,39 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           uint64_t t;
           const int rc = lk_submit(c, workers[w], &d, reinterpret_cast<const void *>(in), reinterpret_cast<void *>(o), &t);
           if (rc == LK_EAGAIN) break;
-          if (rc) return fail(rc);
+          if (rc) return rc;
           posted[w].push_back(Posted{t, tl.req, clk::now()});
+          ++tiles_posted[s];
           queue.pop_front();
         }
       }
       rr = workers.empty() ? 0 : (rr + 1) % workers.size();
+      return LK_OK;
+    };
+    while (finished < mine.size() && error.load(std::memory_order_relaxed) == LK_OK) {
+      const int rc = step();
+      if (rc != LK_OK) {
+        int expected = LK_OK;
+        error.compare_exchange_strong(expected, rc);
+        break;
+      }
       _mm_pause();
     }
     peak[s] = arena.peak();
-    // On error, drain what this shard still has posted so its workers are idle.
+    // After an error (this shard's or another's) tiles may still be posted: wait for each
+    // of them, so that no tile of this run still reads or writes memory when lks_run
+    // returns.  A tile that does not finish within the drain deadline is left to the
+    // caller-visible fallback below (disposing the context).
+    const int64_t drain_ns = cfg->timeout_ns >= 0 ? std::max<int64_t>(cfg->timeout_ns, 1000000000ll) : -1;
     for (size_t w = 0; w < workers.size(); ++w)
-      for (const Posted &p : posted[w]) (void)lk_wait(c, workers[w], p.ticket, 2000000000ll, nullptr);
+      for (const Posted &p : posted[w]) {
+        const int rc = lk_wait(c, workers[w], p.ticket, drain_ns, nullptr);
+        if (rc == LK_ETIMEDOUT) {
+          undrained.fetch_add(1, std::memory_order_relaxed);
+          break;  // later tickets of this worker run after it: none of them finished either
+        }
+        if (rc == LK_OK) ++tiles_drained[s];
+      }
   };
   std::vector<std::thread> th;
   for (uint32_t s = 0; s < T; ++s) th.emplace_back(shard, s);
@@ -206,16 +227,26 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
   t0 = clk::now() + std::chrono::milliseconds(2);
   t0_ns.store(std::max<int64_t>(1, t0.time_since_epoch().count()), std::memory_order_release);
   for (auto &t : th) t.join();
-  const int rc = error.load();
+  int rc = error.load();
+  if (undrained.load() != 0) {
+    // A posted tile did not finish within the drain deadline and may still touch the
+    // arena or the request buffers: dispose the context, which either ends the workers
+    // (every tile done) or leaves the context poisoned (lk_get_info state 2), telling the
+    // caller that this memory may still be written.
+    (void)lk_dispose(c);
+    if (rc == LK_OK) rc = LK_ETIMEDOUT;
+  }
   if (stats) {
     double last = 0;
     for (uint64_t i = 0; i < count; ++i) last = std::max(last, out[i].done_us);
     stats->elapsed_s = (last - (count ? reqs[0].arrival_us : 0.0)) * 1e-6;
-    stats->tiles = stats->deferred = stats->peak_bytes = 0;
+    stats->tiles = stats->deferred = stats->peak_bytes = stats->posted = stats->drained = 0;
     for (uint32_t s = 0; s < T; ++s) {
       stats->tiles += tiles_done[s];
       stats->deferred += deferred[s];
       stats->peak_bytes += peak[s];
+      stats->posted += tiles_posted[s];
+      stats->drained += tiles_drained[s];
     }
   }
   if (rc)

@@ -493,6 +493,64 @@ static void serving() {
   printf("OK %s\n", g_case);
 }
 
+// Serving stopped by an error: one worker hangs, its scheduler times out, every scheduler
+// stops, and lks_run returns only once the tiles already posted have finished (the hung
+// worker is released 600 ms in, after the 200 ms timeout has fired): posted = taken +
+// drained, and the context is still running and usable afterwards.
+static void serving_error_drains() {
+  g_case = "serving_error_drains";
+  lk_ctx *c = open_ctx(8, 4, LK_CLUSTERS_PER_WORKER);
+  const uint32_t count = 64;
+  const uint64_t n = 20000;
+  std::vector<std::vector<int32_t>> xs(count, std::vector<int32_t>(n));
+  std::vector<lks_request> req(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    for (uint64_t k = 0; k < n; ++k) xs[i][k] = static_cast<int32_t>(k * 2654435761u + i);
+    memset(&req[i], 0, sizeof req[i]);
+    req[i].arrival_us = 0.0;
+    req[i].op = LK_OP_SUM_I32_I64;
+    req[i].n = n;
+    req[i].in = reinterpret_cast<uint64_t>(xs[i].data());
+  }
+  lks_config cfg;
+  memset(&cfg, 0, sizeof cfg);
+  cfg.tile_elems = 4096;
+  cfg.threads = 4;
+  cfg.timeout_ns = 200000000ll;
+  std::vector<lks_outcome> out(count);
+  lks_stats st;
+  std::atomic<bool> released{false};
+  lkfake_freeze(3);
+  std::thread unfreeze([&] {
+    std::this_thread::sleep_for(std::chrono::milliseconds(600));
+    released.store(true);
+    lkfake_freeze(-1);
+  });
+  const int rc = lks_run(c, &cfg, req.data(), count, out.data(), &st);
+  const bool after_release = released.load();
+  unfreeze.join();
+  CHECK(rc == LK_ETIMEDOUT);
+  CHECK(after_release);
+  CHECK(st.posted > 0 && st.drained > 0 && st.posted == st.tiles + st.drained);
+  for (uint32_t i = 0; i < count; ++i) {
+    if (out[i].status != LK_OK) continue;
+    int64_t sr = 0;
+    for (int32_t v : xs[i]) sr += v;
+    CHECK(out[i].result == sr);
+  }
+  lk_info info;
+  CHECK(lk_get_info(c, &info) == LK_OK && info.state == 0);
+  for (uint32_t cl = 0; cl < 8; ++cl) {
+    lk_desc nop = desc(LK_OP_NOP, 0);
+    uint64_t t;
+    CHECK(lk_submit(c, cl, &nop, nullptr, nullptr, &t) == LK_OK);
+    CHECK(lk_wait(c, cl, t, 5000000000ll, nullptr) == LK_OK);
+  }
+  CHECK(lk_dispose(c) == LK_OK);
+  lk_free(c);
+  printf("OK %s\n", g_case);
+}
+
 // Idle watchdog: workers leave after the idle timeout; later calls see ESTATE.
 static void idle_watchdog() {
   g_case = "idle_watchdog";
@@ -614,6 +672,7 @@ int main() {
   cluster_split();
   batch_tiles();
   serving();
+  serving_error_drains();
   idle_watchdog();
   dispose_in_flight();
   dispose_hung_worker();

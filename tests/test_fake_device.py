@@ -2,7 +2,8 @@
 workers that speak the same mailbox protocol (tests/fake/lk_backend_fake.cpp), built with
 ThreadSanitizer and with AddressSanitizer + UBSan: exactly-once and FIFO under concurrent
 clusters, ring-full, bad arguments, a hung worker (timeout, then recovery), disposed
-state, cluster slicing, batches, serving with retained outputs, the idle watchdog,
+state, cluster slicing, batches, serving with retained outputs, serving stopped by a hung
+worker (posted tiles drained before it returns), the idle watchdog,
 dispose with items in flight, dispose of a hung worker and the CU reservation.  No GPU involved."""
 import os
 import shutil
@@ -16,7 +17,7 @@ SOURCES = [os.path.join(ROOT, "tests", "fake", "fake_device_test.cpp"),
            os.path.join(ROOT, "tests", "fake", "lk_backend_fake.cpp"),
            os.path.join(CSRC, "lk_host.cpp"), os.path.join(CSRC, "lk_serve.cpp")]
 SCENARIOS = ["single_worker_1000", "concurrent_clusters", "error_paths", "pinned_input", "cluster_split", "batch_tiles",
-             "serving", "idle_watchdog", "dispose_in_flight", "dispose_hung_worker", "cu_reservation", "xcd_mask"]
+             "serving", "serving_error_drains", "idle_watchdog", "dispose_in_flight", "dispose_hung_worker", "cu_reservation", "xcd_mask"]
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
