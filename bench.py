@@ -130,8 +130,9 @@ def parse():
                          "operands stream from HBM (0/1 = the headline's fixed pair)")
     ap.add_argument("--variant-per-cu", type=int, default=2,
                     help="workers per CU of the variant reported beside the one-per-CU headline (0/1 = skip)")
-    ap.add_argument("--threads", type=int, default=max(1, min(14, (os.cpu_count() or 2) - 2)),
-                    help="host feeder threads (one producer per mailbox)")
+    ap.add_argument("--threads", type=int, default=None,
+                    help="host feeder threads (one producer per mailbox; default: every host CPU but two, "
+                         "at most 14)")
     ap.add_argument("--poll-sleep", type=int, default=0)
     ap.add_argument("--baseline-steps", type=int, default=1, help="steps timed for each baseline")
     ap.add_argument("--streams", type=int, default=4, help="HIP streams of the per-launch baseline")
@@ -155,7 +156,11 @@ def parse():
     ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
     ap.add_argument("--period-us", type=float, default=1000.0)
     ap.add_argument("--copy-mib", type=int, default=256, help="isolation: interference buffer size")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.threads is None:
+        from paper_2310_01212_amd import workloads
+        args.threads = workloads.feeder_threads()
+    return args
 
 
 def main():

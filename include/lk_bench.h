@@ -82,9 +82,12 @@ LK_API int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit,
  * SPIN item on n_workers workgroups), Wait (stream synchronisation), Dispose (stream
  * destruction + hipFree).
  * Phase r*4 + {0,1,2,3} of each output: microseconds (lk_us, hip_us) and host
- * time-stamp-counter cycles (lk_cycles, hip_cycles); any output may be NULL. */
+ * time-stamp-counter cycles (lk_cycles, hip_cycles); results[2r] and results[2r + 1]
+ * receive run r's item result on the persistent and on the per-launch path (the sum over
+ * its workers / workgroups; the compute-only item's result is 0), read outside the timed
+ * phases; any output may be NULL. */
 LK_API int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t runs, double *lk_us,
-               double *hip_us, uint64_t *lk_cycles, uint64_t *hip_cycles);
+               double *hip_us, uint64_t *lk_cycles, uint64_t *hip_cycles, int64_t *results);
 
 /* Batches: `reps` times, post one batch of n_tiles device tiles to `cluster` and wait for
  * it; makespan_us[r] = lk_submit_batch start to lk_wait return; info (nullable) = the

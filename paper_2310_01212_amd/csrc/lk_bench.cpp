@@ -8,6 +8,7 @@
 #include <pthread.h>
 #include <sched.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -383,7 +384,7 @@ int lkb_isolation(lk_ctx *c, uint32_t crit_cluster, const lkb_item *crit, uint64
 }
 
 int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t runs, double *lk_us, double *hip_us,
-               uint64_t *lk_cycles, uint64_t *hip_cycles) {
+               uint64_t *lk_cycles, uint64_t *hip_cycles, int64_t *results) {
   if (runs == 0 || n_workers == 0 || n_workers > LK_MAX_WORKERS) return bfail(LK_EINVAL, "bad runs/n_workers");
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
@@ -420,12 +421,14 @@ int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t run
     b = clk::now();
     record(lk_us, lk_cycles, r, 1, a, b, ca, cb);
     if (rc == LK_OK) {
+      int64_t res = 0;
       a = clk::now();
       ca = __rdtsc();
-      rc = lk_wait(c, 0, t, 10000000000ll, nullptr);
+      rc = lk_wait(c, 0, t, 10000000000ll, &res);
       cb = __rdtsc();
       b = clk::now();
       record(lk_us, lk_cycles, r, 2, a, b, ca, cb);
+      if (results) results[2ull * r] = res;
     }
     a = clk::now();
     ca = __rdtsc();
@@ -441,13 +444,15 @@ int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t run
     hipStream_t s = nullptr;
     a = clk::now();
     ca = __rdtsc();
-    e = hipMalloc(&buf, 4096);
+    const size_t buf_bytes = std::max<size_t>(4096, 8ull * n_workers);  // one int64 result per workgroup
+    e = hipMalloc(&buf, buf_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     cb = __rdtsc();
     b = clk::now();
     if (e != hipSuccess) return bfail(LK_EHIP, "replay alloc: %s", hipGetErrorString(e));
     record(hip_us, hip_cycles, r, 0, a, b, ca, cb);
     lkd::ItemArgs ia = item_args(spin_item, n_workers);
+    ia.aux = static_cast<int64_t *>(buf);
     a = clk::now();
     ca = __rdtsc();
     e = lkd::launch_item(ia, 256, s);
@@ -462,6 +467,14 @@ int lkb_replay(int device, uint32_t n_workers, uint32_t spin_iters, uint32_t run
     b = clk::now();
     record(hip_us, hip_cycles, r, 2, a, b, ca, cb);
     if (e != hipSuccess) return bfail(LK_EHIP, "replay wait: %s", hipGetErrorString(e));
+    if (results) {  // the item's result, summed over its workgroups (not timed)
+      std::vector<int64_t> parts(n_workers);
+      e = hipMemcpy(parts.data(), buf, 8ull * n_workers, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return bfail(LK_EHIP, "replay result copy: %s", hipGetErrorString(e));
+      int64_t sum = 0;
+      for (int64_t v : parts) sum += v;
+      results[2ull * r + 1] = sum;
+    }
     a = clk::now();
     ca = __rdtsc();
     (void)hipStreamDestroy(s);

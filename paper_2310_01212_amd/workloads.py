@@ -12,6 +12,11 @@ import numpy as np
 PLAIN_ITEMS, PLAIN_N = 1000, 4096
 # all CUs: one worker per CU, 10,000 SAXPY items per mailbox over 16,384 fp32
 ALLCU_ITEMS, ALLCU_N = 10000, 16384
+# ... fed as the benchmark does: workers of 1024 threads (four wave64 per SIMD), ring
+# depth 1 (4 in the pipelined form), and in the cold form each mailbox rotating through
+# 16 (x, y) pairs (512 MiB in all, more than the 256 MB Infinity Cache)
+ALLCU_THREADS, ALLCU_PIPELINED_DEPTH, ALLCU_COLD_PAIRS = 1024, 4, 16
+
 # batching: bursts of uneven items, log-uniform 256 .. 2^20 elements, affine / SAXPY 50/50
 BATCH_SIZES = (1, 4, 16, 64, 256, 1024, 4096)
 BATCH_LOG2_RANGE = (8, 20)
@@ -22,6 +27,13 @@ SERVE_LOG2_RANGE = (8, 22)
 # cluster isolation: critical int32 affine+sum over 262,144 elements, 1 ms period;
 # interference: 256 MiB fp32 copies on the other clusters
 ISO_N, ISO_PERIOD_S, ISO_COPY_ELEMS = 262144, 1e-3, (256 << 20) // 4
+
+
+def feeder_threads(cpus=None):
+    """Host threads feeding the all-CU mailboxes: every host CPU but two, at most 14."""
+    import os
+    cpus = os.cpu_count() if cpus is None else cpus
+    return max(1, min(14, (cpus or 2) - 2))
 
 
 def uniform_i32(rng, shape):

@@ -4,6 +4,7 @@ Each test prints the case it runs (seed, shape, entry point) before touching the
 While a context is open nothing here calls a device-wide synchronisation: results are
 read after close(), or through an independent stream (the visibility test).
 """
+import os
 import time
 
 import numpy as np
@@ -301,29 +302,136 @@ def test_several_workers_per_cu_fifo_chains_bit_exact(per_cu, threads):
     assert counts.size == lanes // per_cu and np.all(counts == per_cu)
 
 
-def test_all_cus_full_size_sampled_elements():
-    """256 mailboxes x 10,000 back-to-back SAXPY items of 16,384 fp32; final y of 64
-    sampled elements per lane against the oracle's 10,000-step fma chain."""
-    with lk.Context(n_workers=0, depth=1) as ctx:
-        lanes = ctx.info()["n_workers"]
-        say(f"all CUs full size: {lanes} lanes x {workloads.ALLCU_ITEMS} items x {workloads.ALLCU_N}")
-        X, Y0, A, span = _allcu_setup(ctx, workloads.ALLCU_ITEMS, lambda w: workloads.ALLCU_N)
-        x, y = to_dev(X), to_dev(Y0)
-        torch.cuda.current_stream().synchronize()
-        li = np.arange(lanes, dtype=np.uint64)[:, None]
-        items = lk.make_items(lk.OP_SAXPY_F32, workloads.ALLCU_N, addr(x) + li * span * 4,
-                              addr(y) + li * span * 4, alpha=A)
-        t0 = time.time()
-        res, lat, el = ctx.run_lanes(np.arange(lanes), items, in_flight=1, threads=8, timeout=30.0)
-        say(f"  {lanes * workloads.ALLCU_ITEMS / el:.0f} items/s, p50 {np.percentile(lat, 50):.2f} us, "
-            f"wall {time.time() - t0:.2f} s")
-    Y = y.cpu().numpy()
-    rng = np.random.default_rng(77)
+def _oracle_lane_chains(X, Y0, A, pair_of_item=None):
+    """Final y of every lane (and pair) under the oracle's FIFO executor, lanes spread over
+    host threads (the executor is plain C and releases the interpreter while it runs)."""
+    import concurrent.futures as cf
+    lanes = X.shape[0]
+
+    def lane(w):
+        if pair_of_item is None:
+            yr = Y0[w].copy()
+            oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, X[w], yr, A[w]))
+            return yr
+        out = Y0[w].copy()
+        for p in range(X.shape[1]):
+            oracle.run_packed(oracle.pack_chain(oracle.SAXPY_F32, X[w, p], out[p], A[w][pair_of_item == p]))
+        return out
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lane, range(lanes)))
+
+
+@pytest.mark.parametrize("depth,items", [(1, workloads.ALLCU_ITEMS), (workloads.ALLCU_PIPELINED_DEPTH, 3000)])
+def test_all_cus_full_size_every_element_in_the_bench_launch_configuration(depth, items):
+    """The all-CU workload exactly as the benchmark launches it: one worker of 1024
+    threads per CU, ring depth 1 (and the pipelined depth 4), 16,384-element SAXPY items
+    fed back-to-back by the same native runner and host thread count, operands laid out
+    contiguously per lane.  Every element of every lane's final y against the oracle's
+    FIFO chain of that lane's alphas (the chain is order-sensitive, so this also checks
+    that each mailbox ran its items once each, in order)."""
+    n, threads, feeders = workloads.ALLCU_N, workloads.ALLCU_THREADS, workloads.feeder_threads()
+    lanes = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"all CUs full size, bench launch configuration: {lanes} workers x {threads} threads, depth {depth}, "
+        f"{items} SAXPY items of {n} per mailbox, {feeders} feeder threads")
+    X = np.empty((lanes, n), np.float32)
+    Y0 = np.empty((lanes, n), np.float32)
+    A = np.empty((lanes, items), np.float32)
     for w in range(lanes):
-        idx = np.unique(np.concatenate([[0, workloads.ALLCU_N - 1], rng.integers(0, workloads.ALLCU_N, 62)]))
-        for i in idx:
-            want = oracle.saxpy_chain_elem(X[w, i], Y0[w, i], A[w])
-            assert Y[w, i].view(np.uint32) == np.float32(want).view(np.uint32), (w, i)
+        X[w], Y0[w], A[w] = workloads.allcu_lane(w, items=items, n=n)
+    x, y = to_dev(X), to_dev(Y0)
+    li = np.arange(lanes, dtype=np.uint64)[:, None]
+    its = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * n * 4, addr(y) + li * n * 4, alpha=A)
+    with lk.Context(n_workers=lanes, depth=depth, threads=threads, poll_sleep=0, idle_timeout_ms=60000) as ctx:
+        t0 = time.time()
+        res, lat, el = ctx.run_lanes(np.arange(lanes), its, in_flight=depth, threads=feeders, timeout=30.0)
+        say(f"  {lanes * items / el:.0f} items/s, p50 {np.percentile(lat, 50):.2f} us, wall {time.time() - t0:.2f} s")
+    assert not res.any()
+    Y = y.cpu().numpy()
+    want = _oracle_lane_chains(X, Y0, A)
+    for w in range(lanes):
+        assert np.array_equal(Y[w].view(np.uint32), want[w].view(np.uint32)), w
+
+
+@pytest.mark.parametrize("depth", [1, workloads.ALLCU_PIPELINED_DEPTH])
+def test_all_cus_cold_form_full_size_every_element(depth):
+    """The cold form of the all-CU workload as the benchmark runs it: every mailbox rotates
+    through 16 (x, y) pairs of 16,384 fp32 (512 MiB in all, drawn on the device by the same
+    seeded generator), item k using pair k mod 16, 48 items per lane; every element of
+    every pair's final y against the oracle's chain of that pair's alphas."""
+    n, P, items = workloads.ALLCU_N, workloads.ALLCU_COLD_PAIRS, 48
+    threads, feeders = workloads.ALLCU_THREADS, workloads.feeder_threads()
+    lanes = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"all CUs cold form: {lanes} workers x {threads} threads, depth {depth}, {P} pairs x {n} per mailbox, "
+        f"{items} items per mailbox")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2)
+    cx = torch.randn((lanes, P, n), generator=g, device="cuda", dtype=torch.float32)
+    cy = torch.randn((lanes, P, n), generator=g, device="cuda", dtype=torch.float32)
+    X, Y0 = cx.cpu().numpy(), cy.cpu().numpy()
+    A = np.stack([workloads.allcu_lane(w, items=items, n=n)[2] for w in range(lanes)])
+    pair = (np.arange(items) % P).astype(np.uint64)
+    li = np.arange(lanes, dtype=np.uint64)[:, None]
+    off = (li * P + pair[None, :]) * n * 4
+    its = lk.make_items(lk.OP_SAXPY_F32, n, addr(cx) + off, addr(cy) + off, alpha=A)
+    torch.cuda.synchronize()
+    with lk.Context(n_workers=lanes, depth=depth, threads=threads, poll_sleep=0, idle_timeout_ms=60000) as ctx:
+        ctx.run_lanes(np.arange(lanes), its, in_flight=depth, threads=feeders, timeout=30.0)
+    Y = cy.cpu().numpy()
+    want = _oracle_lane_chains(X, Y0, A, pair_of_item=pair)
+    for w in range(lanes):
+        for p in range(P):
+            assert np.array_equal(Y[w, p].view(np.uint32), want[w][p].view(np.uint32)), (w, p)
+
+
+# ------------------------------------------------------------------ the paper's compute-only item
+def test_spin_and_nop_items_leave_memory_untouched_and_match_the_oracle():
+    """SPIN (the paper's compute-only item, Sec. 3) and NOP given sentinel-filled buffers
+    as in/out: on one worker, on an XCD cluster of 32 members, inside a batch and as
+    per-launch kernels, the buffers keep every sentinel word and the results equal the
+    oracle's; in a FIFO with SAXPY items on one y, the final y equals the oracle's run of
+    the same list, SPIN and NOP included."""
+    n = 4096 + 37
+    say(f"SPIN/NOP with sentinel buffers of {n}: 1 worker, XCD cluster, batch, per-launch")
+    sx, sy = sentinel_f32(n), sentinel_i32(n)
+    torch.cuda.synchronize()
+    spin_it = lk.make_items([lk.OP_SPIN, lk.OP_NOP, lk.OP_SPIN], n, addr(sx), addr(sy), a=[20000, 0, 0])
+    want = [oracle.exec_item(oracle.SPIN, n=n, a=20000), oracle.exec_item(oracle.NOP, n=n),
+            oracle.exec_item(oracle.SPIN, n=n, a=0)]
+    rng = np.random.default_rng(43)
+    xf = rng.standard_normal(n).astype(np.float32)
+    y0 = rng.standard_normal(n).astype(np.float32)
+    al = rng.uniform(-2, 2, 6).astype(np.float32)
+    dx, dy = to_dev(xf), to_dev(y0)
+    ops = [lk.OP_SAXPY_F32, lk.OP_SPIN, lk.OP_SAXPY_F32, lk.OP_NOP, lk.OP_SAXPY_F32, lk.OP_SPIN]
+    mix = lk.make_items(ops, n, addr(dx), addr(dy), a=[0, 5000, 0, 0, 0, 1], alpha=al)
+    with lk.Context(n_workers=1, log_capacity=64) as ctx:
+        res, _, _, _ = ctx.run_serial(0, spin_it)
+        assert res.tolist() == want
+        mres, _, _, _ = ctx.run_serial(0, mix)
+    yr = y0.copy()
+    ores = oracle.run_fifo([dict(op=int(o), inp=xf, out=yr, alpha=a, a=int(k), n=n)
+                            for o, a, k in zip(ops, al, mix["a"])])
+    assert mres.tolist() == ores.tolist()
+    assert same_f32(dy.cpu().numpy(), yr)
+    codes = [lk.CODE_WORK + lk.OP_SPIN, lk.CODE_WORK + lk.OP_NOP, lk.CODE_WORK + lk.OP_SPIN]
+    assert ctx.log(0)["code"][:3].tolist() == codes
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD) as ctx:
+        k = len(ctx.members(0))
+        for it, w in zip(spin_it, want):
+            t = ctx.submit(0, int(it["op"]), x=addr(sx), y=addr(sy), a=int(it["a"]), n=n)
+            assert ctx.wait(0, t) == oracle.exec_cluster(int(it["op"]), k, n=n, a=int(it["a"])) == w
+        tiles, _ = lk.batch_plan(spin_it, 1024)
+        d = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
+        part = torch.full((tiles.size,), -7, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        ctx.run_batch(0, d, tiles.size, part, reps=1)
+    assert not part.cpu().numpy().any()
+    for mode in (lk.COMPLETE_SYNC, lk.COMPLETE_FLAG):
+        lres, _, _ = lk.launch_serial(spin_it, k=4, mode=mode)
+        assert lres.tolist() == want
+    torch.cuda.synchronize()
+    assert torch.all(sx.view(torch.int32) == SENT_F32_BITS) and torch.all(sy == SENT_I32)
 
 
 # ------------------------------------------------------------------ pinned input (x in LDS)
@@ -941,11 +1049,14 @@ def test_isolation_full_size_critical_items_and_256mib_copies_exact(pinned):
 def test_replay_protocol_runs_on_one_cu_and_all_cus():
     say("replay: 3 runs of Init/Trigger/Wait/Dispose vs Alloc/Spawn/Wait/Dispose, SPIN 20000")
     for nw in (1, torch.cuda.get_device_properties(0).multi_processor_count):
-        lk_us, hip_us, lk_cy, hip_cy = lk.replay(nw, 20000, 3)
+        lk_us, hip_us, lk_cy, hip_cy, res = lk.replay(nw, 20000, 3, with_results=True)
         assert np.all(lk_us > 0) and np.all(hip_us > 0)
         assert np.all(lk_cy > 0) and np.all(hip_cy > 0)
         # the loop dominates Wait; Trigger is a few host stores
         assert np.all(lk_us[:, 1] < lk_us[:, 2])
+        # the item's result on both paths, summed over the nw workers, is the oracle's
+        want = oracle.exec_cluster(oracle.SPIN, nw, n=0, a=20000)
+        assert np.all(res == want), res
 
 
 # ------------------------------------------------------------------ batches
