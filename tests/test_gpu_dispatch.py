@@ -40,12 +40,16 @@ def to_dev(a):
     return t
 
 
+def _shape(shape):
+    return (shape,) if isinstance(shape, int) else tuple(shape)
+
+
 def sentinel_i32(shape):
-    return torch.full(shape, SENT_I32, dtype=torch.int32, device="cuda")
+    return torch.full(_shape(shape), SENT_I32, dtype=torch.int32, device="cuda")
 
 
 def sentinel_f32(shape):
-    return torch.full(shape, SENT_F32_BITS, dtype=torch.int32, device="cuda").view(torch.float32)
+    return torch.full(_shape(shape), SENT_F32_BITS, dtype=torch.int32, device="cuda").view(torch.float32)
 
 
 def addr(t, elem_offset=0):
