@@ -22,6 +22,7 @@
 #include "lk_affinity.hpp"
 #include "lk_bench.h"
 #include "lk_device.h"
+#include "lk_error.h"
 
 namespace {
 
@@ -31,8 +32,6 @@ inline double us_between(clk::time_point a, clk::time_point b) {
   return std::chrono::duration<double, std::micro>(b - a).count();
 }
 
-thread_local std::string g_err;
-
 int bfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int bfail(int code, const char *fmt, ...) {
   char buf[512];
@@ -40,7 +39,7 @@ int bfail(int code, const char *fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  lkh::set_last_error(buf);
   fprintf(stderr, "lk_bench: %s\n", buf);
   return code;
 }

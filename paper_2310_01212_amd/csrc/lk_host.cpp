@@ -26,6 +26,7 @@
 #include "lk.h"
 #include "lk_backend.h"
 #include "lk_common.h"
+#include "lk_error.h"
 #include "lk_wire.h"
 
 namespace {
@@ -43,6 +44,11 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+void lkh::set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+
+namespace {
 
 using clk = std::chrono::steady_clock;
 
