@@ -16,6 +16,7 @@
  *                       Alloc/Spawn/Wait/Dispose) with its compute-only item;
  *   - lkb_launch_serial one ordinary kernel launch per item (the paper's spawn path),
  *                       optionally through a single-node hipGraph relaunched per item;
+ *                       lkb_launch_serial_static is its form that allocates nothing;
  *   - lkb_launch_lanes  the lanes workload with one launch (or graph launch) per item;
  *   - lkb_pingpong      the bare host<->device echo: the floor of any mailbox round trip;
  *   - lkb_copy          streaming-copy bandwidth: the HBM roofline, and the known-size
@@ -115,6 +116,19 @@ LK_API int lkb_launch_burst(int device, const lkb_item *items, uint32_t count, u
  * lat_us[i] = launch start to completion observed; launch_us[i] = the launch call. */
 LK_API int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb_item *items, uint64_t count,
                       uint32_t mode, int64_t *results, double *lat_us, double *launch_us);
+
+/* Allocation-free form of lkb_launch_serial with mode LKB_COMPLETE_SYNC, for callers that
+ * cannot allocate (loops or harnesses in which hipMalloc, hipHostMalloc and stream
+ * creation are not allowed).  Same items, grid, slicing, results and timings; instead of
+ * a stream and a host-coherent partial-result array created per call, the launches go to
+ * the null stream and the k per-workgroup partials go to a static device array of the
+ * library (32 KiB per GPU, held until the process ends), read back with hipMemcpy after
+ * each item's stream synchronisation (outside lat_us).  k is limited to 1..4096
+ * (LK_EINVAL beyond, with nothing launched).  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on the same GPU, from any threads, race on it and
+ * their results are undefined. */
+LK_API int lkb_launch_serial_static(int device, uint32_t k, uint32_t threads, const lkb_item *items,
+                                    uint64_t count, int64_t *results, double *lat_us, double *launch_us);
 
 /* The lanes workload with one launch per item: lane l runs on stream l % n_streams, one
  * item in flight per lane, completion observed through the flag form, host thread

@@ -23,6 +23,7 @@
 #include "lk_bench.h"
 #include "lk_device.h"
 #include "lk_error.h"
+#include "lk_scratch.h"
 
 namespace {
 
@@ -627,6 +628,48 @@ int lkb_launch_serial(int device, uint32_t k, uint32_t threads, const lkb_item *
   (void)hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
   return rc;
+}
+
+int lkb_launch_serial_static(int device, uint32_t k, uint32_t threads, const lkb_item *items, uint64_t count,
+                             int64_t *results, double *lat_us, double *launch_us) {
+  if (!items && count) return bfail(LK_EINVAL, "NULL items");
+  if (k == 0 || k > lkd::kStaticMaxK)
+    return bfail(LK_EINVAL, "k = %u workgroups: the static partial-result array holds 1..%u", k, lkd::kStaticMaxK);
+  if (threads < 64 || threads > 1024 || threads % 64) return bfail(LK_EINVAL, "bad threads");
+  for (uint64_t i = 0; i < count; ++i)
+    if (!valid_item(items[i])) return bfail(LK_EINVAL, "item %llu invalid", static_cast<unsigned long long>(i));
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  int64_t *partials = nullptr;
+  if ((e = lkd::static_partials(device, &partials)) != hipSuccess)
+    return bfail(LK_EHIP, "static scratch address: %s", hipGetErrorString(e));
+  // The null stream, so that nothing is created; every entry 0..k-1 of the array is
+  // written by workgroup j of each launch before it is read, so nothing is cleared.
+  hipStream_t s = nullptr;
+  constexpr uint32_t kChunk = 512;  // partials read back in chunks through a stack buffer
+  int64_t buf[kChunk];
+  for (uint64_t i = 0; i < count; ++i) {
+    lkd::ItemArgs a = item_args(items[i], k);
+    a.partials = partials;
+    const auto t0 = clk::now();
+    e = lkd::launch_item(a, threads, s);
+    const auto t1 = clk::now();
+    if (e != hipSuccess) return bfail(LK_EHIP, "launch: %s", hipGetErrorString(e));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+      return bfail(LK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    const auto t2 = clk::now();
+    int64_t sum = 0;
+    for (uint32_t j0 = 0; j0 < k; j0 += kChunk) {
+      const uint32_t m = std::min(kChunk, k - j0);
+      if ((e = hipMemcpy(buf, partials + j0, 8ull * m, hipMemcpyDeviceToHost)) != hipSuccess)
+        return bfail(LK_EHIP, "partials copy: %s", hipGetErrorString(e));
+      for (uint32_t j = 0; j < m; ++j) sum += buf[j];
+    }
+    if (results) results[i] = sum;
+    if (lat_us) lat_us[i] = us_between(t0, t2);
+    if (launch_us) launch_us[i] = us_between(t0, t1);
+  }
+  return LK_OK;
 }
 
 int lkb_launch_lanes(int device, uint32_t n_lanes, const lkb_item *items, uint64_t items_per_lane, uint32_t n_streams,

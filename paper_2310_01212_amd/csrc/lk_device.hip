@@ -12,9 +12,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lk_devutil.hpp"
 #include "lk_device.h"
 #include "lk_ops.hpp"
+#include "lk_scratch.h"
 #include "lk_wire.h"
 
 using namespace lkdev;
@@ -58,6 +61,13 @@ __global__ void __launch_bounds__(1024) lk_item(lkd::ItemArgs a) {
     }
   }
 }
+
+// ----------------------------------------------------------------------------- static scratch
+// Per-workgroup partial results of the allocation-free per-launch path.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code the array's
+// name is not a device address: the address comes from hipGetSymbolAddress, once per
+// device (static_partials below), and only that address is handed to kernels or copies.
+static __device__ __align__(256) int64_t scratch[lkd::kStaticMaxK];
 
 // ----------------------------------------------------------------------------- probes
 // Echo: workgroup w (lane 0) waits for h2d[w*stride] to reach the next value and echoes
@@ -108,6 +118,31 @@ __global__ void __launch_bounds__(256) lk_copy_probe(const lkops::u32x4 *__restr
 namespace lkd {
 
 const void *item_kernel() { return reinterpret_cast<const void *>(lk_item); }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_partials(int device, int64_t **p) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    // the symbol's address on the current device, which the caller has made `device`
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!q) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = q;
+  }
+  *p = static_cast<int64_t *>(g_scratch_addr[device]);
+  return hipSuccess;
+}
 
 hipError_t launch_item(const ItemArgs &a, uint32_t threads, hipStream_t s) {
   // Host-side check of what the kernel assumes: k workgroups (one slice each), a counter

@@ -31,7 +31,7 @@ EXPORTED = [
     "lk_read_log", "lk_slice", "lk_strerror", "lk_last_error",
     "lkb_serial", "lkb_lanes", "lkb_isolation", "lkb_replay", "lkb_batch", "lkb_launch_burst",
     "lkb_launch_serial", "lks_run", "lkb_launch_lanes", "lkb_pingpong",
-    "lkb_copy",
+    "lkb_copy", "lkb_launch_serial_static",
 ]
 
 
@@ -157,6 +157,7 @@ def lib():
         "lkb_batch": (ctypes.c_int, [P, U32, P, U32, P, U32, I64, P, P]),
         "lkb_launch_burst": (ctypes.c_int, [I32, P, U32, U64, U32, U32, U32, P]),
         "lkb_launch_serial": (ctypes.c_int, [I32, U32, U32, P, U64, U32, P, P, P]),
+        "lkb_launch_serial_static": (ctypes.c_int, [I32, U32, U32, P, U64, P, P, P]),
         "lks_run": (ctypes.c_int, [P, ctypes.POINTER(ServeConfig), P, U64, P, ctypes.POINTER(ServeStats)]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
@@ -520,6 +521,20 @@ def launch_serial(items, k=1, threads=256, mode=COMPLETE_SYNC, device=0):
     lau = np.zeros(n, np.float64)
     _check(lib().lkb_launch_serial(device, k, threads, _np_ptr(items), n, mode, _np_ptr(res),
                                    _np_ptr(lat), _np_ptr(lau)), "lkb_launch_serial")
+    return res, lat, lau
+
+
+def launch_serial_static(items, k=1, threads=256, device=0):
+    """launch_serial with stream-synchronised completion through the library's
+    allocation-free entry point (null stream, partials in a static device array; k at
+    most 4096).  Returns (results, lat_us, launch_us)."""
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+    n = items.size
+    res = np.zeros(n, np.int64)
+    lat = np.zeros(n, np.float64)
+    lau = np.zeros(n, np.float64)
+    _check(lib().lkb_launch_serial_static(device, k, threads, _np_ptr(items), n, _np_ptr(res), _np_ptr(lat),
+                                          _np_ptr(lau)), "lkb_launch_serial_static")
     return res, lat, lau
 
 

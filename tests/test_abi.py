@@ -175,6 +175,22 @@ def test_calls_on_a_null_context_fail_cleanly():
     assert L.lk_init(None, None) == lk.EINVAL
 
 
+def test_static_launch_entry_point_rejects_bad_sizes_before_touching_a_device():
+    """The allocation-free per-launch entry point refuses k outside its static array
+    (1..4096) and a misaligned item before any HIP call; the detail reaches lk_last_error
+    (the runners share the library's per-thread error detail)."""
+    it = lk.make_items(lk.OP_SUM_I32_I64, 16, 0x1000, 0)
+    for k in (0, 4097):
+        with pytest.raises(lk.LKError) as e:
+            lk.launch_serial_static(it, k=k)
+        assert e.value.code == lk.EINVAL
+        assert "1..4096" in lk.last_error() and "1..4096" in str(e.value)
+    bad = lk.make_items(lk.OP_SUM_I32_I64, 16, 0x1002, 0)
+    with pytest.raises(lk.LKError) as e:
+        lk.launch_serial_static(bad, k=1)
+    assert e.value.code == lk.EINVAL and "invalid" in lk.last_error()
+
+
 def test_init_without_a_gpu_reports_no_device():
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
