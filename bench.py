@@ -103,6 +103,23 @@ def traffic_per_item(n, threads_per_worker, pin_input=False, depth=1, cold_pairs
     return None
 
 
+def host_cpu_model():
+    """Model name of the host CPU as lscpu reports it (/proc/cpuinfo if lscpu is missing)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +154,16 @@ def parse():
     ap.add_argument("--baseline-steps", type=int, default=1, help="steps timed for each baseline")
     ap.add_argument("--streams", type=int, default=4, help="HIP streams of the per-launch baseline")
     ap.add_argument("--skip-baselines", action="store_true")
+    ap.add_argument("--no-graph-relaunch", action="store_true",
+                    help="leave out the baselines that relaunch one single-node hipGraph per item (lanes and "
+                         "plain forms); the per-launch and captured-chain baselines still run")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-legs", action="store_true",
+                    help="default workload: leave out the shortened isolation, serving, batching and replay runs")
+    ap.add_argument("--leg-periods", type=int, default=2000, help="isolation periods per variant in the default run")
+    ap.add_argument("--leg-serve-seconds", type=float, default=1.0,
+                    help="serving trace length per rate in the default run")
+    ap.add_argument("--leg-runs", type=int, default=100, help="replay runs per configuration in the default run")
     ap.add_argument("--cpu-items", type=int, default=10000,
                     help="items per mailbox in the CPU sample (capped at the workload's own)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024)
@@ -171,15 +197,9 @@ def main():
               "the dispatch path has no multi-GPU component (each GPU would run a context of its own).",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "isolation":
-        return bench_isolation(args)
-    if args.workload == "replay":
-        return bench_replay(args)
-    if args.workload == "batching":
-        return bench_batching(args)
-    if args.workload == "serving":
-        return bench_serving(args)
-    return bench_allcu(args)
+    run = {"isolation": bench_isolation, "replay": bench_replay, "batching": bench_batching,
+           "serving": bench_serving, "allcu": bench_allcu}[args.workload]
+    print(json.dumps(run(args)), flush=True)
 
 
 # Host clock cycles per phase printed in the paper (Sec. 3): Table 2 averages (single SM,
@@ -300,7 +320,7 @@ def bench_batching(args):
     out["roofline"] = {"bound": "hbm", "achieved": big["persistent"]["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac": round(big["persistent"]["gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
                        "kernel": "lk_worker (one batch)"}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serving(args):
@@ -379,7 +399,7 @@ def bench_serving(args):
     top = out["rates"][str(int(max(rates)))]
     out["value"] = top["items_per_s"]
     out["ms_per_step"] = None
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_replay(args):
@@ -411,7 +431,7 @@ def bench_replay(args):
     out["paper_cycles_gtx980_i7_3.6GHz"] = {f"{a}/{b}/{c}": v for (a, b, c), v in PAPER_CYCLES.items()}
     out["value"] = out["single_cu"]["LK"]["Trigger"]["avg_us"] + out["single_cu"]["LK"]["Wait"]["avg_us"]
     out["ms_per_step"] = None
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_isolation(args):
@@ -497,7 +517,7 @@ def bench_isolation(args):
         out["absent"] = summarize(ca.run_isolation(0, crit, args.period_us * 1e-6, [], bg[:0]), [])
     out["value"] = out["on"]["latency_us"]["max"]
     out["ms_per_step"] = round(out["on"]["elapsed_s"] * 1e3 / P, 4)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_allcu(args):
@@ -564,16 +584,19 @@ def bench_allcu(args):
         ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads)
     log("persistent path: timed steps")
     torch.cuda.synchronize()
-    lat_all = []
+    lat_all, comp_all = [], []
     t0 = time.perf_counter()
     for s in range(args.warmup, args.warmup + args.steps):
-        _, lat, _ = ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads)
+        _, lat, _, comp = ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads,
+                                        with_info=True)
         lat_all.append(lat)
+        comp_all.append(comp)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.close()
     info = ctx.info()
     lat_all = np.concatenate([l.ravel() for l in lat_all])
+    comp_all = np.concatenate([c.ravel() for c in comp_all])
     timed_items = lanes * per * args.steps
     items_per_s = timed_items / elapsed
     # duration of the single worker dispatch, measured by the kernel itself on the device
@@ -612,17 +635,20 @@ def bench_allcu(args):
         "dispose_ms": round(info["dispose_ms"], 3),
     }
 
-    # ---------------- roofline of the worker kernel (one launch = the session)
-    result["roofline"] = {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": HBM_PEAK_GBPS,
-                          "unit": "GB/s", "frac": round(achieved_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
-                          "kernel": "lk_worker", "kernel_ms": round(kernel_ms, 3), "kernel_clock": kernel_clock,
-                          "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
-                          "items_per_launch": session_items, "algorithmic_bytes_per_item": hbm_bytes_per_item,
-                          "algorithmic_bytes": session_items * hbm_bytes_per_item}
+    # ---------------- byte rate of the worker kernel (one launch = the session).  For the
+    # hot workload this is not the binding bound: x and y of every mailbox stay in its XCD's
+    # L2 and the Infinity Cache, and the item rate is bound by dispatch latency (below).
+    # The cold form (--cold P) streams every operand from HBM and is bound by it.
+    byte_rate = {"achieved": round(achieved_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                 "frac": round(achieved_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                 "kernel": "lk_worker", "kernel_ms": round(kernel_ms, 3), "kernel_clock": kernel_clock,
+                 "dispatch_timestamps_ms": round(info["kernel_ms"], 3),
+                 "items_per_launch": session_items, "algorithmic_bytes_per_item": hbm_bytes_per_item,
+                 "algorithmic_bytes": session_items * hbm_bytes_per_item}
     tr = traffic_per_item(n, args.threads_per_worker, args.pin_input, args.depth, cold_pairs)
     if tr is not None:
-        result["roofline"]["traffic"] = round(tr["bytes_per_item"] * session_items)
-        result["roofline"]["traffic_source"] = tr["source"]
+        byte_rate["traffic"] = round(tr["bytes_per_item"] * session_items)
+        byte_rate["traffic_source"] = tr["source"]
 
     # ---------------- baselines on the same workload
     if not args.skip_baselines:
@@ -631,7 +657,10 @@ def bench_allcu(args):
         # item (its parameters updated); graph_chain: each lane's items captured once as a
         # chain of kernel nodes and launched as one graph (throughput only: the timed region
         # is the native runner's, excluding capture and instantiation)
-        for name, mode in (("launch", 0), ("graph", lk.USE_GRAPH), ("graph_chain", lk.GRAPH_CHAIN)):
+        lane_forms = [("launch", 0), ("graph", lk.USE_GRAPH), ("graph_chain", lk.GRAPH_CHAIN)]
+        if args.no_graph_relaunch:
+            lane_forms = [f for f in lane_forms if f[1] != lk.USE_GRAPH]
+        for name, mode in lane_forms:
             bl, el_native = [], 0.0
             t0 = time.perf_counter()
             for s in range(args.baseline_steps):
@@ -809,70 +838,96 @@ def bench_allcu(args):
             del ycold
             result["pinned_variant"] = pv
 
-        # serial single-worker comparison (1 CU, 1000 affine+sum items of 4096 int32)
-        Xs, ABs = workloads.plain()
-        xs = torch.from_numpy(Xs).to(dev)
-        ys = torch.zeros_like(xs)
-        torch.cuda.synchronize()
-        rows = np.arange(Xs.shape[0], dtype=np.uint64)
-        items = lk.make_items(lk.OP_AFFINE_SUM_I32, Xs.shape[1], xs.data_ptr() + rows * Xs.shape[1] * 4,
-                              ys.data_ptr() + rows * Xs.shape[1] * 4, ABs[:, 0], ABs[:, 1])
-        with lk.Context(n_workers=1, idle_timeout_ms=30000) as c1:
-            c1.run_serial(0, items[:100])
-            _, lat_p, trig_p, _ = c1.run_serial(0, items)
-        serial = {"persistent": lat_summary(lat_p), "persistent_trigger": lat_summary(trig_p)}
+    # ---------------- dispatch latency floors (measured in every run)
+    # the bare host<->device echo, one wave alone and with every CU's wave polling its own
+    # word (the host pings them in turn)
+    rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
+    rtt_all = lk.pingpong(workers=lanes, iters=200)[:, 20:]
+    # one headline item on one worker alone: device pickup to status record, from the log
+    with lk.Context(n_workers=1, threads=args.threads_per_worker, log_capacity=512,
+                    idle_timeout_ms=30000) as c1:
+        c1.run_lanes(np.arange(1), step_items(0)[:1, :500], in_flight=1, threads=1)
+    hz = float(c1.info()["wall_clock_hz"])
+    e1 = c1.log(0)[100:]
+    item_alone_us = float(np.median((e1["t_done"] - e1["t_pick"]) / hz * 1e6))
+    echo_all_us = pct(rtt_all, 0.5)
+    # At depth 1 every item of a mailbox costs at least one host round trip (status record
+    # seen, next command posted and seen) plus the item itself; with the ring kept ahead the
+    # round trip can hide behind the item, which then bounds alone.
+    floor_all = (echo_all_us if args.depth == 1 else 0.0) + item_alone_us
+    bound = lanes / (floor_all * 1e-6)
+    result["latency_roofline_all_cus"] = {
+        "floor": ("all-CU ping-pong RTT p50 + the headline item's device span on one worker alone"
+                  if args.depth == 1 else "the headline item's device span on one worker alone"),
+        "echo_us": round(echo_all_us, 3), "item_alone_us": round(item_alone_us, 3), "floor_us": round(floor_all, 3),
+        "items_per_s_bound": round(bound, 1), "achieved_items_per_s": round(items_per_s, 1),
+        "frac": round(items_per_s / bound, 3)}
+    log(f"all-CU latency bound: {bound:,.0f} items/s (echo {echo_all_us:.3f} us + item {item_alone_us:.2f} us)")
+    if cold_pairs:
+        result["roofline"] = {"bound": "hbm", **byte_rate}
+    else:
+        result["roofline"] = {"bound": "latency", "achieved": round(items_per_s, 1), "peak": round(bound, 1),
+                              "unit": "items/s", "frac": round(items_per_s / bound, 4), "traffic": byte_rate["traffic"],
+                              "floor": result["latency_roofline_all_cus"]["floor"], "floor_us": round(floor_all, 3),
+                              "kernel": "lk_worker", "kernel_ms": byte_rate["kernel_ms"],
+                              "items_per_launch": session_items}
+        result["byte_rate"] = byte_rate
+
+    # where an item's time goes (host steady clock and device wall clock): Trigger is
+    # inside the latency; the device span runs from the first member's pickup to the last
+    # member's status record; the rest is the two host-link crossings and the polls
+    span_all = (comp_all["t_done_max"] - comp_all["t_pick_min"]) / hz * 1e6
+    result["latency_split_us"] = {"latency": lat_summary(lat_all), "device_span": lat_summary(span_all),
+                                  "host_link_and_polls": lat_summary(lat_all - span_all),
+                                  "echo_floor_p50": round(echo_all_us, 3)}
+
+    # ---------------- the plain single-worker workload (1 CU, 1000 affine+sum items of 4096 int32)
+    Xs, ABs = workloads.plain()
+    xs = torch.from_numpy(Xs).to(dev)
+    ys = torch.zeros_like(xs)
+    torch.cuda.synchronize()
+    rows = np.arange(Xs.shape[0], dtype=np.uint64)
+    items = lk.make_items(lk.OP_AFFINE_SUM_I32, Xs.shape[1], xs.data_ptr() + rows * Xs.shape[1] * 4,
+                          ys.data_ptr() + rows * Xs.shape[1] * 4, ABs[:, 0], ABs[:, 1])
+    with lk.Context(n_workers=1, idle_timeout_ms=30000) as c1:
+        c1.run_serial(0, items[:100])
+        _, lat_p, trig_p, comp_p = c1.run_serial(0, items)
+    span_p = (comp_p["t_done_max"] - comp_p["t_pick_min"]) / hz * 1e6
+    serial = {"persistent": lat_summary(lat_p), "persistent_trigger": lat_summary(trig_p),
+              "persistent_device_span": lat_summary(span_p),
+              "persistent_host_link_and_polls": lat_summary(lat_p - trig_p - span_p)}
+    if not args.skip_baselines:
         for name, mode in (("launch_sync", lk.COMPLETE_SYNC), ("launch_flag", lk.COMPLETE_FLAG),
                            ("graph_sync", lk.COMPLETE_SYNC | lk.USE_GRAPH),
                            ("graph_flag", lk.COMPLETE_FLAG | lk.USE_GRAPH)):
+            if args.no_graph_relaunch and mode & lk.USE_GRAPH:
+                continue
             lk.launch_serial(items[:100], mode=mode)
             _, lat_b, lau_b = lk.launch_serial(items, mode=mode)
             serial[name] = lat_summary(lat_b)
             serial[name + "_launch_call"] = lat_summary(lau_b)
-        rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
-        serial["pingpong_rtt"] = lat_summary(rtt)
-        # the same echo with every CU's wave resident and polling its own word (host pings
-        # them in turn): the floor under all-CU load
-        rtt_all = lk.pingpong(workers=lanes, iters=200)[:, 20:]
-        serial["pingpong_rtt_all_cus"] = lat_summary(rtt_all)
-        # one-CU streaming copy: the bandwidth one worker can reach on its own
-        cb = 32 << 20
-        csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
-        cdst = torch.empty_like(csrc)
-        torch.cuda.synchronize()
-        _, bw1 = lk.copy_bandwidth(csrc, cdst, cb, grid=1, reps=3)
-        del csrc, cdst
-        item_bytes = 8 * Xs.shape[1] + 8
-        serial["copy_1cu_gbps"] = round(bw1, 2)
-        result["serial_1cu"] = {"workload": "1 worker on 1 CU, 1000 submit-then-wait items: int32 affine "
-                                            "+ int64 sum over 4096 elements", **serial}
-        result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
-                                      "floor_us": serial["pingpong_rtt"]["p50"],
-                                      "floor_us_all_cus_polling": serial["pingpong_rtt_all_cus"]["p50"],
-                                      "dispatch_p50_us": serial["persistent"]["p50"],
-                                      "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
-                                      "item_bytes": item_bytes,
-                                      "bytes_frac_of_1cu_copy": round(
-                                          item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
-        log(f"serial: persistent p50 {serial['persistent']['p50']} us, launch p50 {serial['launch_sync']['p50']} us")
-
-        # all-CU latency bound: one headline item on one worker alone (device pickup to
-        # status record, from the device log) plus the host<->device echo with every CU's
-        # wave polling; 256 mailboxes at depth 1 cannot beat lanes / (echo + item)
-        with lk.Context(n_workers=1, threads=args.threads_per_worker, log_capacity=512,
-                        idle_timeout_ms=30000) as c1:
-            c1.run_lanes(np.arange(1), step_items(0)[:1, :500], in_flight=1, threads=1)
-        hz = float(c1.info()["wall_clock_hz"])
-        e1 = c1.log(0)[100:]
-        item_alone_us = float(np.median((e1["t_done"] - e1["t_pick"]) / hz * 1e6))
-        floor_all = serial["pingpong_rtt_all_cus"]["p50"] + item_alone_us
-        result["latency_roofline_all_cus"] = {
-            "floor": "all-CU ping-pong RTT p50 + the headline item's device span on one worker alone",
-            "item_alone_us": round(item_alone_us, 3), "floor_us": round(floor_all, 3),
-            "items_per_s_bound": round(lanes / (floor_all * 1e-6), 1),
-            "achieved_items_per_s": round(items_per_s, 1),
-            "frac": round(items_per_s * floor_all * 1e-6 / lanes, 3)}
-        log(f"all-CU latency bound: {lanes / (floor_all * 1e-6):,.0f} items/s "
-            f"(echo {serial['pingpong_rtt_all_cus']['p50']} us + item {item_alone_us:.2f} us)")
+    serial["pingpong_rtt"] = lat_summary(rtt)
+    serial["pingpong_rtt_all_cus"] = lat_summary(rtt_all)
+    # one-CU streaming copy: the bandwidth one worker can reach on its own
+    cb = 32 << 20
+    csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
+    cdst = torch.empty_like(csrc)
+    torch.cuda.synchronize()
+    _, bw1 = lk.copy_bandwidth(csrc, cdst, cb, grid=1, reps=3)
+    del csrc, cdst
+    item_bytes = 8 * Xs.shape[1] + 8
+    serial["copy_1cu_gbps"] = round(bw1, 2)
+    result["serial_1cu"] = {"workload": "1 worker on 1 CU, 1000 submit-then-wait items: int32 affine "
+                                        "+ int64 sum over 4096 elements", **serial}
+    result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
+                                  "floor_us": serial["pingpong_rtt"]["p50"],
+                                  "floor_us_all_cus_polling": serial["pingpong_rtt_all_cus"]["p50"],
+                                  "dispatch_p50_us": serial["persistent"]["p50"],
+                                  "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
+                                  "item_bytes": item_bytes,
+                                  "bytes_frac_of_1cu_copy": round(
+                                      item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
+    log(f"serial: persistent p50 {serial['persistent']['p50']} us")
 
     # ---------------- streaming-copy probe (HBM roofline reference, known-size kernel)
     nbytes = args.copy_probe_mib << 20
@@ -884,16 +939,31 @@ def bench_allcu(args):
                             "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
     del src, dst
 
+    # ---------------- the other workloads, shortened: cluster isolation, serving, batching
+    # and the paper's phase protocol (each also runs at full length with --workload)
+    if not args.skip_legs:
+        for name, fn, over in (("isolation", bench_isolation, {"periods": args.leg_periods}),
+                               ("serving", bench_serving, {"serve_seconds": args.leg_serve_seconds}),
+                               ("batching", bench_batching, {}),
+                               ("replay", bench_replay, {"runs": args.leg_runs})):
+            t0 = time.perf_counter()
+            leg = fn(argparse.Namespace(**{**vars(args), **over}))
+            for k in ("n_gpus", "scaling", "vs_baseline", "higher_is_better"):
+                leg.pop(k, None)
+            leg["wall_s"] = round(time.perf_counter() - t0, 2)
+            result[name] = leg
+
     # ---------------- CPU oracle on a bounded sample of the same workload
     if not args.skip_cpu:
         import oracle
         oracle.build(force=False)
-        cores = min(16, os.cpu_count() or 1)
+        host_cpus = len(os.sched_getaffinity(0))
+        cores = min(16, host_cpus)
         per_cpu = min(args.cpu_items, A.shape[1])
         # The item lists are marshalled before the clock starts; the timed region is the
         # oracle's own FIFO executor, one mailbox after another on each thread.
-        ys = [Y0[w].copy() for w in range(lanes)]
-        packed = [oracle.pack_chain(oracle.SAXPY_F32, X[w], ys[w], A[w, :per_cpu]) for w in range(lanes)]
+        ys_cpu = [Y0[w].copy() for w in range(lanes)]
+        packed = [oracle.pack_chain(oracle.SAXPY_F32, X[w], ys_cpu[w], A[w, :per_cpu]) for w in range(lanes)]
 
         def lane_job(w):
             oracle.run_packed(packed[w])
@@ -902,20 +972,30 @@ def bench_allcu(args):
         with cf.ThreadPoolExecutor(max_workers=cores) as ex:
             list(ex.map(lane_job, range(lanes)))
         el = time.perf_counter() - t0
-        cpu_model = ""
-        try:
-            with open("/proc/cpuinfo") as fh:
-                cpu_model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
-        except OSError:
-            pass
+        # the plain workload on one host thread: each item executed as soon as it is
+        # "submitted", one after another
+        lat_c = np.empty(Xs.shape[0])
+        yc = np.empty(Xs.shape[1], np.int32)
+        t1 = time.perf_counter()
+        for i in range(Xs.shape[0]):
+            ti = time.perf_counter()
+            oracle.affine_sum_i32(Xs[i], int(ABs[i, 0]), int(ABs[i, 1]), y=yc)
+            lat_c[i] = (time.perf_counter() - ti) * 1e6
+        el1 = time.perf_counter() - t1
         result["cpu_baseline"] = {"value": round(lanes * per_cpu / el, 1), "unit": "items/s", "cores": cores,
-                                  "kind": "oracle", "cpu_model": cpu_model,
+                                  "kind": "oracle", "host_cpus": host_cpus, "cpu_model": host_cpu_model(),
                                   "sample": f"{lanes} mailboxes x {per_cpu} SAXPY items of {n} fp32 "
                                             f"({lanes * per_cpu} items), lanes spread over {cores} threads",
-                                  "seconds": round(el, 3)}
-        log(f"cpu oracle: {lanes * per_cpu / el:,.0f} items/s on {cores} threads")
+                                  "seconds": round(el, 3),
+                                  "plain_single_thread": {
+                                      "items_per_s": round(Xs.shape[0] / el1, 1), "cores": 1,
+                                      "latency_us": lat_summary(lat_c),
+                                      "sample": f"{Xs.shape[0]} affine+sum items of {Xs.shape[1]} int32, one "
+                                                "after another on one host thread"}}
+        log(f"cpu oracle: {lanes * per_cpu / el:,.0f} items/s on {cores} threads; plain workload "
+            f"{Xs.shape[0] / el1:,.0f} items/s on 1 thread")
 
-    print(json.dumps(result), flush=True)
+    return result
 
 
 if __name__ == "__main__":

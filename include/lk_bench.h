@@ -150,10 +150,17 @@ LK_API int lkb_pingpong(int device, uint32_t workers, uint64_t iters, uint32_t p
                  double *rtt_us);
 
 /* Streaming copy of `bytes` (multiple of 16, 16-byte aligned device buffers) with `grid`
- * workgroups of 256 threads, repeated `reps` times; *ms_avg = average kernel time from
- * HIP events; *gbps = 2*bytes / time (read + write). */
-LK_API int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t reps,
-             double *ms_avg, double *gbps);
+ * workgroups of `threads` (64..1024, whole waves), each thread keeping `unroll` (4, 8 or
+ * 16) 16-byte vectors in flight, repeated `reps` times after one untimed copy; *ms_avg =
+ * average kernel time from HIP events; *gbps = 2*bytes / time (read + write).  policy:
+ * LKB_COPY_PLAIN ordinary loads and stores, LKB_COPY_NONTEMPORAL non-temporal loads and
+ * stores, LKB_COPY_SYSTEM ordinary loads and stores written through the L2 (cache
+ * policy sc0 sc1, the persistent worker's output path; bytes below 2 GiB). */
+#define LKB_COPY_PLAIN 0u
+#define LKB_COPY_NONTEMPORAL 1u
+#define LKB_COPY_SYSTEM 2u
+LK_API int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t threads,
+                    uint32_t unroll, uint32_t policy, uint32_t reps, double *ms_avg, double *gbps);
 
 #ifdef __cplusplus
 }

@@ -832,11 +832,15 @@ int lkb_pingpong(int device, uint32_t workers, uint64_t iters, uint32_t poll_sle
   return rc;
 }
 
-int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t reps, double *ms_avg,
-             double *gbps) {
+int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t grid, uint32_t threads,
+             uint32_t unroll, uint32_t policy, uint32_t reps, double *ms_avg, double *gbps) {
   if (!src || !dst || bytes % 16 || (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 ||
       grid == 0 || grid > (1u << 20) || reps == 0)
     return bfail(LK_EINVAL, "bad copy arguments");
+  if (threads < 64 || threads > 1024 || threads % 64 || (unroll != 4 && unroll != 8 && unroll != 16))
+    return bfail(LK_EINVAL, "copy: threads 64..1024 in whole waves, unroll 4, 8 or 16");
+  if (policy > LKB_COPY_SYSTEM || (policy == LKB_COPY_SYSTEM && bytes >= (1ull << 31)))
+    return bfail(LK_EINVAL, "copy: unknown store policy, or written-through stores over 2 GiB or more");
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return bfail(LK_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
   hipStream_t s;
@@ -845,11 +849,12 @@ int lkb_copy(int device, const void *src, void *dst, uint64_t bytes, uint32_t gr
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
   int rc = LK_OK;
+  auto launch = [&]() { return lkd::launch_copy_probe(src, dst, bytes, grid, threads, unroll, policy, s); };
   // one untimed warm-up
-  if ((e = lkd::launch_copy_probe(src, dst, bytes, grid, s)) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
+  if ((e = launch()) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
   (void)hipEventRecord(a, s);
   for (uint32_t r = 0; rc == LK_OK && r < reps; ++r)
-    if ((e = lkd::launch_copy_probe(src, dst, bytes, grid, s)) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
+    if ((e = launch()) != hipSuccess) rc = bfail(LK_EHIP, "copy: %s", hipGetErrorString(e));
   (void)hipEventRecord(b, s);
   (void)hipStreamSynchronize(s);
   float ms = 0.f;

@@ -35,7 +35,10 @@ hipError_t launch_item(const ItemArgs &a, uint32_t threads, hipStream_t s);
 hipError_t launch_pingpong(uint64_t *h2d, uint64_t *d2h, uint32_t stride, uint32_t workers, uint64_t iters,
                            uint64_t deadline_ticks, uint32_t poll_sleep, uint32_t *status, bool spread,
                            hipStream_t s);
-hipError_t launch_copy_probe(const void *in, void *out, uint64_t bytes, uint32_t grid, hipStream_t s);
+// Store policies of the copy probe.
+constexpr uint32_t kCopyPlain = 0, kCopyNontemporal = 1, kCopySystem = 2;
+hipError_t launch_copy_probe(const void *in, void *out, uint64_t bytes, uint32_t grid, uint32_t threads,
+                             uint32_t unroll, uint32_t policy, hipStream_t s);
 
 }  // namespace lkd
 

@@ -99,19 +99,34 @@ __global__ void lk_pingpong(uint64_t *h2d, uint64_t *d2h, uint32_t stride, uint6
   status[w] = 1;
 }
 
-__global__ void __launch_bounds__(256) lk_copy_probe(const lkops::u32x4 *__restrict__ in,
-                                                     lkops::u32x4 *__restrict__ out, uint64_t nvec) {
-  constexpr int U = 8;
+// Streaming copy of nvec 16-byte vectors, grid-stride, U vectors in flight per thread.
+// Store policy P: kCopyPlain (ordinary loads and stores), kCopyNontemporal (non-temporal
+// loads and stores) or kCopySystem (ordinary loads, stores written through the XCD's L2
+// with cache policy sc0 sc1, as the persistent worker writes its outputs; the host keeps
+// the output under 2 GiB so that one buffer resource with 32-bit offsets covers it).
+template <int U, int P>
+__global__ void __launch_bounds__(1024) lk_copy_probe(const lkops::u32x4 *__restrict__ in,
+                                                      lkops::u32x4 *__restrict__ out, uint64_t nvec) {
   const uint64_t nt = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const lkops::SystemStore sys(out, P == lkd::kCopySystem ? nvec * 16 : 0);
+  auto put = [&](uint64_t i, lkops::u32x4 v) {
+    if (P == lkd::kCopyNontemporal) {
+      __builtin_nontemporal_store(v, out + i);
+    } else if (P == lkd::kCopySystem) {
+      sys.put(out + i, v);
+    } else {
+      out[i] = v;
+    }
+  };
   for (; k + (U - 1) * nt < nvec; k += U * nt) {
     lkops::u32x4 r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(in + k + u * nt);
+    for (int u = 0; u < U; ++u) r[u] = P == lkd::kCopyNontemporal ? __builtin_nontemporal_load(in + k + u * nt) : in[k + u * nt];
 #pragma unroll
-    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(r[u], out + k + u * nt);
+    for (int u = 0; u < U; ++u) put(k + u * nt, r[u]);
   }
-  for (; k < nvec; k += nt) out[k] = in[k];
+  for (; k < nvec; k += nt) put(k, in[k]);
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -173,9 +188,30 @@ hipError_t launch_pingpong(uint64_t *h2d, uint64_t *d2h, uint32_t stride, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_copy_probe(const void *in, void *out, uint64_t bytes, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(lk_copy_probe, dim3(grid), dim3(256), 0, s, static_cast<const lkops::u32x4 *>(in),
-                     static_cast<lkops::u32x4 *>(out), bytes / 16);
+hipError_t launch_copy_probe(const void *in, void *out, uint64_t bytes, uint32_t grid, uint32_t threads,
+                             uint32_t unroll, uint32_t policy, hipStream_t s) {
+  // Host-side check of what the kernel assumes: whole 16-byte vectors, a workgroup of
+  // whole waves, and (written-through stores) an output one 32-bit-offset resource covers.
+  if (bytes % 16 || grid == 0 || threads == 0 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+  if (policy > kCopySystem || (policy == kCopySystem && bytes >= (1ull << 31))) return hipErrorInvalidValue;
+  const auto *src = static_cast<const lkops::u32x4 *>(in);
+  auto *dst = static_cast<lkops::u32x4 *>(out);
+  const uint64_t nvec = bytes / 16;
+#define LKD_COPY(U, P) hipLaunchKernelGGL((lk_copy_probe<U, P>), dim3(grid), dim3(threads), 0, s, src, dst, nvec)
+#define LKD_COPY_U(P)                   \
+  switch (unroll) {                     \
+    case 4: LKD_COPY(4, P); break;      \
+    case 8: LKD_COPY(8, P); break;      \
+    case 16: LKD_COPY(16, P); break;    \
+    default: return hipErrorInvalidValue; \
+  }
+  switch (policy) {
+    case kCopyPlain: LKD_COPY_U(kCopyPlain); break;
+    case kCopyNontemporal: LKD_COPY_U(kCopyNontemporal); break;
+    default: LKD_COPY_U(kCopySystem); break;
+  }
+#undef LKD_COPY_U
+#undef LKD_COPY
   return hipGetLastError();
 }
 

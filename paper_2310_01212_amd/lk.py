@@ -161,7 +161,7 @@ def lib():
         "lks_run": (ctypes.c_int, [P, ctypes.POINTER(ServeConfig), P, U64, P, ctypes.POINTER(ServeStats)]),
         "lkb_launch_lanes": (ctypes.c_int, [I32, U32, P, U64, U32, U32, U32, U32, P, P, PD]),
         "lkb_pingpong": (ctypes.c_int, [I32, U32, U64, U32, ctypes.c_int, P]),
-        "lkb_copy": (ctypes.c_int, [I32, P, P, U64, U32, U32, PD, PD]),
+        "lkb_copy": (ctypes.c_int, [I32, P, P, U64, U32, U32, U32, U32, U32, PD, PD]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -611,10 +611,14 @@ def pingpong(workers=1, iters=10000, poll_sleep=0, spread=True, device=0):
     return rtt.reshape(workers, iters)
 
 
-def copy_bandwidth(src, dst, nbytes, grid, reps=10, device=0):
+COPY_PLAIN, COPY_NONTEMPORAL, COPY_SYSTEM = 0, 1, 2
+
+
+def copy_bandwidth(src, dst, nbytes, grid, reps=10, threads=256, unroll=8, policy=COPY_NONTEMPORAL, device=0):
+    """Streaming-copy probe (lkb_copy): returns (average ms per copy, GB/s read + written)."""
     ms, gbps = ctypes.c_double(), ctypes.c_double()
-    _check(lib().lkb_copy(device, _ptr(src), _ptr(dst), nbytes, grid, reps, ctypes.byref(ms),
-                          ctypes.byref(gbps)), "lkb_copy")
+    _check(lib().lkb_copy(device, _ptr(src), _ptr(dst), nbytes, grid, threads, unroll, policy, reps,
+                          ctypes.byref(ms), ctypes.byref(gbps)), "lkb_copy")
     return ms.value, gbps.value
 
 

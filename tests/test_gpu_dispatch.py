@@ -996,6 +996,21 @@ def test_pingpong_and_copy_probes_run():
     assert torch.equal(src.cpu(), dst.cpu())
 
 
+@pytest.mark.parametrize("policy", [lk.COPY_PLAIN, lk.COPY_NONTEMPORAL, lk.COPY_SYSTEM])
+def test_copy_probe_forms_copy_every_byte(policy):
+    """Every launch shape and store policy of the bandwidth probe copies the buffer exactly,
+    including a ragged tail of vectors beyond the unrolled loop; bytes after it untouched."""
+    vec = (5 << 20) // 16 + 37
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (vec * 4,), dtype=torch.int32, device="cuda")
+    for threads, unroll, grid in ((256, 4, 512), (1024, 8, 256), (64, 16, 1000), (1024, 16, 4096)):
+        say(f"copy probe: policy {policy}, {threads} threads, unroll {unroll}, grid {grid}, {vec} vectors")
+        dst = torch.full((vec * 4 + 64,), SENT_I32, dtype=torch.int32, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        lk.copy_bandwidth(src, dst, vec * 16, grid=grid, reps=1, threads=threads, unroll=unroll, policy=policy)
+        d = dst.cpu()
+        assert torch.equal(d[:vec * 4], src.cpu()) and torch.all(d[vec * 4:] == SENT_I32)
+
+
 # ------------------------------------------------------------------ cluster isolation runner
 def test_isolation_runner_critical_items_and_copies_exact():
     say("isolation: 200 periods of 0.5 ms on XCD 0, copies of 16 MiB on XCDs 1-2")
