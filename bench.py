@@ -158,6 +158,9 @@ def parse():
                     help="leave out the baselines that relaunch one single-node hipGraph per item (lanes and "
                          "plain forms); the per-launch and captured-chain baselines still run")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-floors", action="store_true",
+                    help="leave out the latency floors (host<->device echo, the item alone) and the one-CU "
+                         "workload: for counter-collection runs, where a kernel that waits on the host must not run")
     ap.add_argument("--skip-legs", action="store_true",
                     help="default workload: leave out the shortened isolation, serving, batching and replay runs")
     ap.add_argument("--leg-periods", type=int, default=2000, help="isolation periods per variant in the default run")
@@ -650,6 +653,27 @@ def bench_allcu(args):
         byte_rate["traffic"] = round(tr["bytes_per_item"] * session_items)
         byte_rate["traffic_source"] = tr["source"]
 
+    # ---------------- streaming-copy probe (HBM roofline reference, known-size kernel): the
+    # fastest form measured on this machine (one workgroup of 256 threads per CU, four
+    # 16-byte vectors in flight per thread, non-temporal loads and stores), and beside it
+    # the persistent worker's own shape and store policy (1024 threads per CU, stores
+    # written through the L2)
+    nbytes = args.copy_probe_mib << 20
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ms, gbps = lk.copy_bandwidth(src, dst, nbytes, grid=lanes, reps=5, threads=256, unroll=4,
+                                 policy=lk.COPY_NONTEMPORAL)
+    wms, wgbps = lk.copy_bandwidth(src, dst, nbytes, grid=lanes, reps=5, threads=1024, unroll=4,
+                                   policy=lk.COPY_SYSTEM)
+    result["copy_probe"] = {"bytes": nbytes, "ms": round(ms, 4), "gbps": round(gbps, 1),
+                            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
+                            "form": f"{lanes} workgroups x 256 threads, 4 vectors in flight, non-temporal",
+                            "worker_shape_written_through": {
+                                "ms": round(wms, 4), "gbps": round(wgbps, 1),
+                                "form": f"{lanes} workgroups x 1024 threads, 4 vectors in flight, stores sc0 sc1"}}
+    del src, dst
+
     # ---------------- baselines on the same workload
     if not args.skip_baselines:
         base = {}
@@ -770,6 +794,14 @@ def bench_allcu(args):
                 if ctr is not None:
                     cold[cd]["traffic_bytes_per_item"] = ctr["bytes_per_item"]
                     cold[cd]["traffic_source"] = ctr["source"]
+                # every operand streams from HBM: the binding roofline is bandwidth, against
+                # the 8 TB/s peak and, beside it, the best streaming copy measured here
+                cold[cd]["roofline"] = {"bound": "hbm", "achieved": round(c_gbps, 1), "peak": HBM_PEAK_GBPS,
+                                        "unit": "GB/s", "frac": round(c_gbps / HBM_PEAK_GBPS, 4),
+                                        "traffic": round(ctr["bytes_per_item"] * c_items) if ctr else None,
+                                        "kernel": "lk_worker", "kernel_ms": round(cinfo["device_span_ms"], 3),
+                                        "copy_probe_gbps": result["copy_probe"]["gbps"],
+                                        "frac_of_copy_probe": round(c_gbps / result["copy_probe"]["gbps"], 4)}
                 log(f"cold ({P} pairs per mailbox, depth {cd}): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
             del cx, cy
             result["cold_variant"] = {"pairs_per_mailbox": P, "footprint_bytes": lanes * P * n * 8, **cold[1]}
@@ -838,106 +870,104 @@ def bench_allcu(args):
             del ycold
             result["pinned_variant"] = pv
 
-    # ---------------- dispatch latency floors (measured in every run)
-    # the bare host<->device echo, one wave alone and with every CU's wave polling its own
-    # word (the host pings them in turn)
-    rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
-    rtt_all = lk.pingpong(workers=lanes, iters=200)[:, 20:]
-    # one headline item on one worker alone: device pickup to status record, from the log
-    with lk.Context(n_workers=1, threads=args.threads_per_worker, log_capacity=512,
-                    idle_timeout_ms=30000) as c1:
-        c1.run_lanes(np.arange(1), step_items(0)[:1, :500], in_flight=1, threads=1)
-    hz = float(c1.info()["wall_clock_hz"])
-    e1 = c1.log(0)[100:]
-    item_alone_us = float(np.median((e1["t_done"] - e1["t_pick"]) / hz * 1e6))
-    echo_all_us = pct(rtt_all, 0.5)
-    # At depth 1 every item of a mailbox costs at least one host round trip (status record
-    # seen, next command posted and seen) plus the item itself; with the ring kept ahead the
-    # round trip can hide behind the item, which then bounds alone.
-    floor_all = (echo_all_us if args.depth == 1 else 0.0) + item_alone_us
-    bound = lanes / (floor_all * 1e-6)
-    result["latency_roofline_all_cus"] = {
-        "floor": ("all-CU ping-pong RTT p50 + the headline item's device span on one worker alone"
-                  if args.depth == 1 else "the headline item's device span on one worker alone"),
-        "echo_us": round(echo_all_us, 3), "item_alone_us": round(item_alone_us, 3), "floor_us": round(floor_all, 3),
-        "items_per_s_bound": round(bound, 1), "achieved_items_per_s": round(items_per_s, 1),
-        "frac": round(items_per_s / bound, 3)}
-    log(f"all-CU latency bound: {bound:,.0f} items/s (echo {echo_all_us:.3f} us + item {item_alone_us:.2f} us)")
-    if cold_pairs:
-        result["roofline"] = {"bound": "hbm", **byte_rate}
+    if args.skip_floors:
+        result["roofline"] = ({"bound": "hbm", **byte_rate} if cold_pairs else
+                              {"bound": "latency", "achieved": round(items_per_s, 1), "peak": None, "unit": "items/s",
+                               "frac": None, "traffic": byte_rate["traffic"], "kernel": "lk_worker",
+                               "kernel_ms": byte_rate["kernel_ms"], "items_per_launch": session_items})
+        if not cold_pairs:
+            result["byte_rate"] = byte_rate
     else:
-        result["roofline"] = {"bound": "latency", "achieved": round(items_per_s, 1), "peak": round(bound, 1),
-                              "unit": "items/s", "frac": round(items_per_s / bound, 4), "traffic": byte_rate["traffic"],
-                              "floor": result["latency_roofline_all_cus"]["floor"], "floor_us": round(floor_all, 3),
-                              "kernel": "lk_worker", "kernel_ms": byte_rate["kernel_ms"],
-                              "items_per_launch": session_items}
-        result["byte_rate"] = byte_rate
+        # ---------------- dispatch latency floors (measured in every run)
+        # the bare host<->device echo, one wave alone and with every CU's wave polling its own
+        # word (the host pings them in turn)
+        rtt = lk.pingpong(workers=1, iters=5000)[:, 500:]
+        rtt_all = lk.pingpong(workers=lanes, iters=200)[:, 20:]
+        # one headline item on one worker alone: device pickup to status record, from the log
+        with lk.Context(n_workers=1, threads=args.threads_per_worker, log_capacity=512,
+                        idle_timeout_ms=30000) as c1:
+            c1.run_lanes(np.arange(1), step_items(0)[:1, :500], in_flight=1, threads=1)
+        hz = float(c1.info()["wall_clock_hz"])
+        e1 = c1.log(0)[100:]
+        item_alone_us = float(np.median((e1["t_done"] - e1["t_pick"]) / hz * 1e6))
+        echo_all_us = pct(rtt_all, 0.5)
+        # At depth 1 every item of a mailbox costs at least one host round trip (status record
+        # seen, next command posted and seen) plus the item itself; with the ring kept ahead the
+        # round trip can hide behind the item, which then bounds alone.
+        floor_all = (echo_all_us if args.depth == 1 else 0.0) + item_alone_us
+        bound = lanes / (floor_all * 1e-6)
+        result["latency_roofline_all_cus"] = {
+            "floor": ("all-CU ping-pong RTT p50 + the headline item's device span on one worker alone"
+                      if args.depth == 1 else "the headline item's device span on one worker alone"),
+            "echo_us": round(echo_all_us, 3), "item_alone_us": round(item_alone_us, 3), "floor_us": round(floor_all, 3),
+            "items_per_s_bound": round(bound, 1), "achieved_items_per_s": round(items_per_s, 1),
+            "frac": round(items_per_s / bound, 3)}
+        log(f"all-CU latency bound: {bound:,.0f} items/s (echo {echo_all_us:.3f} us + item {item_alone_us:.2f} us)")
+        if cold_pairs:
+            result["roofline"] = {"bound": "hbm", **byte_rate}
+        else:
+            result["roofline"] = {"bound": "latency", "achieved": round(items_per_s, 1), "peak": round(bound, 1),
+                                  "unit": "items/s", "frac": round(items_per_s / bound, 4), "traffic": byte_rate["traffic"],
+                                  "floor": result["latency_roofline_all_cus"]["floor"], "floor_us": round(floor_all, 3),
+                                  "kernel": "lk_worker", "kernel_ms": byte_rate["kernel_ms"],
+                                  "items_per_launch": session_items}
+            result["byte_rate"] = byte_rate
 
-    # where an item's time goes (host steady clock and device wall clock): Trigger is
-    # inside the latency; the device span runs from the first member's pickup to the last
-    # member's status record; the rest is the two host-link crossings and the polls
-    span_all = (comp_all["t_done_max"] - comp_all["t_pick_min"]) / hz * 1e6
-    result["latency_split_us"] = {"latency": lat_summary(lat_all), "device_span": lat_summary(span_all),
-                                  "host_link_and_polls": lat_summary(lat_all - span_all),
-                                  "echo_floor_p50": round(echo_all_us, 3)}
+        # where an item's time goes (host steady clock and device wall clock): Trigger is
+        # inside the latency; the device span runs from the first member's pickup to the last
+        # member's status record; the rest is the two host-link crossings and the polls
+        span_all = (comp_all["t_done_max"] - comp_all["t_pick_min"]) / hz * 1e6
+        result["latency_split_us"] = {"latency": lat_summary(lat_all), "device_span": lat_summary(span_all),
+                                      "host_link_and_polls": lat_summary(lat_all - span_all),
+                                      "echo_floor_p50": round(echo_all_us, 3)}
 
-    # ---------------- the plain single-worker workload (1 CU, 1000 affine+sum items of 4096 int32)
-    Xs, ABs = workloads.plain()
-    xs = torch.from_numpy(Xs).to(dev)
-    ys = torch.zeros_like(xs)
-    torch.cuda.synchronize()
-    rows = np.arange(Xs.shape[0], dtype=np.uint64)
-    items = lk.make_items(lk.OP_AFFINE_SUM_I32, Xs.shape[1], xs.data_ptr() + rows * Xs.shape[1] * 4,
-                          ys.data_ptr() + rows * Xs.shape[1] * 4, ABs[:, 0], ABs[:, 1])
-    with lk.Context(n_workers=1, idle_timeout_ms=30000) as c1:
-        c1.run_serial(0, items[:100])
-        _, lat_p, trig_p, comp_p = c1.run_serial(0, items)
-    span_p = (comp_p["t_done_max"] - comp_p["t_pick_min"]) / hz * 1e6
-    serial = {"persistent": lat_summary(lat_p), "persistent_trigger": lat_summary(trig_p),
-              "persistent_device_span": lat_summary(span_p),
-              "persistent_host_link_and_polls": lat_summary(lat_p - trig_p - span_p)}
-    if not args.skip_baselines:
-        for name, mode in (("launch_sync", lk.COMPLETE_SYNC), ("launch_flag", lk.COMPLETE_FLAG),
-                           ("graph_sync", lk.COMPLETE_SYNC | lk.USE_GRAPH),
-                           ("graph_flag", lk.COMPLETE_FLAG | lk.USE_GRAPH)):
-            if args.no_graph_relaunch and mode & lk.USE_GRAPH:
-                continue
-            lk.launch_serial(items[:100], mode=mode)
-            _, lat_b, lau_b = lk.launch_serial(items, mode=mode)
-            serial[name] = lat_summary(lat_b)
-            serial[name + "_launch_call"] = lat_summary(lau_b)
-    serial["pingpong_rtt"] = lat_summary(rtt)
-    serial["pingpong_rtt_all_cus"] = lat_summary(rtt_all)
-    # one-CU streaming copy: the bandwidth one worker can reach on its own
-    cb = 32 << 20
-    csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
-    cdst = torch.empty_like(csrc)
-    torch.cuda.synchronize()
-    _, bw1 = lk.copy_bandwidth(csrc, cdst, cb, grid=1, reps=3)
-    del csrc, cdst
-    item_bytes = 8 * Xs.shape[1] + 8
-    serial["copy_1cu_gbps"] = round(bw1, 2)
-    result["serial_1cu"] = {"workload": "1 worker on 1 CU, 1000 submit-then-wait items: int32 affine "
-                                        "+ int64 sum over 4096 elements", **serial}
-    result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
-                                  "floor_us": serial["pingpong_rtt"]["p50"],
-                                  "floor_us_all_cus_polling": serial["pingpong_rtt_all_cus"]["p50"],
-                                  "dispatch_p50_us": serial["persistent"]["p50"],
-                                  "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
-                                  "item_bytes": item_bytes,
-                                  "bytes_frac_of_1cu_copy": round(
-                                      item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
-    log(f"serial: persistent p50 {serial['persistent']['p50']} us")
-
-    # ---------------- streaming-copy probe (HBM roofline reference, known-size kernel)
-    nbytes = args.copy_probe_mib << 20
-    src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    ms, gbps = lk.copy_bandwidth(src, dst, nbytes, grid=lanes * 8, reps=5)
-    result["copy_probe"] = {"bytes": nbytes, "ms": round(ms, 4), "gbps": round(gbps, 1),
-                            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
-    del src, dst
+        # ---------------- the plain single-worker workload (1 CU, 1000 affine+sum items of 4096 int32)
+        Xs, ABs = workloads.plain()
+        xs = torch.from_numpy(Xs).to(dev)
+        ys = torch.zeros_like(xs)
+        torch.cuda.synchronize()
+        rows = np.arange(Xs.shape[0], dtype=np.uint64)
+        items = lk.make_items(lk.OP_AFFINE_SUM_I32, Xs.shape[1], xs.data_ptr() + rows * Xs.shape[1] * 4,
+                              ys.data_ptr() + rows * Xs.shape[1] * 4, ABs[:, 0], ABs[:, 1])
+        with lk.Context(n_workers=1, idle_timeout_ms=30000) as c1:
+            c1.run_serial(0, items[:100])
+            _, lat_p, trig_p, comp_p = c1.run_serial(0, items)
+        span_p = (comp_p["t_done_max"] - comp_p["t_pick_min"]) / hz * 1e6
+        serial = {"persistent": lat_summary(lat_p), "persistent_trigger": lat_summary(trig_p),
+                  "persistent_device_span": lat_summary(span_p),
+                  "persistent_host_link_and_polls": lat_summary(lat_p - trig_p - span_p)}
+        if not args.skip_baselines:
+            for name, mode in (("launch_sync", lk.COMPLETE_SYNC), ("launch_flag", lk.COMPLETE_FLAG),
+                               ("graph_sync", lk.COMPLETE_SYNC | lk.USE_GRAPH),
+                               ("graph_flag", lk.COMPLETE_FLAG | lk.USE_GRAPH)):
+                if args.no_graph_relaunch and mode & lk.USE_GRAPH:
+                    continue
+                lk.launch_serial(items[:100], mode=mode)
+                _, lat_b, lau_b = lk.launch_serial(items, mode=mode)
+                serial[name] = lat_summary(lat_b)
+                serial[name + "_launch_call"] = lat_summary(lau_b)
+        serial["pingpong_rtt"] = lat_summary(rtt)
+        serial["pingpong_rtt_all_cus"] = lat_summary(rtt_all)
+        # one-CU streaming copy: the bandwidth one worker can reach on its own
+        cb = 32 << 20
+        csrc = torch.empty(cb // 4, dtype=torch.int32, device=dev)
+        cdst = torch.empty_like(csrc)
+        torch.cuda.synchronize()
+        _, bw1 = lk.copy_bandwidth(csrc, cdst, cb, grid=1, reps=3)
+        del csrc, cdst
+        item_bytes = 8 * Xs.shape[1] + 8
+        serial["copy_1cu_gbps"] = round(bw1, 2)
+        result["serial_1cu"] = {"workload": "1 worker on 1 CU, 1000 submit-then-wait items: int32 affine "
+                                            "+ int64 sum over 4096 elements", **serial}
+        result["latency_roofline"] = {"floor": "host<->device coherent ping-pong RTT p50",
+                                      "floor_us": serial["pingpong_rtt"]["p50"],
+                                      "floor_us_all_cus_polling": serial["pingpong_rtt_all_cus"]["p50"],
+                                      "dispatch_p50_us": serial["persistent"]["p50"],
+                                      "frac": round(serial["pingpong_rtt"]["p50"] / serial["persistent"]["p50"], 3),
+                                      "item_bytes": item_bytes,
+                                      "bytes_frac_of_1cu_copy": round(
+                                          item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
+        log(f"serial: persistent p50 {serial['persistent']['p50']} us")
 
     # ---------------- the other workloads, shortened: cluster isolation, serving, batching
     # and the paper's phase protocol (each also runs at full length with --workload)
@@ -974,6 +1004,7 @@ def bench_allcu(args):
         el = time.perf_counter() - t0
         # the plain workload on one host thread: each item executed as soon as it is
         # "submitted", one after another
+        Xs, ABs = workloads.plain()
         lat_c = np.empty(Xs.shape[0])
         yc = np.empty(Xs.shape[1], np.int32)
         t1 = time.perf_counter()

@@ -334,7 +334,12 @@ typedef struct lk_info {
 
 LK_API int lk_get_info(lk_ctx *ctx, lk_info *info);
 
-/* Physical placement of worker w, read from the HW_ID / XCC_ID registers at boot. */
+/* Physical placement of worker w, read from the HW_ID / XCC_ID registers at boot: the
+ * check Sec. 2.3 makes, that each persistent block sits on the core it was meant for
+ * (there, that the hardware placed the blocks round-robin, one per SM; here the
+ * workgroups' own hardware ids, from which the host orders the workers).  The worker's
+ * XCD, shader engine, shader array and CU index go to the non-NULL outputs.
+ * Errors: LK_EINVAL (NULL context or worker out of range). */
 LK_API int lk_topology(lk_ctx *ctx, uint32_t worker, uint32_t *xcc, uint32_t *se, uint32_t *sh,
                 uint32_t *cu);
 

@@ -147,6 +147,7 @@ struct SystemStore {
 // address per operand and access; these are also plain vector-memory reads, where a
 // generic pointer would give flat accesses that also wait on the LDS counter.
 struct BufIn {
+  static constexpr int kNonTemporal = 2;  // cache policy nt
   __amdgpu_buffer_rsrc_t rsrc;
   __device__ __forceinline__ BufIn(const void *p, uint64_t bytes) {
     const uint64_t b = reinterpret_cast<uint64_t>(p);
@@ -158,6 +159,12 @@ struct BufIn {
   }
   __device__ __forceinline__ float4 f4(uint32_t off) const {
     const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<int>(off), 0, 0);
+    return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w));
+  }
+  // Non-temporal read (cache policy nt): for an operand that the same item overwrites, so
+  // that keeping its lines in the caches can serve no later read.
+  __device__ __forceinline__ float4 f4nt(uint32_t off) const {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<int>(off), 0, kNonTemporal);
     return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w));
   }
   __device__ __forceinline__ int4 i4(uint32_t off) const {
@@ -239,7 +246,9 @@ __device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
   return o;
 }
 
-// y[i] = fma(alpha, x[i], y[i]) in place.
+// y[i] = fma(alpha, x[i], y[i]) in place.  y is read non-temporally: the item overwrites
+// it, so its lines cannot serve a later read (the written-through stores do not leave them
+// valid in the L2 either), and the hint keeps them from displacing x.
 template <class St>
 __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__restrict__ y, uint64_t n,
                                       float alpha, uint64_t nt) {
@@ -263,14 +272,14 @@ __device__ __forceinline__ void saxpy(const float *__restrict__ x, float *__rest
       for (int u = 0; u < U; ++u) {
         o[u] = voff(hb, k + u * nt);
         rx[u] = xin.f4(o[u]);
-        ry[u] = yin.f4(o[u]);
+        ry[u] = yin.f4nt(o[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) st.put_at(o[u], fma4(alpha, rx[u], ry[u]));
     }
     for (; k < nv; k += nt) {
       const uint32_t o = voff(hb, k);
-      st.put_at(o, fma4(alpha, xin.f4(o), yin.f4(o)));
+      st.put_at(o, fma4(alpha, xin.f4(o), yin.f4nt(o)));
     }
     done = head + nv * 4;
   }
