@@ -4,14 +4,20 @@
 Headline workload (one worker per CU, all CUs): every mailbox is fed fp32 SAXPY items
 y <- alpha*x + y over 16,384 elements back-to-back, 10,000 items per mailbox in total
 (10 steps of 1,000 items per mailbox).  One step = every mailbox receiving 1,000 items
-through post -> poll -> execute -> complete -> wait; the context is booted before the
-warm-up and disposed after the timed steps (boot and dispose times are reported apart).
+through post -> poll -> execute -> complete -> wait; the warm-up steps run first, then
+the timed steps run as one stream per mailbox (no pause at step boundaries); the context
+is booted before the warm-up and disposed after the timed steps (boot and dispose times
+are reported apart).
 
 Printed as one JSON line: items/s of the persistent path (value), its dispatch latency
-percentiles, the same workload as one hipLaunchKernelGGL per item and as a relaunched
-hipGraph, the serial single-worker comparison (1 CU, affine+sum over 4,096 int32), the
-ping-pong latency floor, the HBM roofline of the worker kernel and the CPU oracle timed
-on a bounded sample of the same workload.
+percentiles and their split into device span and host link, the latency bound it is
+measured against (roofline), the same workload as one hipLaunchKernelGGL per item, as a
+relaunched hipGraph and as captured per-lane graph chains, its variants (ring kept ahead,
+two workers per CU, operands streaming from HBM with their HBM roofline, x pinned in
+LDS), the serial single-worker comparison (1 CU, affine+sum over 4,096 int32), the
+ping-pong latency floors, the streaming-copy probes, shortened runs of the cluster
+isolation, serving, batching and replay workloads, and the CPU oracle timed on a bounded
+sample of the same workload.
 
 Inputs are seeded synthetic data resident in HBM before the timed region.
 """
@@ -46,9 +52,11 @@ def pct(v, p):
 
 
 def lat_summary(v):
+    v = np.asarray(v, dtype=np.float64).ravel()
     return {"p50": round(pct(v, 0.50), 3), "p99": round(pct(v, 0.99), 3),
             "p999": round(pct(v, 0.999), 3), "max": round(pct(v, 1.0), 3),
-            "jitter": round(pct(v, 1.0) - pct(v, 0.0), 3)}
+            "jitter": round(pct(v, 1.0) - pct(v, 0.0), 3),
+            "mean": round(float(v.mean()), 3) if v.size else float("nan")}
 
 
 def int_sum_check(x, a=None, b=None):
@@ -163,8 +171,8 @@ def parse():
                          "workload: for counter-collection runs, where a kernel that waits on the host must not run")
     ap.add_argument("--skip-legs", action="store_true",
                     help="default workload: leave out the shortened isolation, serving, batching and replay runs")
-    ap.add_argument("--leg-periods", type=int, default=2000, help="isolation periods per variant in the default run")
-    ap.add_argument("--leg-serve-seconds", type=float, default=1.0,
+    ap.add_argument("--leg-periods", type=int, default=5000, help="isolation periods per variant in the default run")
+    ap.add_argument("--leg-serve-seconds", type=float, default=2.0,
                     help="serving trace length per rate in the default run")
     ap.add_argument("--leg-runs", type=int, default=100, help="replay runs per configuration in the default run")
     ap.add_argument("--cpu-items", type=int, default=10000,
@@ -587,19 +595,22 @@ def bench_allcu(args):
         ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads)
     log("persistent path: timed steps")
     torch.cuda.synchronize()
-    lat_all, comp_all = [], []
+    # The timed steps run as one stream per mailbox: each lane's items of steps
+    # warmup .. warmup + steps - 1 in order, back-to-back, in one call of the native runner
+    # (its host threads start once, and no mailbox waits at a step boundary for the
+    # slowest one); the list is assembled before the clock starts.
+    timed_items = np.concatenate([step_items(s) for s in range(args.warmup, args.warmup + args.steps)], axis=1)
+    timed_out = lk.lanes_outputs(lanes, timed_items.shape[1], with_info=True)
     t0 = time.perf_counter()
-    for s in range(args.warmup, args.warmup + args.steps):
-        _, lat, _, comp = ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads,
-                                        with_info=True)
-        lat_all.append(lat)
-        comp_all.append(comp)
+    _, lat_all, runner_s, comp_all = ctx.run_lanes(np.arange(lanes), timed_items, in_flight=args.depth,
+                                                   threads=args.threads, with_info=True, out=timed_out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.close()
     info = ctx.info()
-    lat_all = np.concatenate([l.ravel() for l in lat_all])
-    comp_all = np.concatenate([c.ravel() for c in comp_all])
+    del timed_items
+    lat_all = lat_all.ravel()
+    comp_all = comp_all.ravel()
     timed_items = lanes * per * args.steps
     items_per_s = timed_items / elapsed
     # duration of the single worker dispatch, measured by the kernel itself on the device
@@ -634,6 +645,9 @@ def bench_allcu(args):
                    "host_threads": args.threads, "threads_per_worker": args.threads_per_worker,
                    "poll_sleep": args.poll_sleep},
         "latency_us": lat_summary(lat_all),
+        # the native runner's own time (first submit to last completion) per step; the rest
+        # of ms_per_step is starting and joining its host threads
+        "runner_ms_per_step": round(runner_s * 1e3 / args.steps, 3),
         "init_ms": round(info0["init_ms"], 3),
         "dispose_ms": round(info["dispose_ms"], 3),
     }
@@ -968,6 +982,31 @@ def bench_allcu(args):
                                       "bytes_frac_of_1cu_copy": round(
                                           item_bytes / (serial["persistent"]["p50"] * 1e-6) / 1e9 / bw1, 3)}
         log(f"serial: persistent p50 {serial['persistent']['p50']} us")
+
+        # one dispatch at a time at the headline's item size: lane 0's SAXPY items of 16,384
+        # on one worker of the headline's width, submit-then-wait, against one launch of
+        # one workgroup of the same width per item (the all-CU baseline latencies above
+        # include waiting behind the other lanes of a stream; these do not)
+        sx = step_items(0)[0, :1000].copy()
+        with lk.Context(n_workers=1, threads=args.threads_per_worker, idle_timeout_ms=30000) as c1:
+            c1.run_serial(0, sx[:100])
+            _, lat_s, trig_s, comp_s = c1.run_serial(0, sx)
+        span_s = (comp_s["t_done_max"] - comp_s["t_pick_min"]) / hz * 1e6
+        one = {"workload": f"1 worker of {args.threads_per_worker} threads on 1 CU, 1000 submit-then-wait SAXPY "
+                           f"items of {n} fp32 (mailbox 0's items)",
+               "persistent": lat_summary(lat_s), "persistent_trigger": lat_summary(trig_s),
+               "persistent_device_span": lat_summary(span_s)}
+        if not args.skip_baselines:
+            for name, mode in (("launch_sync", lk.COMPLETE_SYNC), ("launch_flag", lk.COMPLETE_FLAG),
+                               ("graph_sync", lk.COMPLETE_SYNC | lk.USE_GRAPH),
+                               ("graph_flag", lk.COMPLETE_FLAG | lk.USE_GRAPH)):
+                if args.no_graph_relaunch and mode & lk.USE_GRAPH:
+                    continue
+                lk.launch_serial(sx[:100], threads=args.threads_per_worker, mode=mode)
+                _, lat_b, _ = lk.launch_serial(sx, threads=args.threads_per_worker, mode=mode)
+                one[name] = lat_summary(lat_b)
+        result["serial_1cu_headline_item"] = one
+        log(f"one dispatch at a time, headline item: persistent p50 {one['persistent']['p50']} us")
 
     # ---------------- the other workloads, shortened: cluster isolation, serving, batching
     # and the paper's phase protocol (each also runs at full length with --workload)

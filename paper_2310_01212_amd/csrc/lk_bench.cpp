@@ -240,24 +240,37 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
   // Each host thread owns a fixed set of lanes (one producer per mailbox).  Per lane and
   // per sweep: first collect every finished ticket, then refill up to in_flight, so a
   // lane is re-armed as soon as its completion is seen.  Threads are pinned to distinct
-  // allowed CPUs when there are enough of them (the caller's thread is left one).
-  const bool pin = n_threads < allowed_cpus().size();
+  // allowed CPUs when there are enough of them (the caller's thread only waits to join
+  // them, so it needs no CPU of its own).
+  const bool pin = n_threads <= allowed_cpus().size();
   auto worker = [&](uint32_t tix) {
     if (pin) pin_to_allowed_cpu(tix);
+    // Submit times of the items in flight, in a ring of in_flight entries (item k in
+    // entry k % in_flight), so the per-item bookkeeping stays in the thread's caches.
     struct Lane {
       uint32_t id, cluster;
       uint64_t next = 0, done = 0;
       uint64_t first_ticket = 0;  // ticket of item 0
-      std::vector<clk::time_point> t_sub;
+      clk::time_point t_sub[LK_MAX_DEPTH];
     };
     std::vector<Lane> lanes;
     for (uint32_t l = tix; l < n_lanes; l += n_threads) {
-      Lane L;
+      Lane L{};
       L.id = l;
       L.cluster = lane_cluster[l];
-      L.t_sub.resize(items_per_lane);
-      lanes.push_back(std::move(L));
+      lanes.push_back(L);
     }
+    // The next items' descriptors and output slots are fetched a few items ahead: a thread
+    // serves many lanes, each with its own streams through these arrays.
+    constexpr uint64_t kItemsAhead = 2;
+    auto prefetch_item = [&](const Lane &L, uint64_t k) {
+      if (k >= items_per_lane) return;
+      const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + k;
+      __builtin_prefetch(items + idx, 0, 3);
+      if (results) __builtin_prefetch(results + idx, 1, 3);
+      if (lat_us) __builtin_prefetch(lat_us + idx, 1, 3);
+      if (info) __builtin_prefetch(info + idx, 1, 3);
+    };
     auto fail_all = [&](int rc) {
       error.store(rc);
       stop.store(true);
@@ -277,7 +290,8 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
           lk_completion ci;
           const int rc = lk_try_wait(c, L.cluster, t, &ci);
           if (rc == LK_EAGAIN) {
-            if (timeout_ns >= 0 && clk::now() - L.t_sub[L.done] > std::chrono::nanoseconds(timeout_ns))
+            if (timeout_ns >= 0 &&
+                clk::now() - L.t_sub[L.done % in_flight] > std::chrono::nanoseconds(timeout_ns))
               return fail_all(LK_ETIMEDOUT);
             break;
           }
@@ -285,7 +299,7 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
           const auto now = clk::now();
           const uint64_t idx = static_cast<uint64_t>(L.id) * items_per_lane + L.done;
           if (results) results[idx] = ci.result;
-          if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done], now);
+          if (lat_us) lat_us[idx] = us_between(L.t_sub[L.done % in_flight], now);
           if (info) info[idx] = ci;
           ++L.done;
           --remaining;
@@ -294,13 +308,15 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
           const lkb_item &it = items[static_cast<uint64_t>(L.id) * items_per_lane + L.next];
           const lk_desc d = to_desc(it);
           uint64_t t;
-          L.t_sub[L.next] = clk::now();
+          const auto ts = clk::now();
           const int rc = lk_submit(c, L.cluster, &d, reinterpret_cast<const void *>(it.in),
                                    reinterpret_cast<void *>(it.out), &t);
           if (rc == LK_EAGAIN) break;
           if (rc) return fail_all(rc);
+          L.t_sub[L.next % in_flight] = ts;
           if (L.next == 0) L.first_ticket = t;
           ++L.next;
+          prefetch_item(L, L.next + kItemsAhead - 1);
         }
       }
       _mm_pause();

@@ -472,17 +472,27 @@ class Context:
         _check(rc, "lkb_serial")
         return res, lat, trig, comp
 
-    def run_lanes(self, lane_cluster, items, in_flight=1, threads=8, timeout=10.0, with_info=False):
+    def run_lanes(self, lane_cluster, items, in_flight=1, threads=8, timeout=10.0, with_info=False, out=None):
         """items: (n_lanes, items_per_lane) ITEM_DTYPE array.
         Returns (results, lat_us, elapsed_s), plus the per-item COMPLETION_DTYPE array when
-        with_info is set."""
+        with_info is set.  out = (results, lat_us, info) arrays from lanes_outputs() may be
+        given so that the runner writes into memory allocated (and touched) beforehand."""
         items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
         lanes, per = items.shape
         lc = np.ascontiguousarray(lane_cluster, dtype=np.uint32)
         assert lc.size == lanes
-        res = np.zeros((lanes, per), np.int64)
-        lat = np.zeros((lanes, per), np.float64)
-        info = np.zeros((lanes, per), COMPLETION_DTYPE) if with_info else None
+        if out is None:
+            res, lat, info = lanes_outputs(lanes, per, with_info)
+        else:
+            res, lat, info = out
+            if (res.shape != (lanes, per) or res.dtype != np.int64 or not res.flags.c_contiguous or
+                    lat.shape != (lanes, per) or lat.dtype != np.float64 or not lat.flags.c_contiguous or
+                    (with_info and (info is None or info.shape != (lanes, per) or info.dtype != COMPLETION_DTYPE
+                                    or not info.flags.c_contiguous))):
+                raise ValueError("out arrays must be C-contiguous (lanes, items_per_lane) int64, float64 "
+                                 "and COMPLETION_DTYPE")
+            if not with_info:
+                info = None
         el = ctypes.c_double()
         rc = lib().lkb_lanes(self._h, _np_ptr(lc), lanes, _np_ptr(items), per, in_flight, threads,
                              int(timeout * 1e9), _np_ptr(res), _np_ptr(lat), ctypes.byref(el),
@@ -510,6 +520,20 @@ class Context:
                                  _np_ptr(late), _np_ptr(info), _np_ptr(done), ctypes.byref(el))
         _check(rc, "lkb_isolation")
         return dict(results=res, lat_us=lat, late_us=late, info=info, bg_done=done[:bgc.size], elapsed_s=el.value)
+
+
+def lanes_outputs(lanes, per, with_info=False):
+    """Output arrays for Context.run_lanes, every page written once (so no page is first
+    touched while the runner's host threads write results)."""
+    res = np.empty((lanes, per), np.int64)
+    lat = np.empty((lanes, per), np.float64)
+    res.fill(0)
+    lat.fill(0)
+    info = None
+    if with_info:
+        info = np.empty((lanes, per), COMPLETION_DTYPE)
+        info.view(np.uint8).fill(0)
+    return res, lat, info
 
 
 def launch_serial(items, k=1, threads=256, mode=COMPLETE_SYNC, device=0):

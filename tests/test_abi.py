@@ -297,7 +297,8 @@ def test_bench_percentiles_are_nearest_rank():
     assert (s["p50"], s["p99"], s["p999"], s["max"], s["jitter"]) == (50.0, 99.0, 100.0, 100.0, 99.0)
     w = np.arange(1, 1001, dtype=np.float64)
     assert bench.pct(w, 0.999) == 999.0 and bench.pct(w, 0.5) == 500.0 and bench.pct(w, 0.0) == 1.0
-    assert bench.lat_summary([7.0]) == {"p50": 7.0, "p99": 7.0, "p999": 7.0, "max": 7.0, "jitter": 0.0}
+    assert bench.lat_summary([7.0]) == {"p50": 7.0, "p99": 7.0, "p999": 7.0, "max": 7.0, "jitter": 0.0, "mean": 7.0}
+    assert s["mean"] == 50.5
 
 
 def test_worker_digest_ignores_comments_but_not_code(tmp_path):
