@@ -586,21 +586,25 @@ def bench_allcu(args):
     # with x pinned, memory carries y alone (4n read + 4n written); x is read once per worker
     hbm_bytes_per_item = 8 * n if args.pin_input else bytes_per_item
 
+    # The timed steps run as one stream per mailbox: each lane's items of steps
+    # warmup .. warmup + steps - 1 in order, back-to-back, in one call of the native runner
+    # (its host threads start once, and no mailbox waits at a step boundary for the
+    # slowest one).  The list and the runner's output arrays are prepared before the
+    # context boots, so the persistent dispatch holds nothing but the warm-up and timed work.
+    timed_items = np.concatenate([step_items(s) for s in range(args.warmup, args.warmup + args.steps)], axis=1)
+    timed_out = lk.lanes_outputs(lanes, timed_items.shape[1], with_info=True)
+    warm_items = (np.concatenate([step_items(s) for s in range(args.warmup)], axis=1) if args.warmup else None)
+    warm_out = lk.lanes_outputs(lanes, warm_items.shape[1]) if args.warmup else None
+
     # ---------------- persistent path
     log("persistent path: boot")
     ctx = lk.Context(n_workers=lanes, depth=args.depth, threads=args.threads_per_worker,
                      poll_sleep=args.poll_sleep, idle_timeout_ms=60000)
     info0 = ctx.info()
-    for s in range(args.warmup):
-        ctx.run_lanes(np.arange(lanes), step_items(s), in_flight=args.depth, threads=args.threads)
+    if args.warmup:
+        ctx.run_lanes(np.arange(lanes), warm_items, in_flight=args.depth, threads=args.threads, out=warm_out)
     log("persistent path: timed steps")
     torch.cuda.synchronize()
-    # The timed steps run as one stream per mailbox: each lane's items of steps
-    # warmup .. warmup + steps - 1 in order, back-to-back, in one call of the native runner
-    # (its host threads start once, and no mailbox waits at a step boundary for the
-    # slowest one); the list is assembled before the clock starts.
-    timed_items = np.concatenate([step_items(s) for s in range(args.warmup, args.warmup + args.steps)], axis=1)
-    timed_out = lk.lanes_outputs(lanes, timed_items.shape[1], with_info=True)
     t0 = time.perf_counter()
     _, lat_all, runner_s, comp_all = ctx.run_lanes(np.arange(lanes), timed_items, in_flight=args.depth,
                                                    threads=args.threads, with_info=True, out=timed_out)
@@ -608,11 +612,11 @@ def bench_allcu(args):
     elapsed = time.perf_counter() - t0
     ctx.close()
     info = ctx.info()
-    del timed_items
+    del timed_items, warm_items, warm_out
     lat_all = lat_all.ravel()
     comp_all = comp_all.ravel()
-    timed_items = lanes * per * args.steps
-    items_per_s = timed_items / elapsed
+    timed_count = lanes * per * args.steps
+    items_per_s = timed_count / elapsed
     # duration of the single worker dispatch, measured by the kernel itself on the device
     # wall clock (first worker boot to last worker exit); the packet processor's dispatch
     # timestamps are reported beside it (a tool intercepting the queue can hide them)
@@ -688,6 +692,22 @@ def bench_allcu(args):
                                 "form": f"{lanes} workgroups x 1024 threads, 4 vectors in flight, stores sc0 sc1"}}
     del src, dst
 
+    def session(items_steps, depth=1, **ctx_kw):
+        """One context over a list of per-step item arrays: the first step as an untimed
+        warm-up, the others as one timed call of the native runner; the items and output
+        arrays are prepared before the context boots, so its dispatch holds nothing but
+        this work.  Returns (lat_us, runner_s, info after dispose)."""
+        nm = items_steps[0].shape[0]
+        warm, timed = items_steps[0], np.concatenate(items_steps[1:], axis=1)
+        wout, tout = lk.lanes_outputs(nm, warm.shape[1]), lk.lanes_outputs(nm, timed.shape[1])
+        kw = dict(n_workers=lanes, depth=depth, threads=args.threads_per_worker, poll_sleep=args.poll_sleep,
+                  idle_timeout_ms=60000)
+        kw.update(ctx_kw)
+        with lk.Context(**kw) as cx:
+            cx.run_lanes(np.arange(nm), warm, in_flight=depth, threads=args.threads, out=wout)
+            _, lat, el = cx.run_lanes(np.arange(nm), timed, in_flight=depth, threads=args.threads, out=tout)
+        return lat.ravel(), el, cx.info()
+
     # ---------------- baselines on the same workload
     if not args.skip_baselines:
         base = {}
@@ -721,15 +741,7 @@ def bench_allcu(args):
         # includes the time an item waits behind the ones before it in its ring)
         if args.pipelined_depth > 1:
             d = args.pipelined_depth
-            with lk.Context(n_workers=lanes, depth=d, threads=args.threads_per_worker,
-                            poll_sleep=args.poll_sleep, idle_timeout_ms=60000) as cp:
-                cp.run_lanes(np.arange(lanes), step_items(0), in_flight=d, threads=args.threads)
-                pl, pt = [], 0.0
-                for s in range(1, min(4, args.warmup + args.steps)):
-                    _, lat, el = cp.run_lanes(np.arange(lanes), step_items(s), in_flight=d, threads=args.threads)
-                    pl.append(lat)
-                    pt += el
-            pl = np.concatenate([l.ravel() for l in pl])
+            pl, pt, _ = session([step_items(s) for s in range(min(4, args.warmup + args.steps))], depth=d)
             result["pipelined"] = {"queue_depth": d, "items_per_s": round(pl.size / pt, 1),
                                    "latency_us": lat_summary(pl), "items": int(pl.size)}
             log(f"pipelined depth {d}: {pl.size / pt:,.0f} items/s")
@@ -751,16 +763,8 @@ def bench_allcu(args):
             vli = np.arange(vl, dtype=np.uint64)[:, None]
             vitems = [lk.make_items(lk.OP_SAXPY_F32, n, vx.data_ptr() + vli * n * 4, vy.data_ptr() + vli * n * 4,
                                     alpha=VA[:, s * per:(s + 1) * per]) for s in range(vsteps)]
-            with lk.Context(n_workers=0, workers_per_cu=k, threads=tv, poll_sleep=args.poll_sleep,
-                            idle_timeout_ms=60000) as cv:
-                cv.run_lanes(np.arange(vl), vitems[0], in_flight=1, threads=args.threads)
-                vlat, vt = [], 0.0
-                for s in range(1, vsteps):
-                    _, lat, el = cv.run_lanes(np.arange(vl), vitems[s], in_flight=1, threads=args.threads)
-                    vlat.append(lat)
-                    vt += el
+            vlat, vt, _ = session(vitems, n_workers=0, workers_per_cu=k, threads=tv)
             del vx, vy
-            vlat = np.concatenate([l.ravel() for l in vlat])
             result["workers_per_cu_variant"] = {"workers_per_cu": k, "threads_per_worker": tv, "mailboxes": vl,
                                                 "queue_depth": 1, "items_per_s": round(vlat.size / vt, 1),
                                                 "latency_us": lat_summary(vlat), "items": int(vlat.size)}
@@ -787,16 +791,7 @@ def bench_allcu(args):
             # depth 1 (the headline's form), then the ring kept args.pipelined_depth ahead:
             # with the look-ahead read the CUs stay busy and HBM becomes the bound
             for cd in sorted({1, max(1, args.pipelined_depth)}):
-                with lk.Context(n_workers=lanes, depth=cd, threads=args.threads_per_worker,
-                                poll_sleep=args.poll_sleep, idle_timeout_ms=60000) as cc:
-                    cc.run_lanes(np.arange(lanes), cit[0], in_flight=cd, threads=args.threads)
-                    clat, ct = [], 0.0
-                    for s in range(1, csteps):
-                        _, lat, el = cc.run_lanes(np.arange(lanes), cit[s], in_flight=cd, threads=args.threads)
-                        clat.append(lat)
-                        ct += el
-                cinfo = cc.info()
-                clat = np.concatenate([l.ravel() for l in clat])
+                clat, ct, cinfo = session(cit, depth=cd)
                 c_items = lanes * per * csteps
                 c_gbps = c_items * bytes_per_item / (cinfo["device_span_ms"] * 1e-3) / 1e9
                 cold[cd] = {"queue_depth": cd, "items_per_s": round(clat.size / ct, 1), "latency_us": lat_summary(clat),
@@ -829,18 +824,7 @@ def bench_allcu(args):
         # as for the headline
         if args.pinned and not args.pin_input:
             def timed(ctx_kw, items_of_step, nsteps, depth=1):
-                with lk.Context(n_workers=lanes, depth=depth, threads=args.threads_per_worker,
-                                poll_sleep=args.poll_sleep, idle_timeout_ms=60000, **ctx_kw) as cx:
-                    cx.run_lanes(np.arange(lanes), items_of_step(0), in_flight=depth, threads=args.threads)
-                    ll, tt = [], 0.0
-                    for s in range(1, nsteps):
-                        _, lat, el = cx.run_lanes(np.arange(lanes), items_of_step(s), in_flight=depth,
-                                                  threads=args.threads)
-                        ll.append(lat)
-                        tt += el
-                inf = cx.info()
-                ll = np.concatenate([l.ravel() for l in ll])
-                return ll, tt, inf
+                return session([items_of_step(s) for s in range(nsteps)], depth=depth, **ctx_kw)
 
             psteps = min(4, args.warmup + args.steps)
             pin_items = []
