@@ -290,6 +290,15 @@ def test_committed_traffic_profiles_are_used_only_while_they_match_the_worker():
     assert seen > 0
 
 
+def test_lanes_outputs_are_zeroed_contiguous_arrays_of_the_runner_layout():
+    res, lat, info = lk.lanes_outputs(3, 5, with_info=True)
+    assert res.shape == lat.shape == info.shape == (3, 5)
+    assert res.dtype == np.int64 and lat.dtype == np.float64 and info.dtype == lk.COMPLETION_DTYPE
+    assert all(a.flags.c_contiguous for a in (res, lat, info))
+    assert not res.any() and not lat.any() and not info.view(np.uint8).any()
+    assert lk.lanes_outputs(2, 2)[2] is None
+
+
 def test_bench_percentiles_are_nearest_rank():
     import bench
     v = np.arange(1, 101, dtype=np.float64)[::-1]  # order must not matter

@@ -346,11 +346,15 @@ def test_all_cus_full_size_every_element_in_the_bench_launch_configuration(depth
     x, y = to_dev(X), to_dev(Y0)
     li = np.arange(lanes, dtype=np.uint64)[:, None]
     its = lk.make_items(lk.OP_SAXPY_F32, n, addr(x) + li * n * 4, addr(y) + li * n * 4, alpha=A)
+    out = lk.lanes_outputs(lanes, items, with_info=True)  # as the benchmark passes them
     with lk.Context(n_workers=lanes, depth=depth, threads=threads, poll_sleep=0, idle_timeout_ms=60000) as ctx:
         t0 = time.time()
-        res, lat, el = ctx.run_lanes(np.arange(lanes), its, in_flight=depth, threads=feeders, timeout=30.0)
+        res, lat, el, info = ctx.run_lanes(np.arange(lanes), its, in_flight=depth, threads=feeders, timeout=30.0,
+                                           with_info=True, out=out)
         say(f"  {lanes * items / el:.0f} items/s, p50 {np.percentile(lat, 50):.2f} us, wall {time.time() - t0:.2f} s")
     assert not res.any()
+    assert res is out[0] and lat is out[1] and info is out[2]
+    assert np.all(lat > 0) and np.all(info["t_done_max"] >= info["t_pick_min"]) and np.all(info["t_pick_min"] > 0)
     Y = y.cpu().numpy()
     want = _oracle_lane_chains(X, Y0, A)
     for w in range(lanes):
