@@ -14,9 +14,10 @@
  * budget.  A request is admitted when it has arrived and its output fits; admission is
  * first come, first served (a request that does not fit waits, and so do those behind
  * it).  An admitted request is cut into tiles of tile_elems elements; tiles of all
- * admitted requests are queued in admission order and posted to free mailbox slots, so
- * work from requests that arrived while others are running overlaps with theirs on the
- * GPU.  When its last tile completes the request is done, its int64 result is the exact
+ * admitted requests are queued in admission order and posted to free mailbox slots,
+ * breadth first (every idle worker gets a tile before any worker gets a second), so work
+ * from requests that arrived while others are running overlaps with theirs on the GPU and
+ * does not queue behind it while a worker is idle.  When its last tile completes the request is done, its int64 result is the exact
  * sum of its tiles' partial results, and its output memory returns to the budget (unless
  * `retain` is set).
  *

@@ -277,7 +277,7 @@ int lkb_lanes(lk_ctx *c, const uint32_t *lane_cluster, uint32_t n_lanes, const l
     };
     uint64_t remaining = lanes.size() * items_per_lane;
     const size_t nl = lanes.size();
-    constexpr size_t kAhead = 3;  // lanes between a prefetch and its use
+    constexpr size_t kAhead = 6;  // lanes between a prefetch and its use (about one memory miss)
     while (remaining && !stop.load(std::memory_order_relaxed)) {
       for (size_t li = 0; li < nl; ++li) {
         Lane &L = lanes[li];

@@ -106,6 +106,11 @@ struct lk_ctx {
   lk_config cfg{};
   int device = 0;
   uint32_t n_workers = 0, depth = 1, threads = 256, n_clusters = 0, cu_count = 0, xcd_count = 0;
+  // Ring arithmetic of every submit and wait, without a division on the common path:
+  // slots per mailbox, and depth - 1 when the depth is a power of two (else 0).
+  uint64_t stride = 1;
+  uint32_t depth_mask = 0;
+  bool depth_pow2 = true;
   uint32_t per_cu = 1, max_on_a_cu = 0;
   uint32_t cus_held = 0;  // CUs counted for this context in the process registry
   uint32_t pin_bytes = 0; // dynamic LDS of each worker: the largest x slice it can pin
@@ -137,11 +142,14 @@ struct lk_ctx {
 
 namespace {
 
+inline uint64_t ring_slot(const lk_ctx *c, uint64_t seq) {
+  return c->depth_pow2 ? (seq & c->depth_mask) : seq % c->depth;
+}
 lkw_cmd *slot_cmd(lk_ctx *c, uint32_t mb, uint64_t seq) {
-  return c->cmd + static_cast<uint64_t>(mb) * LKW_RING_STRIDE(c->depth) + seq % c->depth;
+  return c->cmd + static_cast<uint64_t>(mb) * c->stride + ring_slot(c, seq);
 }
 lkw_status *slot_status(lk_ctx *c, uint32_t mb, uint64_t seq) {
-  return c->status + static_cast<uint64_t>(mb) * LKW_RING_STRIDE(c->depth) + seq % c->depth;
+  return c->status + static_cast<uint64_t>(mb) * c->stride + ring_slot(c, seq);
 }
 
 // True (and *out filled) once the status record of `seq` is complete: word 0 holds seq
@@ -329,6 +337,9 @@ int lk_init(const lk_config *cfg_in, lk_ctx **out) {
       c->masked ? c->cu_count / nx * static_cast<uint32_t>(__builtin_popcount(c->xcd_mask)) : c->cu_count;
   c->n_workers = cfg.n_workers ? cfg.n_workers : cus_usable * c->per_cu;
   c->depth = cfg.queue_depth ? cfg.queue_depth : 1;
+  c->stride = LKW_RING_STRIDE(c->depth);
+  c->depth_pow2 = (c->depth & (c->depth - 1)) == 0;
+  c->depth_mask = c->depth_pow2 ? c->depth - 1 : 0;
   c->threads = cfg.threads_per_worker ? cfg.threads_per_worker : 256;
   c->log_cap = cfg.log_capacity;
   if (c->n_workers > cus_usable * c->per_cu || c->n_workers > LK_MAX_WORKERS) {
@@ -627,7 +638,7 @@ int lk_submit_batch(lk_ctx *c, uint32_t cluster, const lk_tile *tiles, uint32_t 
   const std::vector<uint32_t> &mbs = c->cluster_mbox[cluster];
   for (uint32_t mb : mbs)
     if (exited_code(worker_code(c, mb))) return fail(LK_ESTATE, "worker of mailbox %u has exited", mb);
-  const size_t slot = static_cast<size_t>(cluster) * c->depth + t % c->depth;
+  const size_t slot = static_cast<size_t>(cluster) * c->depth + ring_slot(c, t);
   uint64_t &base = c->batch_base[slot];
   const uint64_t counter = reinterpret_cast<uint64_t>(c->d_batch_counters) + slot * 128;
   for (uint32_t j = 0; j < mbs.size(); ++j)

@@ -168,10 +168,13 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           }
         }
       }
-      // 4. dispatch: fill free mailbox slots round-robin
-      for (size_t k = 0; k < workers.size() && !queue.empty(); ++k) {
-        const size_t w = (rr + k) % workers.size();
-        while (!queue.empty() && posted[w].size() < depth) {
+      // 4. dispatch, breadth first: every idle worker gets a tile, then every worker holding
+      // one gets a second, and so on up to the ring depth, so that a new request's tiles
+      // do not queue behind earlier tiles while one of the shard's workers is idle.
+      for (uint32_t level = 0; level < depth && !queue.empty(); ++level) {
+        for (size_t k = 0; k < workers.size() && !queue.empty(); ++k) {
+          const size_t w = (rr + k) % workers.size();
+          if (posted[w].size() != level) continue;
           const Tile tl = queue.front();
           const lks_request &r = reqs[tl.req];
           lk_desc d{};
@@ -186,7 +189,7 @@ extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs
           const uint64_t o = ob ? ob + tl.lo * 4 : 0;
           uint64_t t;
           const int rc = lk_submit(c, workers[w], &d, reinterpret_cast<const void *>(in), reinterpret_cast<void *>(o), &t);
-          if (rc == LK_EAGAIN) break;
+          if (rc == LK_EAGAIN) continue;
           if (rc) return rc;
           posted[w].push_back(Posted{t, tl.req, clk::now()});
           ++tiles_posted[s];
