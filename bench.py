@@ -59,6 +59,32 @@ def lat_summary(v):
             "mean": round(float(v.mean()), 3) if v.size else float("nan")}
 
 
+def gb_per_s(bytes_total, ms):
+    """Bytes over a duration in milliseconds, in GB/s (0 for a non-positive duration)."""
+    return bytes_total / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+
+
+def latency_bound(mailboxes, echo_us, item_us, depth):
+    """Items/s bound of mailboxes fed back-to-back: at depth 1 each item of a mailbox costs
+    at least one host round trip (the echo) plus the item's device span; with the ring kept
+    ahead the round trip can hide behind the item.  Returns (floor_us, items_per_s)."""
+    floor_us = (echo_us if depth == 1 else 0.0) + item_us
+    return floor_us, mailboxes / (floor_us * 1e-6)
+
+
+def hbm_roofline(bytes_per_launch, kernel_ms, copy_gbps=None, traffic=None, **extra):
+    """Roofline object of a bandwidth-bound kernel launch against the HBM peak (and, when
+    given, the best streaming copy measured in the same run)."""
+    a = gb_per_s(bytes_per_launch, kernel_ms)
+    r = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": round(a / HBM_PEAK_GBPS, 4), "traffic": traffic,
+         "kernel_ms": round(kernel_ms, 3), **extra}
+    if copy_gbps:
+        r["copy_probe_gbps"] = copy_gbps
+        r["frac_of_copy_probe"] = round(a / copy_gbps, 4)
+    return r
+
+
 def int_sum_check(x, a=None, b=None):
     """Sanity value for a sampled result: int64 sum of x (int32), or of the int32 affine
     map a*x + b mod 2^32 when a is given.  Parity proper is established by the tests."""
@@ -624,7 +650,7 @@ def bench_allcu(args):
     if kernel_ms <= 0:
         kernel_ms, kernel_clock = info["kernel_ms"], "dispatch timestamps"
     session_items = lanes * per * (args.warmup + args.steps)
-    achieved_gbps = session_items * hbm_bytes_per_item / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
+    achieved_gbps = gb_per_s(session_items * hbm_bytes_per_item, kernel_ms)
     log(f"persistent: {items_per_s:,.0f} items/s, p50 {pct(lat_all, .5):.2f} us, kernel {kernel_ms:.1f} ms")
 
     result = {
@@ -741,9 +767,24 @@ def bench_allcu(args):
         # includes the time an item waits behind the ones before it in its ring)
         if args.pipelined_depth > 1:
             d = args.pipelined_depth
-            pl, pt, _ = session([step_items(s) for s in range(min(4, args.warmup + args.steps))], depth=d)
+            psteps = min(4, args.warmup + args.steps)
+            pl, pt, pinf = session([step_items(s) for s in range(psteps)], depth=d)
             result["pipelined"] = {"queue_depth": d, "items_per_s": round(pl.size / pt, 1),
                                    "latency_us": lat_summary(pl), "items": int(pl.size)}
+            # With the ring kept ahead the CUs never wait for the host, and the bound becomes
+            # the memory side: y's reads and written-through stores miss the L2 on every
+            # item (x stays in it), so the measured traffic of the committed counter summary
+            # of this workload, over the dispatch, is set against the 8 TB/s peak and the
+            # best streaming copy
+            ptr = traffic_per_item(n, args.threads_per_worker, args.pin_input, d, cold_pairs)
+            if ptr is not None and pinf["device_span_ms"] > 0:
+                p_items = lanes * per * psteps
+                p_traffic = round(ptr["bytes_per_item"] * p_items)
+                result["pipelined"]["roofline"] = hbm_roofline(
+                    p_traffic, pinf["device_span_ms"], result["copy_probe"]["gbps"], traffic=p_traffic,
+                    traffic_source=ptr["source"], kernel="lk_worker", items_per_launch=p_items,
+                    bytes="memory-side traffic measured by the counters (L2 misses to the Infinity Cache and "
+                          "HBM), not algorithmic bytes")
             log(f"pipelined depth {d}: {pl.size / pt:,.0f} items/s")
 
         # several workers per CU: k mailboxes per CU, each fed back-to-back at depth 1, so
@@ -793,7 +834,7 @@ def bench_allcu(args):
             for cd in sorted({1, max(1, args.pipelined_depth)}):
                 clat, ct, cinfo = session(cit, depth=cd)
                 c_items = lanes * per * csteps
-                c_gbps = c_items * bytes_per_item / (cinfo["device_span_ms"] * 1e-3) / 1e9
+                c_gbps = gb_per_s(c_items * bytes_per_item, cinfo["device_span_ms"])
                 cold[cd] = {"queue_depth": cd, "items_per_s": round(clat.size / ct, 1), "latency_us": lat_summary(clat),
                             "kernel_ms": round(cinfo["device_span_ms"], 3), "items_per_launch": c_items,
                             "achieved_gbps": round(c_gbps, 1), "frac_of_peak": round(c_gbps / HBM_PEAK_GBPS, 4)}
@@ -805,12 +846,9 @@ def bench_allcu(args):
                     cold[cd]["traffic_source"] = ctr["source"]
                 # every operand streams from HBM: the binding roofline is bandwidth, against
                 # the 8 TB/s peak and, beside it, the best streaming copy measured here
-                cold[cd]["roofline"] = {"bound": "hbm", "achieved": round(c_gbps, 1), "peak": HBM_PEAK_GBPS,
-                                        "unit": "GB/s", "frac": round(c_gbps / HBM_PEAK_GBPS, 4),
-                                        "traffic": round(ctr["bytes_per_item"] * c_items) if ctr else None,
-                                        "kernel": "lk_worker", "kernel_ms": round(cinfo["device_span_ms"], 3),
-                                        "copy_probe_gbps": result["copy_probe"]["gbps"],
-                                        "frac_of_copy_probe": round(c_gbps / result["copy_probe"]["gbps"], 4)}
+                cold[cd]["roofline"] = hbm_roofline(
+                    c_items * bytes_per_item, cinfo["device_span_ms"], result["copy_probe"]["gbps"],
+                    traffic=round(ctr["bytes_per_item"] * c_items) if ctr else None, kernel="lk_worker")
                 log(f"cold ({P} pairs per mailbox, depth {cd}): {clat.size / ct:,.0f} items/s, {c_gbps:,.0f} GB/s")
             del cx, cy
             result["cold_variant"] = {"pairs_per_mailbox": P, "footprint_bytes": lanes * P * n * 8, **cold[1]}
@@ -892,8 +930,7 @@ def bench_allcu(args):
         # At depth 1 every item of a mailbox costs at least one host round trip (status record
         # seen, next command posted and seen) plus the item itself; with the ring kept ahead the
         # round trip can hide behind the item, which then bounds alone.
-        floor_all = (echo_all_us if args.depth == 1 else 0.0) + item_alone_us
-        bound = lanes / (floor_all * 1e-6)
+        floor_all, bound = latency_bound(lanes, echo_all_us, item_alone_us, args.depth)
         result["latency_roofline_all_cus"] = {
             "floor": ("all-CU ping-pong RTT p50 + the headline item's device span on one worker alone"
                       if args.depth == 1 else "the headline item's device span on one worker alone"),

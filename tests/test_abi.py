@@ -299,6 +299,29 @@ def test_lanes_outputs_are_zeroed_contiguous_arrays_of_the_runner_layout():
     assert lk.lanes_outputs(2, 2)[2] is None
 
 
+def test_bench_roofline_arithmetic():
+    """The bench's bound and roofline objects: GB/s from bytes and milliseconds, the
+    depth-1 latency bound (round trip + item per mailbox) and its depth > 1 form (the item
+    alone), and an HBM roofline against the 8 TB/s peak and a measured copy."""
+    import bench
+    assert bench.gb_per_s(8e9, 1000.0) == 8.0 and bench.gb_per_s(1e9, 0.0) == 0.0
+    floor, bound = bench.latency_bound(256, 2.0, 3.0, 1)
+    assert floor == 5.0 and abs(bound - 256 / 5e-6) < 1e-3
+    floor4, bound4 = bench.latency_bound(256, 2.0, 3.0, 4)
+    assert floor4 == 3.0 and abs(bound4 - 256 / 3e-6) < 1e-3
+    r = bench.hbm_roofline(8e9, 1.0, copy_gbps=6000.0, traffic=123, kernel="k")
+    assert (r["bound"], r["achieved"], r["peak"], r["unit"], r["frac"]) == ("hbm", 8000.0, 8000.0, "GB/s", 1.0)
+    assert r["traffic"] == 123 and r["kernel"] == "k" and r["frac_of_copy_probe"] == round(8000 / 6000, 4)
+    assert r["kernel_ms"] == 1.0
+    assert "copy_probe_gbps" not in bench.hbm_roofline(1e9, 1.0)
+    # the committed kernel trace of the benchmark command: 6,400,000 items of 196,608 bytes
+    # in the 165.553 ms headline dispatch
+    text = open(os.path.join(ROOT, "profiles", "lk_worker_allcu_saxpy_kernel_trace.md")).read()
+    m = re.search(r"took \*\*([0-9.]+) ms\*\* in the trace", text)
+    assert m
+    assert abs(bench.gb_per_s(6_400_000 * 196_608, float(m.group(1))) / 1000 - 7.60) < 0.01
+
+
 def test_bench_percentiles_are_nearest_rank():
     import bench
     v = np.arange(1, 101, dtype=np.float64)[::-1]  # order must not matter
