@@ -213,12 +213,18 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving: trace length per rate")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: device-memory budget for outputs")
     ap.add_argument("--tile", type=int, default=65536, help="serving: elements per tile")
+    ap.add_argument("--serve-threads", type=int, default=1024, help="serving: threads per worker")
+    ap.add_argument("--serve-schedulers", type=int, default=4,
+                    help="serving: host scheduler threads (each owns an equal share of the workers)")
     ap.add_argument("--bursts", type=str, default="1,4,16,64,256,1024,4096", help="batching: burst sizes")
     ap.add_argument("--burst-reps", type=int, default=5, help="batching: timed repetitions per burst")
+    ap.add_argument("--batch-threads", type=str, default="256,1024",
+                    help="batching: worker sizes (threads per worker) the autotuner chooses from")
     ap.add_argument("--spin-iters", type=int, default=20000, help="replay: loop iterations of the item")
     ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
     ap.add_argument("--period-us", type=float, default=1000.0)
     ap.add_argument("--copy-mib", type=int, default=256, help="isolation: interference buffer size")
+    ap.add_argument("--iso-threads", type=int, default=256, help="isolation: threads per worker")
     args = ap.parse_args()
     if args.threads is None:
         from paper_2310_01212_amd import workloads
@@ -302,38 +308,50 @@ def bench_batching(args):
 
     ctxs = {}
 
-    def ctx_for(sleep):
+    def ctx_for(sleep, threads):
         # one context at a time: each holds every CU until it is closed
-        if sleep not in ctxs:
+        if (sleep, threads) not in ctxs:
             for old in list(ctxs):
                 ctxs.pop(old).close()
-            ctxs[sleep] = lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=sleep, idle_timeout_ms=120000)
-        return ctxs[sleep]
+            ctxs[(sleep, threads)] = lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=sleep,
+                                                threads=threads, idle_timeout_ms=120000)
+        return ctxs[(sleep, threads)]
 
-    def run_burst(size, tile, sleep, r):
+    def run_burst(size, tile, sleep, threads, r):
         d, nt, part = staged_tiles((size, 50), tile)
-        ctx = ctx_for(sleep)
+        ctx = ctx_for(sleep, threads)
         ctx.run_batch(0, d, nt, part, reps=1)  # warm-up
         return ctx.run_batch(0, d, nt, part, reps=r)
 
     log("batching: autotuning on training bursts (seed 50)")
-    table = autotune.tune(run_burst, sizes, reps=reps)
+    worker_sizes = tuple(int(v) for v in args.batch_threads.split(","))
+    table = autotune.tune(run_burst, sizes, threads=worker_sizes, reps=reps)
     out = {"metric": "burst makespan (µs), items/s and achieved GB/s: one persistent batch vs per-item "
                      "launches vs captured hipGraph",
            "unit": "items/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int32 / f32",
            "data": "synthetic (seeded: bursts seed 5, tuning seed 50)", "steps": reps, "warmup": 1,
            "scaling": "weak", "vs_baseline": None,
            "config": {"workload": "bursts of uneven items, log-uniform 256..2^20 elements, int32 affine and "
-                                  "fp32 SAXPY 50/50, one persistent batch over all CUs", "bursts": sizes},
-           "tuning": {str(k): {"tile": v["tile"], "poll_sleep": v["poll_sleep"]} for k, v in table.items()},
+                                  "fp32 SAXPY 50/50, one persistent batch over all CUs", "bursts": sizes,
+                      "worker_sizes_tuned": list(worker_sizes)},
+           "tuning": {str(k): {"tile": v["tile"], "poll_sleep": v["poll_sleep"], "threads": v["threads"]}
+                      for k, v in table.items()},
            "bursts": {}}
+    # The persistent bursts first, then every context closed, then the per-launch and graph
+    # baselines on a GPU with no persistent workers resident (workers of 1024 threads fill
+    # their CUs' register files, and a launched item could not be scheduled beside them).
+    ms_of = {}
+    for size in sizes:
+        tune_row = table[size]
+        d, nt, part = staged_tiles((size, 5), tune_row["tile"])
+        ctx = ctx_for(tune_row["poll_sleep"], tune_row["threads"])
+        ctx.run_batch(0, d, nt, part, reps=1)
+        ms_of[size] = (ctx.run_batch(0, d, nt, part, reps=reps), nt)
+    for old in list(ctxs):
+        ctxs.pop(old).close()
     for size in sizes:
         key = (size, 5)
-        tune_row = table[size]
-        d, nt, part = staged_tiles(key, tune_row["tile"])
-        ctx = ctx_for(tune_row["poll_sleep"])
-        ctx.run_batch(0, d, nt, part, reps=1)
-        ms_p = ctx.run_batch(0, d, nt, part, reps=reps)
+        ms_p, nt = ms_of[size]
         items = items_of(plans[key])
         lk.launch_burst(items, graph=False, reps=1)
         ms_l = lk.launch_burst(items, graph=False, reps=reps)
@@ -349,8 +367,6 @@ def bench_batching(args):
         out["bursts"][str(size)] = row
         log(f"burst {size}: persistent {row['persistent']['makespan_us']} us, launch {row['launch']['makespan_us']} us, "
             f"graph {row['graph']['makespan_us']} us")
-    for c in ctxs.values():
-        c.close()
     big = out["bursts"][str(max(sizes))]
     out["value"] = big["persistent"]["items_per_s"]
     out["ms_per_step"] = round(big["persistent"]["makespan_us"] / 1e3, 4)
@@ -387,9 +403,10 @@ def bench_serving(args):
            "config": {"workload": "serving with continuous batching: mixed requests (40% affine+sum, 30% sum, 30% "
                                   "SAXPY), log-uniform 256..2^22 elements, Poisson arrivals, outputs admitted against "
                                   f"a {args.budget_gib} GiB device-memory budget", "seconds_per_rate": args.serve_seconds,
-                      "tile_elems": args.tile, "host_threads": args.threads},
+                      "tile_elems": args.tile, "host_threads": args.serve_schedulers,
+                      "threads_per_worker": args.serve_threads},
            "rates": {}}
-    with lk.Context(n_workers=0, depth=4, idle_timeout_ms=600000) as ctx:
+    with lk.Context(n_workers=0, depth=4, threads=args.serve_threads, idle_timeout_ms=600000) as ctx:
         for rate in rates:
             tr = workloads.serving(rate, args.serve_seconds, pool_elems, seed=7)
             kind = tr["kind"]
@@ -400,7 +417,8 @@ def bench_serving(args):
             req["inp"] = np.where(kind == 2, xf.data_ptr(), xi.data_ptr()).astype(np.uint64) + tr["off_x"] * 4
             req["in2"] = np.where(kind == 2, yf.data_ptr() + tr["off_y"].astype(np.int64) * 4, 0).astype(np.uint64)
             log(f"serving: {rate:.0f} req/s, {kind.size} requests")
-            outc, st = ctx.serve(req, arena, budget, tile_elems=args.tile, threads=args.threads, timeout=30.0)
+            outc, st = ctx.serve(req, arena, budget, tile_elems=args.tile, threads=args.serve_schedulers,
+                                 timeout=30.0)
             lat = outc["done_us"] - tr["arrival_us"]
             n = tr["n"].astype(np.float64)
             nbytes = float(np.sum(np.where(kind == 0, 8 * n + 8, np.where(kind == 1, 4 * n + 8, 12 * n))))
@@ -502,8 +520,10 @@ def bench_isolation(args):
            "data": "synthetic (seeded)", "steps": P, "warmup": 0, "scaling": "weak", "vs_baseline": None,
            "config": {"workload": "cluster isolation: 8 clusters = 8 XCDs; cluster 0 critical affine+sum over "
                                   f"{xh.size} int32 every {args.period_us} us; clusters 1-7 copy private "
-                                  f"{args.copy_mib} MiB fp32 buffers back-to-back", "periods": P}}
-    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=600000) as ctx:
+                                  f"{args.copy_mib} MiB fp32 buffers back-to-back", "periods": P,
+                      "threads_per_worker": args.iso_threads}}
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_PER_XCD, threads=args.iso_threads,
+                    idle_timeout_ms=600000) as ctx:
         ncl = ctx.info()["n_clusters"]
         assert ncl == 8, f"expected 8 XCD clusters, got {ncl}"
         ctx.run_isolation(0, crit[:200], args.period_us * 1e-6, [], bg[:0])  # warm-up, untimed
@@ -548,7 +568,8 @@ def bench_isolation(args):
             out[name] = summarize(r, bgc, pinned=items is crit_pinned)
     # absent: only XCD 0's workers exist (the context's XCD mask), nothing else runs
     log("isolation: other clusters absent")
-    with lk.Context(n_workers=0, xcd_mask=0x1, clusters=lk.CLUSTERS_PER_XCD, idle_timeout_ms=600000) as ca:
+    with lk.Context(n_workers=0, xcd_mask=0x1, clusters=lk.CLUSTERS_PER_XCD, threads=args.iso_threads,
+                    idle_timeout_ms=600000) as ca:
         assert ca.info()["n_clusters"] == 1
         ca.run_isolation(0, crit[:200], args.period_us * 1e-6, [], bg[:0])  # warm-up, untimed
         out["absent"] = summarize(ca.run_isolation(0, crit, args.period_us * 1e-6, [], bg[:0]), [])

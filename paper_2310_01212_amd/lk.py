@@ -443,7 +443,7 @@ class Context:
         return self._h
 
     # -- serving (lk_serve.h) ---------------------------------------------------------------
-    def serve(self, requests, arena, arena_bytes, tile_elems=65536, threads=8, retain=False, timeout=10.0):
+    def serve(self, requests, arena, arena_bytes, tile_elems=65536, threads=4, retain=False, timeout=10.0):
         """Run a request trace (REQUEST_DTYPE, sorted by arrival) with continuous batching;
         arena = device buffer (tensor or address) of arena_bytes for request outputs.
         Returns (OUTCOME_DTYPE array, stats dict)."""

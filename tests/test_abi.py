@@ -3,6 +3,7 @@ symbol include/*.h declares, the Python structs match the C layouts, the wire co
 the paper's Table 1 values, argument validation happens before any device call, and the
 host slicing rule agrees with the oracle's."""
 import ctypes
+import json
 import os
 import re
 import subprocess
@@ -379,20 +380,31 @@ def test_batch_plan_cuts_items_into_tiles():
     assert t2["b"][0] == np.float32(2.0).view(np.uint32)
 
 
-def test_autotuner_picks_the_fastest_median_with_stable_ties():
+def test_autotuner_picks_the_fastest_median_with_stable_ties(tmp_path):
     from paper_2310_01212_amd import autotune
-    t = {(4096, 0): [10, 11, 50], (16384, 0): [9, 12, 12], (65536, 8): [11, 11, 11], (65536, 0): [30, 30, 30]}
-    assert autotune.pick_best(t) == (65536, 8)   # medians 11 tie; larger tile wins
-    t2 = {(4096, 0): [5.0], (16384, 0): [5.0], (16384, 8): [5.0]}
-    assert autotune.pick_best(t2) == (16384, 8)   # tie: larger tile, then longer sleep
+    t = {(4096, 0, 256): [10, 11, 50], (16384, 0, 256): [9, 12, 12], (65536, 8, 256): [11, 11, 11],
+         (65536, 0, 256): [30, 30, 30], (65536, 8, 1024): [11, 12, 12]}
+    assert autotune.pick_best(t) == (65536, 8, 256)   # medians 11 tie; larger tile wins
+    t2 = {(4096, 0, 256): [5.0], (16384, 0, 256): [5.0], (16384, 8, 256): [5.0], (16384, 8, 1024): [5.0]}
+    assert autotune.pick_best(t2) == (16384, 8, 256)   # tie: larger tile, longer sleep, smaller worker
+    assert autotune.pick_best({(4096, 0, 256): [6.0], (4096, 0, 1024): [5.0]}) == (4096, 0, 1024)
     calls = []
 
-    def fake(size, tile, sleep, reps):
-        calls.append((size, tile, sleep))
-        return [abs(tile - 16384 * size) / 1e3 + sleep + 1] * reps
-    table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), sleeps=(0, 8), reps=2)
-    assert table[1]["tile"] == 16384 and table[1]["poll_sleep"] == 0
-    assert table[4]["tile"] == 65536 and len(calls) == 12
+    def fake(size, tile, sleep, threads, reps):
+        calls.append((size, tile, sleep, threads))
+        return [abs(tile - 16384 * size) / 1e3 + sleep + 1 + (0.5 if (threads == 1024) == (size == 1) else 0)] * reps
+    table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), sleeps=(0, 8), threads=(256, 1024), reps=2)
+    assert (table[1]["tile"], table[1]["poll_sleep"], table[1]["threads"]) == (16384, 0, 256)
+    assert (table[4]["tile"], table[4]["threads"]) == (65536, 1024) and len(calls) == 24
+    # one context per (threads, sleep) pair: the outer loops change least often
+    assert [c[3] for c in calls] == [256] * 12 + [1024] * 12
+    # a saved table reloads for the same device only; older tables default to 256 threads
+    path = str(tmp_path / "t.json")
+    autotune.save(table, path, "gfx950")
+    assert autotune.load(path, "other") is None
+    assert autotune.load(path, "gfx950")[4]["threads"] == 1024
+    json.dump({"device": "gfx950", "table": {"1": {"tile": 4096, "poll_sleep": 0}}}, open(path, "w"))
+    assert autotune.load(path, "gfx950")[1] == {"threads": 256, "tile": 4096, "poll_sleep": 0}
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
