@@ -162,7 +162,12 @@ typedef struct lk_config {
   int32_t device;              /* HIP device ordinal */
   uint32_t n_workers;          /* 1..LK_MAX_WORKERS, at most the CU count times
                                   workers_per_cu; 0 = workers_per_cu on every CU */
-  uint32_t threads_per_worker; /* 64..1024, multiple of 64; 0 = 256 (4 wave64 per CU) */
+  uint32_t threads_per_worker; /* 64..1024, multiple of 64; 0 = 256 (4 wave64 per CU).
+                                  The workers' CUs stay shared with other kernels only as
+                                  far as registers allow: a worker wave holds 104 VGPRs,
+                                  so with 1024 threads (4 waves per SIMD, 416 of 512)
+                                  a kernel needing more than 96 VGPRs per lane cannot
+                                  run on those CUs while the context lives */
   uint32_t queue_depth;        /* 1..LK_MAX_DEPTH ring slots per mailbox; 0 = 1 */
   uint32_t cluster_policy;     /* LK_CLUSTERS_* */
   uint32_t n_clusters;         /* LK_CLUSTERS_EXPLICIT only */
