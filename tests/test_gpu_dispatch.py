@@ -1153,14 +1153,16 @@ def test_batches_in_flight_two_deep_keep_their_own_counters():
             assert int(P[owner == i].sum()) == sr and np.array_equal(Z[lo:hi], yr)
 
 
-def test_batch_full_size_burst_of_4096_exact():
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_batch_full_size_burst_of_4096_exact(threads):
     """The batching workload's largest evaluation burst at its full sizes (4096 items,
     log-uniform 256 .. 2^20 elements, seed 5), one persistent batch over all CUs with
-    16,384-element tiles; every item checked."""
+    16,384-element tiles, on workers of both sizes the autotuner chooses from; every item
+    checked."""
     ops, n, ab, alpha = workloads.batching(4096, seed=5)
     off = np.concatenate([[0], np.cumsum((n + 255) // 256 * 256)]).astype(np.uint64)
     total = int(off[-1])
-    say(f"batch full size: 4096 items, {int(n.sum())} elements, tiles of 16384")
+    say(f"batch full size: 4096 items, {int(n.sum())} elements, tiles of 16384, {threads}-thread workers")
     rng = np.random.default_rng(1005)
     xi = rng.integers(0, 2 ** 32, total, dtype=np.uint32).view(np.int32)
     xf = rng.standard_normal(total, dtype=np.float32)
@@ -1174,7 +1176,8 @@ def test_batch_full_size_burst_of_4096_exact():
     d_tiles = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
     partials = torch.zeros(tiles.size, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
-    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=8, idle_timeout_ms=30000) as ctx:
+    with lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=8, threads=threads,
+                    idle_timeout_ms=30000) as ctx:
         ctx.run_batch(0, d_tiles, tiles.size, partials, reps=1)
     P = partials.cpu().numpy()
     sums = np.bincount(owner, weights=None, minlength=4096)  # tiles per item
@@ -1341,22 +1344,25 @@ def test_serving_admission_waits_for_memory_budget():
             assert outc["result"][i] == _oracle_request(tr, i, xi, xf, yf)[1], i
 
 
-def test_serving_full_size_requests_exact():
+@pytest.mark.parametrize("threads,schedulers", [(256, 8), (1024, 4)])
+def test_serving_full_size_requests_exact(threads, schedulers):
     """Serving with the workload's full request sizes (log-uniform 256 .. 2^22 elements,
-    windows in resident pools of 2^26 elements), Poisson arrivals, tiles of 65,536, the
-    bench's context (depth 4); every result and every retained output checked."""
+    windows in resident pools of 2^26 elements), Poisson arrivals, tiles of 65,536, depth
+    4, with the bench's workers and schedulers (1024 threads, 4 schedulers) and a second
+    shape; every result and every retained output checked."""
     count = 300
     tr, xi, xf, yf = _serve_setup(count, 23, pool_elems=1 << 26, log2=(8, 22))
-    say(f"serving full size: {count} requests, n up to 2^22, {int(tr['n'].sum())} elements")
+    say(f"serving full size: {count} requests, n up to 2^22, {int(tr['n'].sum())} elements, "
+        f"{threads}-thread workers, {schedulers} schedulers")
     d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf)
     per_req = (tr["n"].astype(np.int64) * 4 + 255) // 256 * 256
-    per_shard = max(int(per_req[s::8].sum()) for s in range(8))
-    need = 8 * (per_shard + (1 << 16))
+    per_shard = max(int(per_req[s::schedulers].sum()) for s in range(schedulers))
+    need = schedulers * (per_shard + (1 << 16))
     arena = torch.zeros(need // 4, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    with lk.Context(n_workers=0, depth=4, idle_timeout_ms=30000) as ctx:
+    with lk.Context(n_workers=0, depth=4, threads=threads, idle_timeout_ms=30000) as ctx:
         outc, st = ctx.serve(_requests(tr, d_xi, d_xf, d_yf, tr["arrival_us"]), arena, need,
-                             tile_elems=65536, threads=8, retain=True)
+                             tile_elems=65536, threads=schedulers, retain=True)
     assert np.all(outc["status"] == 0) and st["tiles"] == int(outc["tiles"].sum())
     for i in range(count):
         k, n = int(tr["kind"][i]), int(tr["n"][i])
