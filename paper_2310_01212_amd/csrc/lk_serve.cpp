@@ -7,6 +7,8 @@
 #include <immintrin.h>
 
 #include <algorithm>
+#include <cstdarg>
+#include <cstdio>
 #include <atomic>
 #include <chrono>
 #include <deque>
@@ -16,8 +18,21 @@
 #include "lk.h"
 #include "lk_affinity.hpp"
 #include "lk_arena.hpp"
+#include "lk_error.h"
 
 namespace {
+
+// Record the detail of a rejected call for lk_last_error and return the code.
+int sfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int sfail(int code, const char *fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  lkh::set_last_error(buf);
+  return code;
+}
 
 using clk = std::chrono::steady_clock;
 using lksrv::Arena;
@@ -50,19 +65,28 @@ struct Posted {
 
 extern "C" int lks_run(lk_ctx *c, const lks_config *cfg, const lks_request *reqs, uint64_t count, lks_outcome *out,
                        lks_stats *stats) {
-  if (!c || !cfg || (!reqs && count) || (!out && count)) return LK_EINVAL;
+  if (!c || !cfg || (!reqs && count) || (!out && count)) return sfail(LK_EINVAL, "lks_run: NULL argument");
   lk_info info;
-  if (lk_get_info(c, &info) != LK_OK || info.state != 0) return LK_ESTATE;
-  if (info.n_clusters != info.n_workers) return LK_EINVAL;  // needs one cluster per worker
+  if (lk_get_info(c, &info) != LK_OK || info.state != 0) return sfail(LK_ESTATE, "lks_run: context is not running");
+  if (info.n_clusters != info.n_workers)
+    return sfail(LK_EINVAL, "lks_run: needs one cluster per worker (%u clusters, %u workers)", info.n_clusters,
+                 info.n_workers);
   const uint32_t T = cfg->threads;
-  if (T == 0 || T > 64 || T > info.n_workers) return LK_EINVAL;
-  if (cfg->tile_elems == 0 || cfg->tile_elems % 256 || cfg->tile_elems > (1ull << 31)) return LK_EINVAL;
-  if ((cfg->arena & (kGranule - 1)) || (cfg->arena_bytes && !cfg->arena)) return LK_EINVAL;
+  if (T == 0 || T > 64 || T > info.n_workers)
+    return sfail(LK_EINVAL, "lks_run: %u scheduler threads: need 1..64 and at most the %u workers", T, info.n_workers);
+  if (cfg->tile_elems == 0 || cfg->tile_elems % 256 || cfg->tile_elems > (1ull << 31))
+    return sfail(LK_EINVAL, "lks_run: tile_elems must be a positive multiple of 256 up to 2^31");
+  if ((cfg->arena & (kGranule - 1)) || (cfg->arena_bytes && !cfg->arena))
+    return sfail(LK_EINVAL, "lks_run: arena must be non-NULL and %llu-byte aligned",
+                 static_cast<unsigned long long>(kGranule));
   for (uint64_t i = 0; i < count; ++i) {
     const lks_request &r = reqs[i];
     if (!op_allowed(r.op) || ((r.in | r.in2) & 3u) || (r.n && !r.in) || (r.op == LK_OP_AXPY_F32 && r.n && !r.in2))
-      return LK_EINVAL;
-    if (i && r.arrival_us < reqs[i - 1].arrival_us) return LK_EINVAL;
+      return sfail(LK_EINVAL, "lks_run: request %llu: op %u not served or pointer NULL or not 4-byte aligned",
+                   static_cast<unsigned long long>(i), r.op);
+    if (i && r.arrival_us < reqs[i - 1].arrival_us)
+      return sfail(LK_EINVAL, "lks_run: request %llu arrives before the one preceding it",
+                   static_cast<unsigned long long>(i));
     out[i] = lks_outcome{0, 0, -1.0, -1.0, LK_OK, 0};
   }
   const uint64_t slice = cfg->arena_bytes / T / kGranule * kGranule;

@@ -443,10 +443,13 @@ class Context:
         return self._h
 
     # -- serving (lk_serve.h) ---------------------------------------------------------------
-    def serve(self, requests, arena, arena_bytes, tile_elems=65536, threads=4, retain=False, timeout=10.0):
+    def serve(self, requests, arena, arena_bytes, tile_elems=65536, threads=None, retain=False, timeout=10.0):
         """Run a request trace (REQUEST_DTYPE, sorted by arrival) with continuous batching;
-        arena = device buffer (tensor or address) of arena_bytes for request outputs.
+        arena = device buffer (tensor or address) of arena_bytes for request outputs;
+        threads = scheduler threads (default 4, or one per worker when there are fewer).
         Returns (OUTCOME_DTYPE array, stats dict)."""
+        if threads is None:
+            threads = min(4, self.info()["n_workers"])
         requests = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE).ravel()
         cfg = ServeConfig(_ptr(arena), int(arena_bytes), int(tile_elems), int(threads), 1 if retain else 0,
                           int(timeout * 1e9))

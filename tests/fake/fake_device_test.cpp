@@ -466,6 +466,21 @@ static void serving() {
   cfg.timeout_ns = 5000000000ll;
   std::vector<lks_outcome> out(count);
   lks_stats st;
+  // Rejected configurations and traces name their reason in lk_last_error.
+  {
+    lks_config bad = cfg;
+    bad.threads = 9;  // more schedulers than the 8 workers
+    CHECK(lks_run(c, &bad, req.data(), count, out.data(), &st) == LK_EINVAL);
+    CHECK(strstr(lk_last_error(), "scheduler threads") != nullptr);
+    bad = cfg;
+    bad.tile_elems = 1000;
+    CHECK(lks_run(c, &bad, req.data(), count, out.data(), &st) == LK_EINVAL);
+    CHECK(strstr(lk_last_error(), "tile_elems") != nullptr);
+    std::vector<lks_request> late(req.begin(), req.begin() + 3);
+    late[2].arrival_us = late[1].arrival_us - 1.0;
+    CHECK(lks_run(c, &cfg, late.data(), 3, out.data(), &st) == LK_EINVAL);
+    CHECK(strstr(lk_last_error(), "request 2 arrives before") != nullptr);
+  }
   CHECK(lks_run(c, &cfg, req.data(), count, out.data(), &st) == LK_OK);
   uint64_t tiles = 0;
   for (uint32_t i = 0; i < count; ++i) {
