@@ -220,6 +220,8 @@ def parse():
     ap.add_argument("--burst-reps", type=int, default=5, help="batching: timed repetitions per burst")
     ap.add_argument("--batch-threads", type=str, default="256,1024",
                     help="batching: worker sizes (threads per worker) the autotuner chooses from")
+    ap.add_argument("--batch-spans", type=str, default="all,xcd",
+                    help="batching: spans the autotuner chooses from (all: every CU, xcd: one XCD's workers)")
     ap.add_argument("--spin-iters", type=int, default=20000, help="replay: loop iterations of the item")
     ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
     ap.add_argument("--period-us", type=float, default=1000.0)
@@ -260,9 +262,10 @@ PAPER_CYCLES = {
 
 def bench_batching(args):
     """Bursts of uneven items (int32 affine / fp32 SAXPY 50/50, log-uniform 256 .. 2^20
-    elements) as one persistent batch over all CUs, with the tile size and polling
-    interval picked per burst size by the autotuner on training bursts (seed 50), against
-    the same bursts as per-item launches and as a captured hipGraph."""
+    elements) as one persistent batch, with the tile size, the polling interval, the worker
+    size and the span (every CU or one XCD's workers) picked per burst size by the
+    autotuner on training bursts (seed 50), against the same bursts as per-item launches
+    and as a captured hipGraph."""
     import torch
     from paper_2310_01212_amd import autotune, lk, workloads
 
@@ -308,34 +311,39 @@ def bench_batching(args):
 
     ctxs = {}
 
-    def ctx_for(sleep, threads):
-        # one context at a time: each holds every CU until it is closed
-        if (sleep, threads) not in ctxs:
+    def ctx_for(cs):
+        # one context at a time: each holds every CU until it is closed.  A burst runs on
+        # cluster 0: every worker ("all") or XCD 0's workers ("xcd")
+        if cs not in ctxs:
             for old in list(ctxs):
                 ctxs.pop(old).close()
-            ctxs[(sleep, threads)] = lk.Context(n_workers=0, clusters=lk.CLUSTERS_ONE, poll_sleep=sleep,
-                                                threads=threads, idle_timeout_ms=120000)
-        return ctxs[(sleep, threads)]
+            sleep, threads, span = cs
+            policy = lk.CLUSTERS_ONE if span == "all" else lk.CLUSTERS_PER_XCD
+            ctxs[cs] = lk.Context(n_workers=0, clusters=policy, poll_sleep=sleep, threads=threads,
+                                  idle_timeout_ms=120000)
+        return ctxs[cs]
 
-    def run_burst(size, tile, sleep, threads, r):
+    def run_burst(size, tile, cs, r):
         d, nt, part = staged_tiles((size, 50), tile)
-        ctx = ctx_for(sleep, threads)
+        ctx = ctx_for(cs)
         ctx.run_batch(0, d, nt, part, reps=1)  # warm-up
         return ctx.run_batch(0, d, nt, part, reps=r)
 
     log("batching: autotuning on training bursts (seed 50)")
     worker_sizes = tuple(int(v) for v in args.batch_threads.split(","))
-    table = autotune.tune(run_burst, sizes, threads=worker_sizes, reps=reps)
+    spans = tuple(args.batch_spans.split(","))
+    table = autotune.tune(run_burst, sizes, ctx_settings=autotune.contexts(threads=worker_sizes, spans=spans),
+                          reps=reps)
     out = {"metric": "burst makespan (µs), items/s and achieved GB/s: one persistent batch vs per-item "
                      "launches vs captured hipGraph",
            "unit": "items/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int32 / f32",
            "data": "synthetic (seeded: bursts seed 5, tuning seed 50)", "steps": reps, "warmup": 1,
            "scaling": "weak", "vs_baseline": None,
            "config": {"workload": "bursts of uneven items, log-uniform 256..2^20 elements, int32 affine and "
-                                  "fp32 SAXPY 50/50, one persistent batch over all CUs", "bursts": sizes,
-                      "worker_sizes_tuned": list(worker_sizes)},
-           "tuning": {str(k): {"tile": v["tile"], "poll_sleep": v["poll_sleep"], "threads": v["threads"]}
-                      for k, v in table.items()},
+                                  "fp32 SAXPY 50/50, one persistent batch per burst", "bursts": sizes,
+                      "worker_sizes_tuned": list(worker_sizes), "spans_tuned": list(spans)},
+           "tuning": {str(k): {"tile": v["tile"], "poll_sleep": v["poll_sleep"], "threads": v["threads"],
+                               "span": v["span"]} for k, v in table.items()},
            "bursts": {}}
     # The persistent bursts first, then every context closed, then the per-launch and graph
     # baselines on a GPU with no persistent workers resident (workers of 1024 threads fill
@@ -344,7 +352,7 @@ def bench_batching(args):
     for size in sizes:
         tune_row = table[size]
         d, nt, part = staged_tiles((size, 5), tune_row["tile"])
-        ctx = ctx_for(tune_row["poll_sleep"], tune_row["threads"])
+        ctx = ctx_for((tune_row["poll_sleep"], tune_row["threads"], tune_row["span"]))
         ctx.run_batch(0, d, nt, part, reps=1)
         ms_of[size] = (ctx.run_batch(0, d, nt, part, reps=reps), nt)
     for old in list(ctxs):

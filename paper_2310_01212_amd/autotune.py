@@ -1,13 +1,15 @@
 """Autotuner of the batched persistent dispatch: per burst size, the tile size (elements
-per claimed tile), the workers' polling interval and the workers' size (threads per
-workgroup) that minimise the median makespan.
+per claimed tile) and the context the burst runs on -- the workers' polling interval,
+their size (threads per workgroup) and how many CUs the burst spreads over (every CU, or
+one XCD's) -- that minimise the median makespan.
 
 Tuning runs on training bursts (their own seed) and the chosen table is then used on the
 evaluation bursts.  Larger tiles cost fewer counter claims and less per-tile overhead;
-smaller tiles balance uneven items better over the 256 workers; the polling interval
-trades PCIe read traffic of idle workers against pickup latency; larger workers keep more
-loads in flight per CU (long bursts) but take longer over the reductions and barriers of
-short tiles.
+smaller tiles balance uneven items better over the workers; the polling interval trades
+PCIe read traffic of idle workers against pickup latency; larger workers keep more loads
+in flight per CU (long bursts) but take longer over the reductions and barriers of short
+tiles; one XCD's 32 workers take a short burst with an eighth of the command posts and
+tile claims that stay within one L2, while long bursts need every CU.
 """
 import json
 import os
@@ -17,37 +19,45 @@ import numpy as np
 TILE_CANDIDATES = (4096, 16384, 65536, 262144)
 SLEEP_CANDIDATES = (0, 8)
 THREAD_CANDIDATES = (256, 1024)
+SPAN_CANDIDATES = ("all", "xcd")
+
+
+def contexts(sleeps=SLEEP_CANDIDATES, threads=THREAD_CANDIDATES, spans=SPAN_CANDIDATES):
+    """Every context setting (poll_sleep, threads, span) of the candidates."""
+    return tuple((s, t, sp) for sp in spans for t in threads for s in sleeps)
 
 
 def pick_best(timings):
-    """timings: {(tile, sleep, threads): [makespan_us, ...]} -> the key with the smallest
-    median; ties go to the larger tile, then to the longer polling interval, then to the
-    smaller worker (which leaves more of its CU to other kernels)."""
+    """timings: {(tile, (poll_sleep, threads, span)): [makespan_us, ...]} -> the key with
+    the smallest median; ties go to the larger tile, then to the longer polling interval,
+    then to the smaller worker (which leaves more of its CU to other kernels), then to the
+    wider span."""
     best = None
-    for (tile, sleep, threads), v in timings.items():
-        key = (float(np.median(v)), -tile, -sleep, threads)
+    for (tile, (sleep, threads, span)), v in timings.items():
+        key = (float(np.median(v)), -tile, -sleep, threads, SPAN_CANDIDATES.index(span))
         if best is None or key < best[0]:
-            best = (key, (tile, sleep, threads))
+            best = (key, (tile, (sleep, threads, span)))
     return best[1]
 
 
-def tune(run_burst, sizes, tiles=TILE_CANDIDATES, sleeps=SLEEP_CANDIDATES, threads=THREAD_CANDIDATES, reps=5):
-    """run_burst(size, tile, sleep, threads, reps) -> list of makespans (us) of a training
-    burst.  The polling interval and the worker size are properties of a running context,
-    so they are the outer loops (one context per pair).  Returns {size: {"tile": t,
-    "poll_sleep": s, "threads": w, "median_us": m, "grid": {...}}}."""
+def tune(run_burst, sizes, tiles=TILE_CANDIDATES, ctx_settings=None, reps=5):
+    """run_burst(size, tile, (poll_sleep, threads, span), reps) -> list of makespans (us) of a
+    training burst.  A context setting belongs to a running context, so it is the outer
+    loop (one context per setting).  Returns {size: {"tile", "poll_sleep", "threads",
+    "span", "median_us", "grid"}}."""
+    ctx_settings = contexts() if ctx_settings is None else tuple(ctx_settings)
     timings = {size: {} for size in sizes}
-    for thr in threads:
-        for sleep in sleeps:
-            for size in sizes:
-                for tile in tiles:
-                    timings[size][(tile, sleep, thr)] = list(run_burst(size, tile, sleep, thr, reps))
+    for cs in ctx_settings:
+        for size in sizes:
+            for tile in tiles:
+                timings[size][(tile, cs)] = list(run_burst(size, tile, cs, reps))
     table = {}
     for size in sizes:
-        tile, sleep, thr = pick_best(timings[size])
-        table[int(size)] = {"tile": int(tile), "poll_sleep": int(sleep), "threads": int(thr),
-                            "median_us": float(np.median(timings[size][(tile, sleep, thr)])),
-                            "grid": {f"{t}/{s}/{w}": float(np.median(v)) for (t, s, w), v in timings[size].items()}}
+        tile, (sleep, thr, span) = pick_best(timings[size])
+        table[int(size)] = {"tile": int(tile), "poll_sleep": int(sleep), "threads": int(thr), "span": span,
+                            "median_us": float(np.median(timings[size][(tile, (sleep, thr, span))])),
+                            "grid": {f"{t}/{s}/{w}/{sp}": float(np.median(v))
+                                     for (t, (s, w, sp)), v in timings[size].items()}}
     return table
 
 
@@ -62,5 +72,5 @@ def load(path, device_name):
     d = json.load(open(path))
     if d.get("device") != device_name:
         return None
-    # tables written before the worker size was tuned hold 256-thread workers
-    return {int(k): {"threads": 256, **v} for k, v in d["table"].items()}
+    # tables written before the worker size and span were tuned: 256-thread workers on every CU
+    return {int(k): {"threads": 256, "span": "all", **v} for k, v in d["table"].items()}

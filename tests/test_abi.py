@@ -382,29 +382,37 @@ def test_batch_plan_cuts_items_into_tiles():
 
 def test_autotuner_picks_the_fastest_median_with_stable_ties(tmp_path):
     from paper_2310_01212_amd import autotune
-    t = {(4096, 0, 256): [10, 11, 50], (16384, 0, 256): [9, 12, 12], (65536, 8, 256): [11, 11, 11],
-         (65536, 0, 256): [30, 30, 30], (65536, 8, 1024): [11, 12, 12]}
-    assert autotune.pick_best(t) == (65536, 8, 256)   # medians 11 tie; larger tile wins
-    t2 = {(4096, 0, 256): [5.0], (16384, 0, 256): [5.0], (16384, 8, 256): [5.0], (16384, 8, 1024): [5.0]}
-    assert autotune.pick_best(t2) == (16384, 8, 256)   # tie: larger tile, longer sleep, smaller worker
-    assert autotune.pick_best({(4096, 0, 256): [6.0], (4096, 0, 1024): [5.0]}) == (4096, 0, 1024)
+    A0, A8, B8, X0 = (0, 256, "all"), (8, 256, "all"), (8, 1024, "all"), (0, 256, "xcd")
+    t = {(4096, A0): [10, 11, 50], (16384, A0): [9, 12, 12], (65536, A8): [11, 11, 11],
+         (65536, A0): [30, 30, 30], (65536, B8): [11, 12, 12]}
+    assert autotune.pick_best(t) == (65536, A8)   # medians 11 tie; larger tile wins
+    t2 = {(4096, A0): [5.0], (16384, A0): [5.0], (16384, A8): [5.0], (16384, B8): [5.0], (16384, (8, 256, "xcd")): [5.0]}
+    assert autotune.pick_best(t2) == (16384, A8)   # tie: larger tile, longer sleep, smaller worker, wider span
+    assert autotune.pick_best({(4096, A0): [6.0], (4096, X0): [5.0]}) == (4096, X0)
+    assert len(autotune.contexts()) == 8 and autotune.contexts()[0] == (0, 256, "all")
     calls = []
 
-    def fake(size, tile, sleep, threads, reps):
-        calls.append((size, tile, sleep, threads))
-        return [abs(tile - 16384 * size) / 1e3 + sleep + 1 + (0.5 if (threads == 1024) == (size == 1) else 0)] * reps
-    table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), sleeps=(0, 8), threads=(256, 1024), reps=2)
-    assert (table[1]["tile"], table[1]["poll_sleep"], table[1]["threads"]) == (16384, 0, 256)
-    assert (table[4]["tile"], table[4]["threads"]) == (65536, 1024) and len(calls) == 24
-    # one context per (threads, sleep) pair: the outer loops change least often
-    assert [c[3] for c in calls] == [256] * 12 + [1024] * 12
-    # a saved table reloads for the same device only; older tables default to 256 threads
+    def fake(size, tile, cs, reps):
+        sleep, threads, span = cs
+        calls.append((size, tile, cs))
+        cost = abs(tile - 16384 * size) / 1e3 + sleep + 1
+        cost += 0.5 if (threads == 1024) == (size == 1) else 0      # 1024 threads for size 4
+        cost += 0.25 if (span == "xcd") != (size == 1) else 0       # one XCD for size 1
+        return [cost] * reps
+    table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), reps=2)
+    assert (table[1]["tile"], table[1]["poll_sleep"], table[1]["threads"], table[1]["span"]) == (16384, 0, 256, "xcd")
+    assert (table[4]["tile"], table[4]["threads"], table[4]["span"]) == (65536, 1024, "all")
+    assert len(calls) == 2 * 3 * 8
+    # one context per setting: the outer loop changes least often
+    settings = [c[2] for c in calls]
+    assert all(settings[i] == settings[i // 6 * 6] for i in range(len(settings)))
+    # a saved table reloads for the same device only; older tables: 256 threads, every CU
     path = str(tmp_path / "t.json")
     autotune.save(table, path, "gfx950")
     assert autotune.load(path, "other") is None
-    assert autotune.load(path, "gfx950")[4]["threads"] == 1024
+    assert autotune.load(path, "gfx950")[1]["span"] == "xcd" and autotune.load(path, "gfx950")[4]["threads"] == 1024
     json.dump({"device": "gfx950", "table": {"1": {"tile": 4096, "poll_sleep": 0}}}, open(path, "w"))
-    assert autotune.load(path, "gfx950")[1] == {"threads": 256, "tile": 4096, "poll_sleep": 0}
+    assert autotune.load(path, "gfx950")[1] == {"threads": 256, "span": "all", "tile": 4096, "poll_sleep": 0}
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
