@@ -315,12 +315,16 @@ def test_bench_roofline_arithmetic():
     assert r["traffic"] == 123 and r["kernel"] == "k" and r["frac_of_copy_probe"] == round(8000 / 6000, 4)
     assert r["kernel_ms"] == 1.0
     assert "copy_probe_gbps" not in bench.hbm_roofline(1e9, 1.0)
-    # the committed kernel trace of the benchmark command: 6,400,000 items of 196,608 bytes
-    # in the 165.553 ms headline dispatch
+    # the committed kernel trace of the benchmark command: the byte rate it states for the
+    # headline dispatch follows from its 6,400,000 items of 196,608 bytes and the traced
+    # duration, and that duration agrees with the same run's kernel_ms (device clock)
     text = open(os.path.join(ROOT, "profiles", "lk_worker_allcu_saxpy_kernel_trace.md")).read()
     m = re.search(r"took \*\*([0-9.]+) ms\*\* in the trace", text)
-    assert m
-    assert abs(bench.gb_per_s(6_400_000 * 196_608, float(m.group(1))) / 1000 - 7.60) < 0.01
+    rate = re.search(r"algorithmic bytes over ([0-9.]+) ms = ([0-9.]+) TB/s", text)
+    kms = re.search(r"`kernel_ms` = ([0-9.]+) ms", text)
+    assert m and rate and kms and float(rate.group(1)) == float(m.group(1))
+    assert abs(bench.gb_per_s(6_400_000 * 196_608, float(m.group(1))) / 1000 - float(rate.group(2))) < 0.006
+    assert abs(float(kms.group(1)) / float(m.group(1)) - 1) < 0.01
 
 
 def test_bench_percentiles_are_nearest_rank():
