@@ -800,6 +800,41 @@ def test_completion_implies_visibility_on_an_independent_stream():
             del z
 
 
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_torch_work_progresses_beside_workers_on_every_cu(threads):
+    """Torch kernels on a stream of their own run while a worker sits on every CU, also
+    with the benchmark's 1024-thread workers (four worker waves per SIMD, 416 of its 512
+    VGPRs held): elementwise work and a reduction finish within seconds, and afterwards
+    every worker still serves items (none left on its idle watchdog meanwhile)."""
+    say(f"coexistence: torch ops on a side stream beside 256 workers of {threads} threads")
+    n = 1 << 20
+    x = torch.randn(n, device="cuda")
+    want = float((x.double() * 3 + 1).sum())
+    y = torch.zeros(256, 1024, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with lk.Context(n_workers=0, threads=threads, idle_timeout_ms=6000) as ctx:
+        nw = ctx.info()["n_workers"]
+        for w in range(nw):
+            ctx.wait(w, ctx.submit(w, lk.OP_SAXPY_F32, x=x[:1024], y=y[w], alpha=1.0))
+        t0 = time.time()
+        with torch.cuda.stream(side):
+            z = float((x.double() * 3 + 1).sum())
+            side.synchronize()
+        dt = time.time() - t0
+        assert dt < 2.0, f"torch work on a side stream took {dt:.2f} s beside the workers"
+        assert abs(z - want) <= 1e-9 * max(1.0, abs(want))
+        for w in range(nw):
+            ctx.wait(w, ctx.submit(w, lk.OP_SAXPY_F32, x=x[:1024], y=y[w], alpha=1.0))
+    got = y.cpu().numpy()
+    xs = x[:1024].cpu().numpy()
+    want_y = np.zeros(1024, np.float32)
+    for _ in range(2):
+        oracle.saxpy_f32(np.float32(1.0), xs.copy(), want_y)
+    for w in range(nw):
+        assert same_f32(got[w], want_y), w
+
+
 # ------------------------------------------------------------------ error paths
 def test_ring_full_timeout_and_disposed_state():
     say("errors: EAGAIN at depth 1, ETIMEDOUT on a long SPIN item, ESTATE after close")
