@@ -246,9 +246,12 @@ def test_all_cus_small_fifo_chains_bit_exact():
         oracle.run_fifo([dict(op=oracle.SAXPY_F32, inp=X[w, :nl(w)].copy(), out=yr, alpha=a) for a in A[w]])
         assert np.array_equal(Y[w, :nl(w)].view(np.uint32), yr.view(np.uint32)), w
         check_log(ctx.log(w), 60, lk.CODE_WORK + lk.OP_SAXPY_F32)
-    # workers are in physical order and each sits on its own CU
+    # workers are in physical order and each sits on its own CU, every XCD holding the same
+    # number of them (32 on each of the 8 XCDs of an MI355X)
     topo = [ctx.topology(w) for w in range(lanes)]
     assert topo == sorted(topo) and len(set(topo)) == lanes
+    per_xcd = np.unique(np.array([t[0] for t in topo]), return_counts=True)[1]
+    assert np.all(per_xcd == lanes // per_xcd.size), per_xcd
 
 
 def test_rotating_buffer_pairs_chains_bit_exact():
