@@ -332,6 +332,8 @@ def bench_batching(args):
     log("batching: autotuning on training bursts (seed 50)")
     worker_sizes = tuple(int(v) for v in args.batch_threads.split(","))
     spans = tuple(args.batch_spans.split(","))
+    if not spans or not set(spans) <= set(autotune.SPAN_CANDIDATES):
+        sys.exit(f"--batch-spans: give spans from {autotune.SPAN_CANDIDATES}, not {args.batch_spans!r}")
     table = autotune.tune(run_burst, sizes, ctx_settings=autotune.contexts(threads=worker_sizes, spans=spans),
                           reps=reps)
     out = {"metric": "burst makespan (µs), items/s and achieved GB/s: one persistent batch vs per-item "
