@@ -889,8 +889,9 @@ def bench_allcu(args):
         # pinned-input variants: x kept in each worker's LDS across items (descriptor flag
         # DF_PIN_INPUT).  "hot" is the headline workload with the flag; "y_cold" keeps x per
         # mailbox and rotates y through P buffers (512 MiB at P = 32, past the Infinity Cache),
-        # run without and with the flag.  Bandwidths are algorithmic (12n bytes per item),
-        # as for the headline
+        # run without and with the flag.  Their byte rates are given both ways: algorithmic
+        # (12n bytes per item) and HBM (8n: y read and written through; x stays in the XCD's
+        # L2, or in LDS when pinned)
         if args.pinned and not args.pin_input:
             def timed(ctx_kw, items_of_step, nsteps, depth=1):
                 return session([items_of_step(s) for s in range(nsteps)], depth=depth, **ctx_kw)
@@ -927,13 +928,15 @@ def bench_allcu(args):
             for fl, key in ((0, "y_cold_unpinned"), (lk.DF_PIN_INPUT, "y_cold_pinned")):
                 yl, yt, yinf = timed({}, lambda s, fl=fl: ycit[fl][s], psteps)
                 y_items = lanes * per * psteps
-                gbps = y_items * bytes_per_item / (yinf["device_span_ms"] * 1e-3) / 1e9
+                gbps = gb_per_s(y_items * bytes_per_item, yinf["device_span_ms"])
+                hbm_gbps = gb_per_s(y_items * 8 * n, yinf["device_span_ms"])
                 pv[key] = {"y_buffers_per_mailbox": P, "y_footprint_bytes": lanes * P * n * 4,
                            "items_per_s": round(yl.size / yt, 1), "latency_us": lat_summary(yl),
                            "kernel_ms": round(yinf["device_span_ms"], 3), "items_per_launch": y_items,
-                           "algorithmic_bytes_per_item": bytes_per_item, "achieved_gbps": round(gbps, 1),
-                           "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
-                log(f"{key}: {yl.size / yt:,.0f} items/s, {gbps:,.0f} GB/s")
+                           "algorithmic_bytes_per_item": bytes_per_item, "algorithmic_gbps": round(gbps, 1),
+                           "hbm_bytes_per_item": 8 * n, "hbm_gbps": round(hbm_gbps, 1),
+                           "hbm_frac_of_peak": round(hbm_gbps / HBM_PEAK_GBPS, 4)}
+                log(f"{key}: {yl.size / yt:,.0f} items/s, {hbm_gbps:,.0f} GB/s of y from HBM")
             del ycold
             result["pinned_variant"] = pv
 
