@@ -220,8 +220,9 @@ def parse():
     ap.add_argument("--burst-reps", type=int, default=5, help="batching: timed repetitions per burst")
     ap.add_argument("--batch-threads", type=str, default="256,1024",
                     help="batching: worker sizes (threads per worker) the autotuner chooses from")
-    ap.add_argument("--batch-spans", type=str, default="all,xcd",
-                    help="batching: spans the autotuner chooses from (all: every CU, xcd: one XCD's workers)")
+    ap.add_argument("--batch-spans", type=str, default="all,half,xcd",
+                    help="batching: spans the autotuner chooses from (all: every CU, half: four XCDs' workers, "
+                         "xcd: one XCD's workers)")
     ap.add_argument("--spin-iters", type=int, default=20000, help="replay: loop iterations of the item")
     ap.add_argument("--periods", type=int, default=10000, help="isolation: periods per variant")
     ap.add_argument("--period-us", type=float, default=1000.0)
@@ -263,7 +264,7 @@ PAPER_CYCLES = {
 def bench_batching(args):
     """Bursts of uneven items (int32 affine / fp32 SAXPY 50/50, log-uniform 256 .. 2^20
     elements) as one persistent batch, with the tile size, the polling interval, the worker
-    size and the span (every CU or one XCD's workers) picked per burst size by the
+    size and the span (every CU, four XCDs' or one XCD's workers) picked per burst size by the
     autotuner on training bursts (seed 50), against the same bursts as per-item launches
     and as a captured hipGraph."""
     import torch
@@ -311,16 +312,25 @@ def bench_batching(args):
 
     ctxs = {}
 
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+
     def ctx_for(cs):
         # one context at a time: each holds every CU until it is closed.  A burst runs on
-        # cluster 0: every worker ("all") or XCD 0's workers ("xcd")
+        # cluster 0: every worker ("all"), the first half of the physically ordered workers
+        # ("half": XCDs 0-3) or XCD 0's workers ("xcd")
         if cs not in ctxs:
             for old in list(ctxs):
                 ctxs.pop(old).close()
             sleep, threads, span = cs
-            policy = lk.CLUSTERS_ONE if span == "all" else lk.CLUSTERS_PER_XCD
-            ctxs[cs] = lk.Context(n_workers=0, clusters=policy, poll_sleep=sleep, threads=threads,
-                                  idle_timeout_ms=120000)
+            kw = dict(poll_sleep=sleep, threads=threads, idle_timeout_ms=120000)
+            if span == "all":
+                kw.update(n_workers=0, clusters=lk.CLUSTERS_ONE)
+            elif span == "half":
+                kw.update(n_workers=n_cu, clusters=lk.CLUSTERS_EXPLICIT,
+                          cluster_of_worker=(np.arange(n_cu) >= n_cu // 2).astype(np.uint32))
+            else:
+                kw.update(n_workers=0, clusters=lk.CLUSTERS_PER_XCD)
+            ctxs[cs] = lk.Context(**kw)
         return ctxs[cs]
 
     def run_burst(size, tile, cs, r):

@@ -1,15 +1,15 @@
 """Autotuner of the batched persistent dispatch: per burst size, the tile size (elements
 per claimed tile) and the context the burst runs on -- the workers' polling interval,
-their size (threads per workgroup) and how many CUs the burst spreads over (every CU, or
-one XCD's) -- that minimise the median makespan.
+their size (threads per workgroup) and how many CUs the burst spreads over (every CU,
+half of them (four XCDs), or one XCD's) -- that minimise the median makespan.
 
 Tuning runs on training bursts (their own seed) and the chosen table is then used on the
 evaluation bursts.  Larger tiles cost fewer counter claims and less per-tile overhead;
 smaller tiles balance uneven items better over the workers; the polling interval trades
 PCIe read traffic of idle workers against pickup latency; larger workers keep more loads
 in flight per CU (long bursts) but take longer over the reductions and barriers of short
-tiles; one XCD's 32 workers take a short burst with an eighth of the command posts and
-tile claims that stay within one L2, while long bursts need every CU.
+tiles; fewer workers take a short burst with fewer command posts (one XCD's 32 workers
+also keep the tile claims within one L2), while long bursts need every CU.
 """
 import json
 import os
@@ -19,7 +19,7 @@ import numpy as np
 TILE_CANDIDATES = (4096, 16384, 65536, 262144)
 SLEEP_CANDIDATES = (0, 8)
 THREAD_CANDIDATES = (256, 1024)
-SPAN_CANDIDATES = ("all", "xcd")
+SPAN_CANDIDATES = ("all", "half", "xcd")
 
 
 def contexts(sleeps=SLEEP_CANDIDATES, threads=THREAD_CANDIDATES, spans=SPAN_CANDIDATES):

@@ -393,7 +393,8 @@ def test_autotuner_picks_the_fastest_median_with_stable_ties(tmp_path):
     t2 = {(4096, A0): [5.0], (16384, A0): [5.0], (16384, A8): [5.0], (16384, B8): [5.0], (16384, (8, 256, "xcd")): [5.0]}
     assert autotune.pick_best(t2) == (16384, A8)   # tie: larger tile, longer sleep, smaller worker, wider span
     assert autotune.pick_best({(4096, A0): [6.0], (4096, X0): [5.0]}) == (4096, X0)
-    assert len(autotune.contexts()) == 8 and autotune.contexts()[0] == (0, 256, "all")
+    assert len(autotune.contexts()) == 12 and autotune.contexts()[0] == (0, 256, "all")
+    assert autotune.pick_best({(4096, X0): [5.0], (4096, (0, 256, "half")): [5.0]})[1][2] == "half"
     calls = []
 
     def fake(size, tile, cs, reps):
@@ -406,7 +407,7 @@ def test_autotuner_picks_the_fastest_median_with_stable_ties(tmp_path):
     table = autotune.tune(fake, [1, 4], tiles=(4096, 16384, 65536), reps=2)
     assert (table[1]["tile"], table[1]["poll_sleep"], table[1]["threads"], table[1]["span"]) == (16384, 0, 256, "xcd")
     assert (table[4]["tile"], table[4]["threads"], table[4]["span"]) == (65536, 1024, "all")
-    assert len(calls) == 2 * 3 * 8
+    assert len(calls) == 2 * 3 * 12
     # one context per setting: the outer loop changes least often
     settings = [c[2] for c in calls]
     assert all(settings[i] == settings[i // 6 * 6] for i in range(len(settings)))
