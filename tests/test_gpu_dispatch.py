@@ -1134,8 +1134,12 @@ def _burst(count, seed, log2_range=(8, 16)):
 
 def test_batches_of_uneven_items_bit_exact_over_all_cus_and_one_xcd():
     ops, n, ab, alpha, off, xi, xf, yf = _burst(64, 11)
-    say(f"batch: 64 uneven items ({int(n.sum())} elements), tiles of 4096, cluster ONE and XCD 0, 3 reps")
-    for policy, cluster in ((lk.CLUSTERS_ONE, 0), (lk.CLUSTERS_PER_XCD, 0)):
+    say(f"batch: 64 uneven items ({int(n.sum())} elements), tiles of 4096, cluster ONE, XCD 0 and "
+        "the first half of the workers, 3 reps")
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    half = (np.arange(n_cu) >= n_cu // 2).astype(np.uint32)
+    for policy, cluster in ((lk.CLUSTERS_ONE, 0), (lk.CLUSTERS_PER_XCD, 0), (lk.CLUSTERS_EXPLICIT, 0),
+                            (lk.CLUSTERS_EXPLICIT, 1)):
         d_xi, d_xf, d_yf = to_dev(xi), to_dev(xf), to_dev(yf.copy())
         d_z = sentinel_i32(xi.shape)
         ins = np.where(ops == lk.OP_AFFINE_SUM_I32, addr(d_xi), addr(d_xf)) + off[:-1].astype(np.uint64) * 4
@@ -1145,7 +1149,10 @@ def test_batches_of_uneven_items_bit_exact_over_all_cus_and_one_xcd():
         d_tiles = torch.from_numpy(tiles.view(np.uint8)).to("cuda")
         partials = torch.zeros(tiles.size, dtype=torch.int64, device="cuda")
         torch.cuda.synchronize()
-        with lk.Context(n_workers=0, clusters=policy, idle_timeout_ms=20000) as ctx:
+        kw = dict(n_workers=n_cu, cluster_of_worker=half) if policy == lk.CLUSTERS_EXPLICIT else dict(n_workers=0)
+        with lk.Context(clusters=policy, idle_timeout_ms=20000, **kw) as ctx:
+            if policy == lk.CLUSTERS_EXPLICIT:
+                assert sorted(ctx.members(cluster)) == list(range(cluster * n_cu // 2, (cluster + 1) * n_cu // 2))
             ms = ctx.run_batch(cluster, d_tiles, tiles.size, partials, reps=3)
         assert ms.size == 3 and np.all(ms > 0)
         P = partials.cpu().numpy()
